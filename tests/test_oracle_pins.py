@@ -1,0 +1,357 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: every check is a closed form,
+an invariant, a stated property of the paper (arXiv:1106.4198) or a brute
+force on a tiny input.  Each is chosen so that a plausible slip (a dropped
+eps, a wrong exponent, a transposed operand, a missing W^2, rho on the wrong
+term) fails at least one of them.
+"""
+import math
+import os
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1106_4198_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_problem(F, K, N, seed, eps_floor=1e-3):
+    rng = np.random.default_rng(seed)
+    W = np.asfortranarray(rng.uniform(0.2, 1.5, size=(F, K)))
+    H = np.asfortranarray(rng.gamma(0.7, 1.0, size=(K, N)) + eps_floor)
+    V = np.asfortranarray((W @ H) * rng.exponential(1.0, size=(F, N)) + eps_floor)
+    return V, W, H
+
+
+def _relerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ---------------------------------------------------------------- d_IS (section 2.1)
+
+def test_dis_golden_values():
+    """d(2,1) = 1 - ln2, d(1,2) = ln2 - 1/2, d(v,v) = 0 (definition, section 2.1)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "dis_values.txt")) if l.strip() and not l.startswith("#")]
+    assert len(rows) >= 4
+    for y, x, d in rows:
+        got = oracle.dis_term(float(y), float(x))
+        assert abs(got - float(d)) <= 2e-16, (y, x, got, d)
+
+
+def test_dis_zero_on_diagonal_and_nonnegative():
+    rng = np.random.default_rng(0)
+    y = rng.lognormal(0, 3, size=20000)
+    for v in y[:2000]:
+        assert oracle.dis_term(v, v) == 0.0
+    x = rng.lognormal(0, 3, size=20000)
+    vals = np.array([oracle.dis_term(a, b) for a, b in zip(y, x)])
+    assert np.all(vals >= 0.0)
+    # strictly positive away from the diagonal
+    far = np.abs(np.log(y / x)) > 1e-3
+    assert np.all(vals[far] > 0.0)
+
+
+@pytest.mark.parametrize("delta", [1e-9, -1e-9, 3e-6, -3e-6, 1e-4, -1e-4, 9.9e-3, -9.9e-3,
+                                   0.0999, -0.0999, 0.1001, -0.1001, 0.3, -0.3, 5.0])
+def test_dis_against_high_precision(delta):
+    """u - 1 - ln u, with ln evaluated in 60-digit decimal arithmetic."""
+    getcontext().prec = 60
+    u = 1.0 + delta                      # exact double
+    ud = Decimal(u)
+    exact = float((ud - 1) - ud.ln())
+    got = oracle.dis_term(u, 1.0)
+    # within a few ulp of the terms that are subtracted (d and ln u)
+    tol = 4e-16 * exact + 2.3e-16 * (abs(delta) + abs(math.log1p(delta)))
+    assert abs(got - exact) <= tol, (got, exact)
+
+
+def test_dis_scale_invariance_eps0():
+    """d(l y, l x) = d(y, x) for eps = 0: exact for powers of two, within a few ulp otherwise."""
+    rng = np.random.default_rng(1)
+    y = rng.lognormal(0, 2, size=500)
+    x = rng.lognormal(0, 2, size=500)
+    base = oracle.dis(y, x)
+    for lam in [2.0 ** -20, 0.5, 8.0, 2.0 ** 30]:
+        assert oracle.dis(lam * y, lam * x) == base
+    for lam in [0.3, 7.7, 1234.5]:
+        assert abs(oracle.dis(lam * y, lam * x) - base) <= 1e-13 * base
+
+
+def test_dis_eps_shift():
+    """dis(y, x, eps) is d_IS(eps + y, eps + x) (section 2.3, small amplitudes)."""
+    y = np.array([0.0, 1e-14, 2.0])
+    x = np.array([1e-13, 0.0, 1.0])
+    eps = 1e-12
+    want = sum((eps + a) / (eps + b) - math.log((eps + a) / (eps + b)) - 1 for a, b in zip(y, x))
+    assert abs(oracle.dis(y, x, eps) - want) <= 1e-12 * want
+
+
+# ---------------------------------------------------------------- inner fit of h
+
+@pytest.mark.parametrize("iters", [0, 1, 2, 5, 10, 30])
+def test_fit_h_K1_closed_form(iters):
+    """K = 1, eps = 0: one update maps h -> sqrt(h m), m = mean_f(v_f / w_f),
+    so from h0 = 1, h_I = m^(1 - 2^-I)."""
+    rng = np.random.default_rng(2)
+    F = 37
+    w = rng.uniform(0.1, 2.0, size=(F, 1))
+    v = rng.gamma(0.5, 3.0, size=F) + 1e-3
+    m = float(np.mean(v / w[:, 0]))
+    h, fl = oracle.fit_h(v, w, iters=iters, eps=0.0)
+    assert fl == 0
+    want = m ** (1.0 - 2.0 ** (-iters))
+    assert abs(h[0] - want) <= 1e-13 * want
+
+
+def test_fit_h_monotone_descent():
+    """The inner updates are majorize-minimize steps: sum_f d(eps+v, eps+W h) never rises."""
+    V, W, _ = _rand_problem(40, 6, 3, seed=3)
+    eps = 1e-12
+    for n in range(3):
+        prev = np.inf
+        for it in range(0, 60):
+            h, _ = oracle.fit_h(V[:, n], W, iters=it, eps=eps)
+            obj = oracle.dis(V[:, n], W @ h, eps)
+            assert obj <= prev * (1 + 1e-13) + 1e-300
+            prev = obj
+
+
+def test_fit_h_converges_to_stationary_point():
+    """Large I: KKT conditions num_k = den_k wherever h_k stays positive."""
+    V, W, _ = _rand_problem(30, 3, 1, seed=4)
+    v = V[:, 0]
+    h, _ = oracle.fit_h(v, W, iters=4000, eps=0.0)
+    x = W @ h
+    num = W.T @ (v / x ** 2)
+    den = W.T @ (1.0 / x)
+    act = h > 1e-6 * h.max()
+    assert np.all(np.abs(num[act] / den[act] - 1.0) < 1e-9)
+    # and for inactive coordinates, the gradient points outward (num <= den)
+    assert np.all(num[~act] <= den[~act] * (1 + 1e-9))
+
+
+def test_fit_h_matches_bruteforce_minimum():
+    """Tiny K = 2: the MU limit reaches the minimum found by a bounded quasi-Newton search."""
+    scipy_opt = pytest.importorskip("scipy.optimize")
+    rng = np.random.default_rng(5)
+    F = 8
+    W = rng.uniform(0.2, 1.0, size=(F, 2))
+    htrue = np.array([1.7, 0.4])
+    v = (W @ htrue) * rng.exponential(1.0, size=F) + 1e-3
+
+    def obj(z):
+        hh = np.exp(z)
+        x = W @ hh
+        return float(np.sum(v / x - np.log(v / x) - 1))
+
+    best = min((scipy_opt.minimize(obj, np.log(s), method="Nelder-Mead",
+                                   options=dict(xatol=1e-12, fatol=1e-15, maxiter=20000))
+                for s in ([1.0, 1.0], [0.1, 3.0], [3.0, 0.1])), key=lambda r: r.fun)
+    h, _ = oracle.fit_h(v, W, iters=20000, eps=0.0)
+    f_mu = oracle.dis(v, W @ h)
+    assert f_mu <= best.fun + 1e-10
+    assert np.allclose(h, np.exp(best.x), rtol=2e-4)
+
+
+# ---------------------------------------------------------------- eq. (3) statistics
+
+@pytest.mark.parametrize("eps", [0.0, 0.3])
+def test_batch_stats_majorize_objective(eps):
+    """Eq. (2)-(3): with A, B from the oracle and the constant c derived for the
+    eps-shifted divergence, aux(W) >= D(W) for every W, with equality at W = W_.
+    A dropped W_^2, a wrong power of X or a transposed H breaks one of these."""
+    V, W0, H = _rand_problem(9, 3, 14, seed=6)
+    F, N = V.shape
+    A, B = oracle.batch_stats(V, W0, H, eps)
+    y = eps + V
+    x0 = eps + W0 @ H
+    c = float(np.sum(eps * y / x0 ** 2 + eps / x0 + np.log(x0 / y) - 2.0))
+
+    def D(W):
+        return oracle.objective(V, W, H, eps) * N
+
+    def aux(W):
+        return float(np.sum(A / W + B * W)) + c
+
+    assert abs(aux(W0) - D(W0)) <= 1e-12 * D(W0)
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        Wr = W0 * np.exp(rng.normal(0, 0.7, size=W0.shape))
+        assert D(Wr) <= aux(Wr) * (1 + 1e-12)
+    # the minimizer of the majorizer, sqrt(A/B), decreases D (descent of section 2.1)
+    Wn = np.sqrt(A / B)
+    assert D(Wn) <= aux(Wn) <= D(W0)
+
+
+def test_fixed_point_exact_data():
+    """If V = W H exactly (eps = 0) then sqrt(A/B) = W: the online step maps W to
+    its L1-normalized self, and h_true is a fixed point of the inner updates."""
+    rng = np.random.default_rng(8)
+    F, K, b = 31, 4, 6
+    W = np.asfortranarray(rng.uniform(0.2, 1.2, size=(F, K)))
+    Ht = np.asfortranarray(rng.uniform(0.3, 2.0, size=(K, b)))
+    V = np.asfortranarray(W @ Ht)
+    st = oracle.OnlineState(W)
+    Hb, dw, fl = st.step(V, iters=3, eps=0.0, H=Ht, normalize=True)
+    assert fl == 0
+    s = W.sum(axis=0)
+    assert _relerr(st.W, W / s) < 1e-14
+    assert _relerr(Hb, Ht * s[:, None]) < 1e-13
+    assert abs(dw - np.linalg.norm(W / s - W)) <= 1e-12 * np.linalg.norm(W)
+
+
+def test_frozen_w_online_equals_batch_closed_form():
+    """Section 2.2: with T fixed, the online statistics are those of IS-NMF on the
+    finite set.  W frozen, rho = 1, A0 = B0 = 0, ragged minibatches: the online A, B
+    equal eq. (3) at (W0, collected H)."""
+    V, W0, _ = _rand_problem(17, 5, 23, seed=9)
+    st = oracle.OnlineState(W0)
+    Hs = []
+    eps = 1e-12
+    for s in range(0, 23, 4):             # 4,4,4,4,4,3
+        Hb, _, _ = st.step(V[:, s:s + 4], iters=7, eps=eps, update_w=False)
+        Hs.append(Hb)
+    H = np.concatenate(Hs, axis=1)
+    A, B = oracle.batch_stats(V, W0, H, eps)
+    assert _relerr(st.A, A) < 1e-14
+    assert _relerr(st.B, B) < 1e-14
+    assert np.array_equal(st.W, W0)
+    assert st.t == 23
+
+
+def test_K1_online_closed_form_recursion():
+    """K = 1, eps = 0, no rescaling, b = 1:  a_t = v_t / h_t and b_t = 1 / w(t-1), so
+    A_f = sum_t v_ft / h_t,  B_f = sum_t 1 / w_f(t-1),  w = sqrt(A/B), with h_t from
+    the closed form of the inner loop.  Independent scalar recursion."""
+    rng = np.random.default_rng(10)
+    F, T, I = 13, 25, 6
+    V = np.asfortranarray(rng.gamma(0.8, 2.0, size=(F, T)) + 1e-2)
+    w = rng.uniform(0.5, 1.5, size=F)
+    st = oracle.OnlineState(w[:, None])
+    A = np.zeros(F)
+    B = np.zeros(F)
+    for t in range(T):
+        m = float(np.mean(V[:, t] / w))
+        h = m ** (1.0 - 2.0 ** (-I))
+        A += V[:, t] / h
+        B += 1.0 / w
+        w = np.sqrt(A / B)
+        Hb, _, _ = st.step(V[:, t:t + 1], iters=I, eps=0.0, normalize=False)
+        assert abs(Hb[0, 0] - h) <= 1e-12 * h
+    assert _relerr(st.A[:, 0], A) < 1e-12
+    assert _relerr(st.B[:, 0], B) < 1e-12
+    assert _relerr(st.W[:, 0], w) < 1e-12
+
+
+def test_frame_scale_invariance_warm():
+    """eps = 0: scaling frame n by mu_n (and its warm start by mu_n) scales h_n by mu_n
+    and leaves a, b -- hence A, B, W -- unchanged (bitwise for powers of two)."""
+    V, W0, H0 = _rand_problem(19, 4, 8, seed=11)
+    mu = 2.0 ** np.arange(-3, 5)
+    s1 = oracle.OnlineState(W0)
+    s2 = oracle.OnlineState(W0)
+    H1, _, _ = s1.step(V, iters=5, eps=0.0, H=H0)
+    H2, _, _ = s2.step(V * mu, iters=5, eps=0.0, H=H0 * mu)
+    assert np.array_equal(s1.A, s2.A) and np.array_equal(s1.B, s2.B) and np.array_equal(s1.W, s2.W)
+    assert np.array_equal(H1 * mu, H2)
+
+
+def test_rescale_consistency():
+    """Section 2.3, rescaling W: after the step W = sqrt(A/B) still holds, columns
+    sum to one, and with warm restarts W H is the same as without rescaling."""
+    V, W0, H0 = _rand_problem(21, 5, 9, seed=12)
+    su = oracle.OnlineState(W0)
+    sn = oracle.OnlineState(W0)
+    Hu, _, _ = su.step(V, iters=4, H=H0, normalize=False)
+    Hn, _, _ = sn.step(V, iters=4, H=H0, normalize=True)
+    assert _relerr(sn.W, np.sqrt(sn.A / sn.B)) < 1e-14
+    assert np.allclose(sn.W.sum(axis=0), 1.0, rtol=0, atol=1e-14)
+    assert _relerr(sn.W @ Hn, su.W @ Hu) < 1e-14
+
+
+def test_rho_scales_past_only():
+    """Scaling past data (section 2.3, read as A <- rho A + sum a): with W frozen the
+    new statistics are rho times the old plus the same increment for every rho;
+    rho = 1 gives the un-scaled sum of Algorithm 1."""
+    V, W0, _ = _rand_problem(11, 3, 10, seed=13)
+    base = oracle.OnlineState(W0)
+    base.step(V[:, :5], iters=3, update_w=False)
+    incs = []
+    for rho in [0.0, 0.25, 1.0]:
+        s = base.copy()
+        s.step(V[:, 5:], iters=3, rho=rho, update_w=False)
+        incs.append((rho, s.A - rho * base.A, s.B - rho * base.B))
+    for rho, dA, dB in incs[1:]:
+        assert _relerr(dA, incs[0][1]) < 1e-14 and _relerr(dB, incs[0][2]) < 1e-14
+
+
+def test_loss_sum_is_frame_divergence():
+    """The online loss of eq. (5) accumulates sum_f d_IS(eps+v, eps+W h) per frame."""
+    V, W0, _ = _rand_problem(15, 3, 6, seed=14)
+    st = oracle.OnlineState(W0)
+    Hb, _, _ = st.step(V, iters=4, normalize=False, update_w=False)
+    want = sum(oracle.dis(V[:, n], W0 @ Hb[:, n], 1e-12) for n in range(6))
+    assert abs(st.loss_sum - want) <= 1e-13 * want
+
+
+# ---------------------------------------------------------------- batch MU cycle
+
+def test_batch_objective_never_rises():
+    """Section 2.1: alternating MM updates of H and W form a descent algorithm."""
+    V, W0, _ = _rand_problem(20, 4, 60, seed=15)
+    W, H = W0, np.ones((4, 60))
+    prev = oracle.objective(V, W, H)
+    for _ in range(40):
+        W, H, obj, fl = oracle.batch_cycle(V, W, H)
+        assert fl == 0
+        assert obj <= prev * (1 + 1e-12)
+        assert abs(obj - oracle.objective(V, W, H)) <= 1e-13 * obj
+        prev = obj
+
+
+def test_online_equals_batch_when_beta_is_N_and_r_is_0():
+    """Section 2.3 overview: beta = N and r = 0 make the online algorithm the batch
+    one (warm restarts, one h update per visit).  The batch cycle is written
+    separately in matrix form, so this ties the two codes together."""
+    V, W0, _ = _rand_problem(16, 4, 30, seed=16)
+    H = np.ones((4, 30))
+    Wb, Hb, W, Hw = W0, H, W0, H
+    st = oracle.OnlineState(W0)
+    for _ in range(5):
+        Wb, Hb, _, _ = oracle.batch_cycle(V, Wb, Hb)
+        Hw, _, _ = st.step(V, iters=1, rho=0.0, H=Hw)
+        assert _relerr(st.W, Wb) < 1e-13
+        assert _relerr(Hw, Hb) < 1e-13
+
+
+# ---------------------------------------------------------------- generator statistics
+
+def test_objective_at_true_factors_is_euler_gamma():
+    """Under V = (W H) * E with E ~ Exp(1), E[d_IS(v, W h)] per entry is
+    E[E - log E - 1] = Euler's gamma = 0.5772156649...  Pins the objective's
+    normalisation (1/N, summed over f) and the generator together."""
+    F, K, N = 64, 6, 3000
+    V, Ht = synth.frames(F, K, N, seed=123, with_h=True)
+    Wt = synth.true_dictionary(F, K, 123)
+    per_entry = oracle.objective(V.astype(np.float64), Wt, Ht, eps=0.0) / F
+    se = 1.0 / math.sqrt(F * N) * 1.7        # sd of E - log E is about 1.6
+    assert abs(per_entry - 0.5772156649015329) < 5 * se
+
+
+def test_thread_count_does_not_change_results():
+    V, W0, _ = _rand_problem(33, 5, 12, seed=17)
+    outs = []
+    for nt in (1, 3):
+        oracle.set_threads(nt)
+        st = oracle.OnlineState(W0)
+        Hb, dw, _ = st.step(V, iters=5)
+        outs.append((st.W.copy(), st.A.copy(), st.B.copy(), Hb.copy(), dw, st.loss_sum))
+    oracle.set_threads(1)
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
