@@ -1,0 +1,199 @@
+/*
+ * isnmf.h -- C ABI of the MI355X (gfx950) online Itakura-Saito NMF library.
+ *
+ * Method: Lefevre, Bach, Fevotte, "Online algorithms for Nonnegative Matrix
+ * Factorization with the Itakura-Saito divergence" (arXiv:1106.4198).
+ * Problem statement (section 2.1, eq. 1): given V in R+^{F x N}, find
+ * W in R+^{F x K} and H in R+^{K x N} minimizing
+ *     (1/N) sum_n d_IS(v_n, W h_n),   d_IS(y,x) = sum_i y_i/x_i - log(y_i/x_i) - 1,
+ * with the eps shift d_IS(eps + y, eps + x) of section 2.3.
+ *
+ * Conventions shared by every entry point
+ *  - Layout: column-major.  V is F x N with frame n at V + n*ldv (ldv >= F);
+ *    W is F x K with column k at W + k*ldw (ldw >= F); H is K x N with
+ *    column n at H + n*ldh (ldh >= K); A and B are F x K with leading
+ *    dimension exactly F.
+ *  - Pointers named d_* (and every matrix argument unless stated otherwise)
+ *    are DEVICE pointers on the current HIP device; pointers named host_* are
+ *    host pointers.  The caller allocates and owns every buffer, workspaces
+ *    included; the library never frees caller memory.  Handles are host
+ *    objects created and freed by the library.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    Unless stated otherwise a call only enqueues work on that stream and
+ *    returns before it completes.
+ *  - Errors: every call returns an isnmf_status.  ISNMF_EINVAL is detected
+ *    on the host before any device work is enqueued, and leaves all state
+ *    untouched.  Non-finite inputs or state met on the device set a sticky
+ *    flag word that isnmf_online_status() reads.  No exception crosses the
+ *    ABI.
+ *  - Threads: a handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef ISNMF_H
+#define ISNMF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ISNMF_OK = 0,
+    ISNMF_EINVAL = -1,       /* bad argument; nothing was enqueued          */
+    ISNMF_ENOMEM = -2,       /* workspace too small / host allocation failed */
+    ISNMF_EDEVICE = -3,      /* a HIP runtime call failed                   */
+    ISNMF_ENONFINITE = -4,   /* device flag: non-finite value met           */
+    ISNMF_ESTATE = -5,       /* handle in an unusable state                 */
+    ISNMF_EUNSUPPORTED = -6  /* shape/precision combination not built       */
+} isnmf_status;
+
+/* Arithmetic of the W.H products (the MFMA contractions).  The IS ratios and
+ * sqrt(A/B) stay FP32 (FP64 in ISNMF_FP64), A, B and the objective's log-sum
+ * are FP64 in every mode. */
+typedef enum {
+    ISNMF_FP32 = 0,
+    ISNMF_BF16 = 1,
+    ISNMF_FP16 = 2,
+    ISNMF_FP64 = 3   /* whole fit in FP64 (logic check against the oracle) */
+} isnmf_precision;
+
+/* Starting point of the inner fit of h (section 2.3, fresh or warm restarts). */
+typedef enum {
+    ISNMF_H_ONES = 0,  /* fresh restart from h = 1                         */
+    ISNMF_H_WARM = 1   /* warm restart from the caller's H (in/out)        */
+} isnmf_hinit;
+
+/* Kernel family.  PLAIN: unfused one-op-per-launch kernels (the comparison
+ * point); FUSED: one MFMA kernel for the whole inner fit; AUTO: FUSED where
+ * the shape is supported, else PLAIN. */
+typedef enum {
+    ISNMF_KERNEL_AUTO = 0,
+    ISNMF_KERNEL_PLAIN = 1,
+    ISNMF_KERNEL_FUSED = 2
+} isnmf_kernel;
+
+/* Parameters of Algorithm 1.  Defaults (isnmf_params_default):
+ * eps 1e-12, inner_iters 20, rho 1, normalize 1, h_init ONES, precision
+ * FP32, kernel AUTO, update_w 1. */
+typedef struct {
+    double eps;        /* eps >= 0: shift of the small-amplitude remedy (section 2.3)     */
+    int inner_iters;   /* >= 0: multiplicative updates of h per frame                     */
+    double rho;        /* in [0,1]: weight of past statistics, A <- rho*A + sum a          */
+    int normalize;     /* 1: rescale W columns to unit L1 norm after each update (Alg. 1) */
+    int h_init;        /* isnmf_hinit                                                     */
+    int precision;     /* isnmf_precision                                                 */
+    int kernel;        /* isnmf_kernel                                                    */
+    int update_w;      /* 1: W <- sqrt(A/B); 0: W frozen, statistics still accumulate     */
+} isnmf_params;
+
+typedef struct isnmf_online isnmf_online;   /* opaque handle */
+
+/* Fill *p with the defaults above. */
+void isnmf_params_default(isnmf_params *p);
+
+/* Message for a status code (static string, never NULL). */
+const char *isnmf_strerror(int status);
+
+/* ------------------------------------------------------------------ online */
+
+/* Bytes of device workspace an online handle needs for frames of length F,
+ * K components and minibatches of at most b_max frames.  0 on bad sizes. */
+size_t isnmf_online_workspace_size(int F, int K, int b_max, const isnmf_params *p);
+
+/*
+ * Create an online handle (Algorithm 1, inputs W(0), A(0), B(0), rho, beta,
+ * eps).  W0: device F x K FP32 (ldw).  A0, B0: device F x K FP64 or NULL for
+ * zero (A(0) = B(0) = 0).  workspace: device memory of at least
+ * isnmf_online_workspace_size() bytes, 256-byte aligned, owned by the caller
+ * and used by the handle until isnmf_online_destroy.  p == NULL means the
+ * defaults.  On error *out is NULL.
+ */
+int isnmf_online_init(isnmf_online **out, int F, int K, int b_max, const isnmf_params *p,
+                      const float *W0, int ldw, const double *A0, const double *B0,
+                      void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * One minibatch step (the body of Algorithm 1 at t = 0 mod beta, beta = b;
+ * eq. (4) summed over the minibatch):
+ *   for each frame n < b: h_n <- inner_iters MU updates of argmin_h
+ *        d_IS(eps + v_n, eps + W h)  from h = 1 (ONES) or Hb[:,n] (WARM);
+ *   A <- rho*A + sum_n ((eps+v_n)/(eps+W h_n)^2 h_n^T) o W^2,
+ *   B <- rho*B + sum_n (1/(eps+W h_n)) h_n^T;
+ *   W <- sqrt(A/B); columns rescaled to unit L1 norm (A/s, B*s, warm H*s).
+ * Vb: device F x b FP32 (ldv >= F), values >= 0.  1 <= b <= b_max.
+ * Hb: NULL, or device K x b FP32 (ldh >= K) receiving the fitted h (also the
+ *     starting point under ISNMF_H_WARM, where it is required).
+ * d_loss_sum: NULL or device double; sum_n sum_f d_IS(eps+v, eps+W h) of this
+ *     minibatch (W before the update) is ADDED to it.
+ * d_dw: NULL or device double; receives ||W_new - W_old||_F.
+ * The handle's frame counter t advances by b.
+ */
+int isnmf_online_step(isnmf_online *h, const float *Vb, int ldv, int b,
+                      float *Hb, int ldh, double *d_loss_sum, double *d_dw, void *stream);
+
+/* Copy the state out: W (device F x K FP32, ld F) or NULL, A, B (device
+ * F x K FP64) or NULL, host_t (host) or NULL.  Enqueued on `stream`. */
+int isnmf_online_get(const isnmf_online *h, float *W, double *A, double *B,
+                     long long *host_t, void *stream);
+
+/* FP64 master copy of W (device F x K, ld F).  W is kept in FP64 between
+ * steps in every mode; the FP32 (or BF16/FP16) copy is rounded from it. */
+int isnmf_online_get_w64(const isnmf_online *h, double *W, void *stream);
+
+/* Replace the state (checkpoint restore): W device FP32 F x K (ld F) or
+ * NULL to keep, A, B device FP64 or NULL to keep, t the frame counter. */
+int isnmf_online_set(isnmf_online *h, const float *W, const double *A, const double *B,
+                     long long t, void *stream);
+
+/* As isnmf_online_set for an FP64 W (device F x K, ld F). */
+int isnmf_online_set_w64(isnmf_online *h, const double *W, void *stream);
+
+/* Synchronize the handle's last stream and read the sticky device flags:
+ * bit 0 a non-finite value in V, bit 1 a guarded 0/0 in the h update, bit 2
+ * a guarded 0/0 in W = sqrt(A/B) or the rescale.  Returns ISNMF_ENONFINITE
+ * when bit 0 is set, ISNMF_OK otherwise.  Clears the flags. */
+int isnmf_online_status(isnmf_online *h, int *host_flags);
+
+/* Shape / mode queries. */
+int isnmf_online_info(const isnmf_online *h, int *F, int *K, int *b_max, int *kernel_used);
+
+/* Free the handle (not the workspace). Waits for the handle's last stream. */
+int isnmf_online_destroy(isnmf_online *h);
+
+/* ------------------------------------------------------------------- batch */
+
+/* Bytes of device workspace isnmf_batch_mu needs. */
+size_t isnmf_batch_workspace_size(int F, int K, int N, const isnmf_params *p);
+
+/*
+ * `cycles` cycles of batch IS-NMF by multiplicative updates (section 2.1):
+ * each cycle updates all of H once from the current (W, H), recomputes the
+ * statistics A, B of eq. (3) at the new H, sets W = sqrt(A/B) and, if
+ * p->normalize, rescales W's columns to unit L1 norm with H compensated.
+ * V: device F x N FP32.  W (F x K, ldw) and H (K x N, ldh): device FP32,
+ * in/out (H is the starting point; use ones for a fresh start).
+ * d_obj_trace: NULL or device double[cycles], objective of eq. (1) after
+ * each cycle.  p->inner_iters, rho, h_init and update_w are ignored.
+ */
+int isnmf_batch_mu(const float *V, int ldv, int F, int N, float *W, int ldw,
+                   float *H, int ldh, int K, int cycles, const isnmf_params *p,
+                   double *d_obj_trace, void *workspace, size_t ws_bytes, void *stream);
+
+/* Bytes of device workspace isnmf_objective needs. */
+size_t isnmf_objective_workspace_size(int F, int K, int N);
+
+/*
+ * Objective of eq. (1) with the eps shift:
+ *   *d_out = (1/N) sum_n sum_f d_IS(eps + V_fn, eps + (W H)_fn),
+ * summed in FP64 in a fixed order (deterministic).  V, W, H: device FP32.
+ * d_out: device double.
+ */
+int isnmf_objective(const float *V, int ldv, const float *W, int ldw, const float *H, int ldh,
+                    int F, int K, int N, double eps, double *d_out,
+                    void *workspace, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISNMF_H */

@@ -1,0 +1,262 @@
+"""ctypes binding of libisnmf.so (C ABI in include/isnmf.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  torch supplies device memory and streams.  The library is
+required: importing this module raises if it has not been built.
+
+Matrix convention on the Python side.  The ABI is column-major; a column-major
+F x N matrix is the same memory as a row-major (N, F) torch tensor.  So:
+  V: (N, F) float32   frame n is row n
+  W: (K, F) float32   component k is row k      (F x K column-major)
+  H: (N, K) float32   activations of frame n   (K x N column-major)
+  A, B: (K, F) float64
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libisnmf.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "fp64": 3}
+KERNEL = {"auto": 0, "plain": 1, "fused": 2}
+KERNEL_NAME = {v: k for k, v in KERNEL.items()}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("inner_iters", ctypes.c_int), ("rho", ctypes.c_double),
+                ("normalize", ctypes.c_int), ("h_init", ctypes.c_int), ("precision", ctypes.c_int),
+                ("kernel", ctypes.c_int), ("update_w", ctypes.c_int)]
+
+
+class IsnmfError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1106_4198_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    P = ctypes.POINTER(Params)
+    sig = {
+        "isnmf_params_default": (None, [P]),
+        "isnmf_strerror": (ctypes.c_char_p, [i]),
+        "isnmf_online_workspace_size": (sz, [i, i, i, P]),
+        "isnmf_online_init": (i, [ctypes.POINTER(vp), i, i, i, P, vp, i, vp, vp, vp, sz, vp]),
+        "isnmf_online_step": (i, [vp, vp, i, i, vp, i, vp, vp, vp]),
+        "isnmf_online_get": (i, [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_longlong), vp]),
+        "isnmf_online_get_w64": (i, [vp, vp, vp]),
+        "isnmf_online_set": (i, [vp, vp, vp, vp, ctypes.c_longlong, vp]),
+        "isnmf_online_set_w64": (i, [vp, vp, vp]),
+        "isnmf_online_status": (i, [vp, ctypes.POINTER(i)]),
+        "isnmf_online_info": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
+                                  ctypes.POINTER(i)]),
+        "isnmf_online_destroy": (i, [vp]),
+        "isnmf_batch_workspace_size": (sz, [i, i, i, P]),
+        "isnmf_batch_mu": (i, [vp, i, i, i, vp, i, vp, i, i, i, P, vp, vp, sz, vp]),
+        "isnmf_objective_workspace_size": (sz, [i, i, i]),
+        "isnmf_objective": (i, [vp, i, vp, i, vp, i, i, i, i, d, vp, vp, sz, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("isnmf_params_default", "isnmf_strerror", "isnmf_online_workspace_size",
+            "isnmf_online_init", "isnmf_online_step", "isnmf_online_get", "isnmf_online_get_w64",
+            "isnmf_online_set", "isnmf_online_set_w64", "isnmf_online_status", "isnmf_online_info",
+            "isnmf_online_destroy", "isnmf_batch_workspace_size", "isnmf_batch_mu",
+            "isnmf_objective_workspace_size", "isnmf_objective")
+
+
+def lib():
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return _lib.isnmf_strerror(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise IsnmfError(code, what)
+
+
+def make_params(eps=1e-12, inner_iters=20, rho=1.0, normalize=True, warm=False,
+                precision="fp32", kernel="auto", update_w=True) -> Params:
+    p = Params()
+    _lib.isnmf_params_default(ctypes.byref(p))
+    p.eps = float(eps)
+    p.inner_iters = int(inner_iters)
+    p.rho = float(rho)
+    p.normalize = int(bool(normalize))
+    p.h_init = 1 if warm else 0
+    p.precision = PREC[precision]
+    p.kernel = KERNEL[kernel]
+    p.update_w = int(bool(update_w))
+    return p
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _req(t, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.dim() == 2 and t.stride(1) != 1:
+        raise ValueError(f"{name} rows must be contiguous")
+    return t
+
+
+def _ld(t):
+    return t.stride(0) if t.dim() == 2 else t.shape[-1]
+
+
+class OnlineISNMF:
+    """One online IS-NMF stream (Algorithm 1 with mini-batches) on the GPU."""
+
+    def __init__(self, W0: torch.Tensor, b_max: int, *, eps=1e-12, inner_iters=20, rho=1.0,
+                 normalize=True, warm=False, precision="fp32", kernel="auto", update_w=True,
+                 A0=None, B0=None, stream=None):
+        _req(W0, torch.float32, name="W0")
+        K, F = W0.shape
+        self.F, self.K, self.b_max = int(F), int(K), int(b_max)
+        self.params = make_params(eps, inner_iters, rho, normalize, warm, precision, kernel,
+                                  update_w)
+        self.warm = bool(warm)
+        nbytes = _lib.isnmf_online_workspace_size(self.F, self.K, self.b_max,
+                                                  ctypes.byref(self.params))
+        if nbytes == 0:
+            raise IsnmfError(EINVAL, "isnmf_online_workspace_size")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=W0.device)
+        if A0 is not None:
+            _req(A0, torch.float64, (K, F), "A0")
+        if B0 is not None:
+            _req(B0, torch.float64, (K, F), "B0")
+        h = ctypes.c_void_p()
+        _check(_lib.isnmf_online_init(ctypes.byref(h), self.F, self.K, self.b_max,
+                                      ctypes.byref(self.params), _ptr(W0), _ld(W0),
+                                      _ptr(A0), _ptr(B0), _ptr(self.workspace),
+                                      nbytes, _stream(stream)), "isnmf_online_init")
+        self._h = h
+        self.device = W0.device
+
+    @property
+    def kernel_used(self) -> str:
+        k = ctypes.c_int()
+        _check(_lib.isnmf_online_info(self._h, None, None, None, ctypes.byref(k)), "info")
+        return KERNEL_NAME[k.value]
+
+    def step(self, Vb: torch.Tensor, H: torch.Tensor | None = None, loss_sum=None, dw=None,
+             stream=None):
+        """Vb: (b, F) float32 frames.  H: (b, K) float32 out (in/out when warm).
+        loss_sum, dw: optional float64 device scalars (loss is added)."""
+        _req(Vb, torch.float32, name="Vb")
+        b = Vb.shape[0]
+        if Vb.shape[1] != self.F:
+            raise ValueError("frame length != F")
+        if H is not None:
+            _req(H, torch.float32, (b, self.K), "H")
+        _check(_lib.isnmf_online_step(self._h, _ptr(Vb), _ld(Vb), b, _ptr(H),
+                                      _ld(H) if H is not None else self.K,
+                                      _ptr(loss_sum), _ptr(dw), _stream(stream)),
+               "isnmf_online_step")
+
+    def get(self, stream=None):
+        W = torch.empty((self.K, self.F), dtype=torch.float32, device=self.device)
+        A = torch.empty((self.K, self.F), dtype=torch.float64, device=self.device)
+        B = torch.empty_like(A)
+        t = ctypes.c_longlong()
+        _check(_lib.isnmf_online_get(self._h, _ptr(W), _ptr(A), _ptr(B), ctypes.byref(t),
+                                     _stream(stream)), "isnmf_online_get")
+        return W, A, B, t.value
+
+    def get_w64(self, stream=None):
+        W = torch.empty((self.K, self.F), dtype=torch.float64, device=self.device)
+        _check(_lib.isnmf_online_get_w64(self._h, _ptr(W), _stream(stream)), "get_w64")
+        return W
+
+    def set(self, W=None, A=None, B=None, t=0, stream=None):
+        for x, dt, nm in ((W, torch.float32, "W"), (A, torch.float64, "A"), (B, torch.float64, "B")):
+            if x is not None:
+                _req(x, dt, (self.K, self.F), nm)
+        _check(_lib.isnmf_online_set(self._h, _ptr(W), _ptr(A), _ptr(B), int(t), _stream(stream)),
+               "isnmf_online_set")
+
+    def set_w64(self, W, stream=None):
+        _req(W, torch.float64, (self.K, self.F), "W")
+        _check(_lib.isnmf_online_set_w64(self._h, _ptr(W), _stream(stream)), "set_w64")
+
+    def status(self) -> int:
+        f = ctypes.c_int()
+        code = _lib.isnmf_online_status(self._h, ctypes.byref(f))
+        if code not in (OK, ENONFINITE):
+            _check(code, "isnmf_online_status")
+        return f.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.isnmf_online_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_mu(V: torch.Tensor, W: torch.Tensor, H: torch.Tensor, cycles: int, *, eps=1e-12,
+             normalize=True, precision="fp32", kernel="auto", trace=True, stream=None):
+    """In-place batch MU cycles (section 2.1).  V (N, F), W (K, F), H (N, K) float32.
+    Returns the device float64 objective trace (cycles,) or None."""
+    _req(V, torch.float32, name="V")
+    _req(W, torch.float32, name="W")
+    N, F = V.shape
+    K = W.shape[0]
+    _req(H, torch.float32, (N, K), "H")
+    p = make_params(eps=eps, normalize=normalize, precision=precision, kernel=kernel)
+    nbytes = _lib.isnmf_batch_workspace_size(F, K, N, ctypes.byref(p))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=V.device)
+    tr = torch.zeros(max(cycles, 1), dtype=torch.float64, device=V.device) if trace else None
+    _check(_lib.isnmf_batch_mu(_ptr(V), _ld(V), F, N, _ptr(W), _ld(W), _ptr(H), _ld(H), K,
+                               int(cycles), ctypes.byref(p), _ptr(tr), _ptr(ws), nbytes,
+                               _stream(stream)), "isnmf_batch_mu")
+    return tr[:cycles] if trace else None
+
+
+def objective(V: torch.Tensor, W: torch.Tensor, H: torch.Tensor, eps=1e-12, stream=None):
+    """(1/N) sum_n d_IS(eps + v_n, eps + W h_n) as a device float64 scalar."""
+    _req(V, torch.float32, name="V")
+    _req(W, torch.float32, name="W")
+    N, F = V.shape
+    K = W.shape[0]
+    _req(H, torch.float32, (N, K), "H")
+    nbytes = _lib.isnmf_objective_workspace_size(F, K, N)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=V.device)
+    out = torch.zeros((), dtype=torch.float64, device=V.device)
+    _check(_lib.isnmf_objective(_ptr(V), _ld(V), _ptr(W), _ld(W), _ptr(H), _ld(H), F, K, N,
+                                float(eps), _ptr(out), _ptr(ws), nbytes, _stream(stream)),
+           "isnmf_objective")
+    return out

@@ -1,0 +1,342 @@
+// C ABI of the library (declared in include/isnmf.h): argument checks,
+// workspace carving and the kernel sequence of each call.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "common.h"
+
+using namespace isnmf;
+
+struct isnmf_online {
+    OnlineDev d;
+    isnmf_params p;
+    long long t;
+    hipStream_t last;
+    int kernel_used;
+    int w16_kind;  // 0 none, 1 bf16, 2 fp16
+};
+
+namespace {
+
+int elem_size(const isnmf_params &p) { return p.precision == ISNMF_FP64 ? 8 : 4; }
+
+bool params_ok(const isnmf_params &p) {
+    if (!(p.eps >= 0.0) || !isfinite(p.eps)) return false;
+    if (p.inner_iters < 0) return false;
+    if (!(p.rho >= 0.0 && p.rho <= 1.0)) return false;
+    if (p.h_init != ISNMF_H_ONES && p.h_init != ISNMF_H_WARM) return false;
+    if (p.precision < ISNMF_FP32 || p.precision > ISNMF_FP64) return false;
+    if (p.kernel < ISNMF_KERNEL_AUTO || p.kernel > ISNMF_KERNEL_FUSED) return false;
+    return true;
+}
+
+isnmf_params resolve(const isnmf_params *p) {
+    isnmf_params q;
+    isnmf_params_default(&q);
+    if (p) q = *p;
+    return q;
+}
+
+// Carve the online workspace; with base == nullptr only sizes are computed.
+// with_lossel: keep the per-element loss buffer of the plain path.
+size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lossel, char *base,
+                    OnlineDev *d) {
+    const size_t fk = (size_t)F * K;
+    const int FR = round_up(F, CHUNK);
+    const int KP = round_up(K, 4);
+    const int es = elem_size(p);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *ptr = base ? base + off : nullptr;
+        off += align256(bytes);
+        return ptr;
+    };
+    OnlineDev t;
+    t.F = F;
+    t.K = K;
+    t.b_max = b_max;
+    t.FR = FR;
+    t.KP = KP;
+    t.flags = (int *)take(sizeof(int));
+    t.counter = (unsigned *)take(sizeof(unsigned));
+    t.W64 = (double *)take(fk * 8);
+    t.W32 = (float *)take(fk * 4);
+    t.W16 = (uint16_t *)take(fk * 2);
+    t.A = (double *)take(fk * 8);
+    t.B = (double *)take(fk * 8);
+    t.Wn = (double *)take(fk * 8);
+    t.dwpart = (double *)take((size_t)K * 8);
+    t.lossf = (double *)take((size_t)b_max * 8);
+    t.R1 = take((size_t)b_max * FR * es);
+    t.R2 = take((size_t)b_max * FR * es);
+    t.Hi = take((size_t)b_max * KP * es);
+    t.Xt = nullptr;
+    t.lossel = with_lossel ? (double *)take((size_t)b_max * FR * 8) : nullptr;
+    if (d) *d = t;
+    return off;
+}
+
+int use_fused(const isnmf_params &p, int F, int K) {
+    if (p.precision != ISNMF_FP32) return 0;
+    if (p.kernel == ISNMF_KERNEL_PLAIN) return 0;
+    return fused_supported(F, K) ? 1 : 0;
+}
+
+int run_fit(isnmf_online *h, const float *V, int ldv, int b, int iters, int warm, float *Hb,
+            int ldh, hipStream_t s) {
+    const isnmf_params &p = h->p;
+    hipError_t e;
+    if (p.precision == ISNMF_FP64)
+        e = launch_plain_fit<double>(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
+    else if (h->kernel_used == ISNMF_KERNEL_FUSED)
+        e = launch_fused_fit(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
+    else
+        e = launch_plain_fit<float>(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
+    return e == hipSuccess ? ISNMF_OK : ISNMF_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+void isnmf_params_default(isnmf_params *p) {
+    if (!p) return;
+    p->eps = 1e-12;
+    p->inner_iters = 20;
+    p->rho = 1.0;
+    p->normalize = 1;
+    p->h_init = ISNMF_H_ONES;
+    p->precision = ISNMF_FP32;
+    p->kernel = ISNMF_KERNEL_AUTO;
+    p->update_w = 1;
+}
+
+const char *isnmf_strerror(int status) {
+    switch (status) {
+        case ISNMF_OK: return "ok";
+        case ISNMF_EINVAL: return "invalid argument";
+        case ISNMF_ENOMEM: return "workspace too small or host allocation failed";
+        case ISNMF_EDEVICE: return "HIP runtime error";
+        case ISNMF_ENONFINITE: return "non-finite value met on the device";
+        case ISNMF_ESTATE: return "handle in an unusable state";
+        case ISNMF_EUNSUPPORTED: return "shape or precision not supported";
+        default: return "unknown status";
+    }
+}
+
+size_t isnmf_online_workspace_size(int F, int K, int b_max, const isnmf_params *pp) {
+    if (F < 1 || K < 1 || b_max < 1) return 0;
+    const isnmf_params p = resolve(pp);
+    return carve_online(F, K, b_max, p, true, nullptr, nullptr);
+}
+
+int isnmf_online_init(isnmf_online **out, int F, int K, int b_max, const isnmf_params *pp,
+                      const float *W0, int ldw, const double *A0, const double *B0,
+                      void *workspace, size_t ws_bytes, void *stream) {
+    if (!out) return ISNMF_EINVAL;
+    *out = nullptr;
+    const isnmf_params p = resolve(pp);
+    if (F < 1 || K < 1 || b_max < 1 || !W0 || ldw < F || !workspace || !params_ok(p))
+        return ISNMF_EINVAL;
+    if (((uintptr_t)workspace & 255) != 0) return ISNMF_EINVAL;
+    if (p.precision == ISNMF_BF16 || p.precision == ISNMF_FP16) return ISNMF_EUNSUPPORTED;
+    if (p.kernel == ISNMF_KERNEL_FUSED && !use_fused(p, F, K)) return ISNMF_EUNSUPPORTED;
+    const size_t need = carve_online(F, K, b_max, p, true, nullptr, nullptr);
+    if (ws_bytes < need) return ISNMF_ENOMEM;
+    isnmf_online *h = new (std::nothrow) isnmf_online;
+    if (!h) return ISNMF_ENOMEM;
+    carve_online(F, K, b_max, p, true, (char *)workspace, &h->d);
+    h->p = p;
+    h->t = 0;
+    h->last = (hipStream_t)stream;
+    h->kernel_used = use_fused(p, F, K) ? ISNMF_KERNEL_FUSED : ISNMF_KERNEL_PLAIN;
+    h->w16_kind = 0;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t fk8 = sizeof(double) * (size_t)F * K;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemsetAsync(h->d.flags, 0, sizeof(int), s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->d.counter, 0, sizeof(unsigned), s);
+    if (e == hipSuccess) e = launch_set_w(h->d, W0, ldw, nullptr, h->w16_kind, s);
+    if (e == hipSuccess)
+        e = A0 ? hipMemcpyAsync(h->d.A, A0, fk8, hipMemcpyDeviceToDevice, s)
+               : hipMemsetAsync(h->d.A, 0, fk8, s);
+    if (e == hipSuccess)
+        e = B0 ? hipMemcpyAsync(h->d.B, B0, fk8, hipMemcpyDeviceToDevice, s)
+               : hipMemsetAsync(h->d.B, 0, fk8, s);
+    if (e != hipSuccess) {
+        delete h;
+        return ISNMF_EDEVICE;
+    }
+    *out = h;
+    return ISNMF_OK;
+}
+
+int isnmf_online_step(isnmf_online *h, const float *Vb, int ldv, int b, float *Hb, int ldh,
+                      double *d_loss_sum, double *d_dw, void *stream) {
+    if (!h) return ISNMF_EINVAL;
+    const isnmf_params &p = h->p;
+    const int warm = p.h_init == ISNMF_H_WARM;
+    if (!Vb || b < 1 || b > h->d.b_max || ldv < h->d.F) return ISNMF_EINVAL;
+    if (warm && !Hb) return ISNMF_EINVAL;
+    if (Hb && ldh < h->d.K) return ISNMF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int st = run_fit(h, Vb, ldv, b, p.inner_iters, warm, Hb, ldh, s);
+    if (st != ISNMF_OK) return st;
+    if (launch_fold(h->d, b, p.rho, p.update_w, p.precision == ISNMF_FP64, s) != hipSuccess)
+        return ISNMF_EDEVICE;
+    if (launch_rescale(h->d, b, p.update_w, p.normalize, warm, Hb, ldh, d_loss_sum, d_dw,
+                       h->w16_kind, s) != hipSuccess)
+        return ISNMF_EDEVICE;
+    h->t += b;
+    h->last = s;
+    return ISNMF_OK;
+}
+
+int isnmf_online_get(const isnmf_online *h, float *W, double *A, double *B, long long *host_t,
+                     void *stream) {
+    if (!h) return ISNMF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t fk = (size_t)h->d.F * h->d.K;
+    hipError_t e = hipSuccess;
+    if (W && e == hipSuccess) e = launch_get_w(h->d, W, s);
+    if (A && e == hipSuccess) e = hipMemcpyAsync(A, h->d.A, fk * 8, hipMemcpyDeviceToDevice, s);
+    if (B && e == hipSuccess) e = hipMemcpyAsync(B, h->d.B, fk * 8, hipMemcpyDeviceToDevice, s);
+    if (host_t) *host_t = h->t;
+    return e == hipSuccess ? ISNMF_OK : ISNMF_EDEVICE;
+}
+
+int isnmf_online_get_w64(const isnmf_online *h, double *W, void *stream) {
+    if (!h || !W) return ISNMF_EINVAL;
+    const size_t fk = (size_t)h->d.F * h->d.K;
+    return hipMemcpyAsync(W, h->d.W64, fk * 8, hipMemcpyDeviceToDevice, (hipStream_t)stream) ==
+                   hipSuccess
+               ? ISNMF_OK
+               : ISNMF_EDEVICE;
+}
+
+int isnmf_online_set(isnmf_online *h, const float *W, const double *A, const double *B,
+                     long long t, void *stream) {
+    if (!h || t < 0) return ISNMF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t fk = (size_t)h->d.F * h->d.K;
+    hipError_t e = hipSuccess;
+    if (W) e = launch_set_w(h->d, W, h->d.F, nullptr, h->w16_kind, s);
+    if (A && e == hipSuccess) e = hipMemcpyAsync(h->d.A, A, fk * 8, hipMemcpyDeviceToDevice, s);
+    if (B && e == hipSuccess) e = hipMemcpyAsync(h->d.B, B, fk * 8, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return ISNMF_EDEVICE;
+    h->t = t;
+    h->last = s;
+    return ISNMF_OK;
+}
+
+int isnmf_online_set_w64(isnmf_online *h, const double *W, void *stream) {
+    if (!h || !W) return ISNMF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (launch_set_w(h->d, nullptr, h->d.F, W, h->w16_kind, s) != hipSuccess) return ISNMF_EDEVICE;
+    h->last = s;
+    return ISNMF_OK;
+}
+
+int isnmf_online_status(isnmf_online *h, int *host_flags) {
+    if (!h) return ISNMF_EINVAL;
+    if (hipStreamSynchronize(h->last) != hipSuccess) return ISNMF_EDEVICE;
+    int f = 0;
+    if (hipMemcpy(&f, h->d.flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return ISNMF_EDEVICE;
+    if (hipMemset(h->d.flags, 0, sizeof(int)) != hipSuccess) return ISNMF_EDEVICE;
+    if (host_flags) *host_flags = f;
+    return (f & FLAG_NONFINITE_V) ? ISNMF_ENONFINITE : ISNMF_OK;
+}
+
+int isnmf_online_info(const isnmf_online *h, int *F, int *K, int *b_max, int *kernel_used) {
+    if (!h) return ISNMF_EINVAL;
+    if (F) *F = h->d.F;
+    if (K) *K = h->d.K;
+    if (b_max) *b_max = h->d.b_max;
+    if (kernel_used) *kernel_used = h->kernel_used;
+    return ISNMF_OK;
+}
+
+int isnmf_online_destroy(isnmf_online *h) {
+    if (!h) return ISNMF_EINVAL;
+    hipError_t e = hipStreamSynchronize(h->last);
+    delete h;
+    return e == hipSuccess ? ISNMF_OK : ISNMF_EDEVICE;
+}
+
+// ------------------------------------------------------------------- batch
+
+size_t isnmf_batch_workspace_size(int F, int K, int N, const isnmf_params *pp) {
+    if (F < 1 || K < 1 || N < 1) return 0;
+    isnmf_params p = resolve(pp);
+    if (p.precision != ISNMF_FP64) p.precision = ISNMF_FP32;
+    // the online layout with b_max = N, without the per-element loss buffer
+    return carve_online(F, K, N, p, false, nullptr, nullptr);
+}
+
+int isnmf_batch_mu(const float *V, int ldv, int F, int N, float *W, int ldw, float *H, int ldh,
+                   int K, int cycles, const isnmf_params *pp, double *d_obj_trace,
+                   void *workspace, size_t ws_bytes, void *stream) {
+    isnmf_params p = resolve(pp);
+    if (!V || !W || !H || !workspace || F < 1 || K < 1 || N < 1 || cycles < 0 || ldv < F ||
+        ldw < F || ldh < K || !params_ok(p))
+        return ISNMF_EINVAL;
+    if (((uintptr_t)workspace & 255) != 0) return ISNMF_EINVAL;
+    if (p.precision == ISNMF_BF16 || p.precision == ISNMF_FP16) return ISNMF_EUNSUPPORTED;
+    if (ws_bytes < isnmf_batch_workspace_size(F, K, N, &p)) return ISNMF_ENOMEM;
+    // an online handle over the whole set: beta = N, rho = 0, warm restarts,
+    // one h update per cycle (section 2.3, overview).
+    isnmf_online h;
+    carve_online(F, K, N, p, false, (char *)workspace, &h.d);
+    h.p = p;
+    h.p.rho = 0.0;
+    h.p.h_init = ISNMF_H_WARM;
+    h.p.update_w = 1;
+    h.t = 0;
+    h.w16_kind = 0;
+    h.kernel_used = use_fused(p, F, K) ? ISNMF_KERNEL_FUSED : ISNMF_KERNEL_PLAIN;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemsetAsync(h.d.flags, 0, sizeof(int), s) != hipSuccess) return ISNMF_EDEVICE;
+    if (hipMemsetAsync(h.d.counter, 0, sizeof(unsigned), s) != hipSuccess) return ISNMF_EDEVICE;
+    if (launch_set_w(h.d, W, ldw, nullptr, 0, s) != hipSuccess) return ISNMF_EDEVICE;
+    for (int c = 0; c < cycles; ++c) {
+        int st = run_fit(&h, V, ldv, N, 1, 1, H, ldh, s);
+        if (st != ISNMF_OK) return st;
+        if (launch_fold(h.d, N, 0.0, 1, p.precision == ISNMF_FP64, s) != hipSuccess)
+            return ISNMF_EDEVICE;
+        if (launch_rescale(h.d, N, 1, p.normalize, 1, H, ldh, nullptr, nullptr, 0, s) !=
+            hipSuccess)
+            return ISNMF_EDEVICE;
+        if (d_obj_trace &&
+            launch_objective(V, ldv, h.d.W32, F, H, ldh, F, K, N, p.eps, h.d.lossf,
+                             d_obj_trace + c, s) != hipSuccess)
+            return ISNMF_EDEVICE;
+    }
+    if (hipMemcpy2DAsync(W, sizeof(float) * ldw, h.d.W32, sizeof(float) * F, sizeof(float) * F, K,
+                         hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return ISNMF_EDEVICE;
+    return ISNMF_OK;
+}
+
+size_t isnmf_objective_workspace_size(int F, int K, int N) {
+    if (F < 1 || K < 1 || N < 0) return 0;
+    return align256((size_t)(N > 0 ? N : 1) * 8);
+}
+
+int isnmf_objective(const float *V, int ldv, const float *W, int ldw, const float *H, int ldh,
+                    int F, int K, int N, double eps, double *d_out, void *workspace,
+                    size_t ws_bytes, void *stream) {
+    if (!V || !W || !H || !d_out || !workspace || F < 1 || K < 1 || N < 0 || ldv < F ||
+        ldw < F || ldh < K || !(eps >= 0.0))
+        return ISNMF_EINVAL;
+    if (ws_bytes < isnmf_objective_workspace_size(F, K, N)) return ISNMF_ENOMEM;
+    return launch_objective(V, ldv, W, ldw, H, ldh, F, K, N, eps, (double *)workspace, d_out,
+                            (hipStream_t)stream) == hipSuccess
+               ? ISNMF_OK
+               : ISNMF_EDEVICE;
+}
+
+}  // extern "C"

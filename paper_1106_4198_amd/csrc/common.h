@@ -1,0 +1,86 @@
+// Internal declarations of the gfx950 online IS-NMF library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "isnmf.h"
+
+namespace isnmf {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Sticky device flag bits (isnmf_online_status).
+enum : int {
+    FLAG_NONFINITE_V = 1,
+    FLAG_GUARD_H = 2,
+    FLAG_GUARD_W = 4,
+};
+
+// Rows per MFMA chunk of the fused fit: 16 blocks x 4 rows of v_mfma_f32_4x4x1_16b.
+constexpr int CHUNK = 64;
+// Frames per workgroup of the fused fit (the 4 columns of each 4x4 block).
+constexpr int NF = 4;
+// Rows past the last full chunk that the fused fit handles on the VALU
+// (F = 64 m + 1 for the STFT sizes 129, 257, 513, 1025).
+constexpr int TAIL_MAX = 2;
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Device-side state of one online stream (views into the caller's workspace).
+struct OnlineDev {
+    int F, K, b_max;
+    int FR;              // padded row stride of the R buffers (multiple of 4)
+    int KP;              // padded row stride of the internal H buffer
+    double *W64;         // F x K, ld F: master W (FP64)
+    float *W32;          // F x K, ld F: working copy (FP32)
+    uint16_t *W16;       // F x K, ld F: BF16/FP16 copy (precision forms)
+    double *A, *B;       // F x K, ld F
+    double *Wn;          // F x K: sqrt(A/B) before rescaling
+    double *dwpart;      // K: per-column sum of squared change of W
+    double *lossf;       // b_max: per-frame loss of the current minibatch
+    void *R1, *R2;       // b_max x FR (float, or double in FP64 mode): 1/x and (eps+v)/x^2
+    void *Hi;            // b_max x KP (float or double): fitted h of the minibatch
+    void *Xt;            // plain path scratch: b_max x FR model values / loss terms
+    double *lossel;      // plain path: b_max x FR per-element loss terms
+    int *flags;          // sticky flags
+    unsigned *counter;   // last-block counter of the rescale kernel
+};
+
+// ---------------------------------------------------------------- launchers
+
+// Plain (unfused) fit of all frames of a minibatch; T = float or double.
+// Hb: caller's K x b activations (warm start in, fitted h out) or nullptr.
+template <typename T>
+hipError_t launch_plain_fit(const OnlineDev &d, const float *V, int ldv, int b, int iters,
+                            double eps, int warm, float *Hb, int ldh, hipStream_t s);
+
+// Fused MFMA fit (FP32).  Returns hipErrorNotSupported for shapes it does not cover.
+hipError_t launch_fused_fit(const OnlineDev &d, const float *V, int ldv, int b, int iters,
+                            double eps, int warm, float *Hb, int ldh, hipStream_t s);
+bool fused_supported(int F, int K);
+
+// Fold the minibatch into A, B and (optionally) form sqrt(A/B).
+// Rin/Hin element type: float (is_double = 0) or double (1).
+hipError_t launch_fold(const OnlineDev &d, int b, double rho, int update_w, int is_double,
+                       hipStream_t s);
+
+// Column rescale, W copies, dW, warm-H compensation, loss and diagnostics.
+hipError_t launch_rescale(const OnlineDev &d, int b, int update_w, int normalize, int warm,
+                          float *Hb, int ldh, double *d_loss_sum, double *d_dw, int w16_kind,
+                          hipStream_t s);
+
+// Copy helpers.
+hipError_t launch_set_w(const OnlineDev &d, const float *W, int ldw, const double *W64,
+                        int w16_kind, hipStream_t s);
+hipError_t launch_get_w(const OnlineDev &d, float *W, hipStream_t s);
+
+// Objective of eq. (1): per-frame sums into frame_out (double, N entries) then a
+// fixed-order total into d_out (scaled by 1/N).
+hipError_t launch_objective(const float *V, int ldv, const float *W, int ldw, const float *H,
+                            int ldh, int F, int K, int N, double eps, double *frame_buf,
+                            double *d_out, hipStream_t s);
+
+}  // namespace isnmf

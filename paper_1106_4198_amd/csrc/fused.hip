@@ -1,0 +1,402 @@
+// Fused inner fit of a minibatch on gfx950 MFMA (FP32).
+//
+// What it computes (Algorithm 1, inner argmin truncated to I multiplicative
+// updates, eps shift of section 2.3; the h update of section 2.1):
+//   for each frame n, from h = 1 (or the caller's warm start), I times:
+//     x = eps + W h ; r1 = 1/x ; r2 = (eps + v) r1^2
+//     num = W^T r2 ; den = W^T r1 ; h <- h sqrt(num / den)
+//   then once more x, r1, r2 with the final h, which are written out for the
+//   fold of eq. (4), together with h and the frame loss sum_f d_IS(eps+v, x).
+//
+// Mapping.  A workgroup owns NF = 4 frames.  Rows are cut into chunks of 64;
+// wave w owns chunks w, w + NW, ...  Both contractions run on
+// v_mfma_f32_4x4x1_16b (16 independent 4x4 blocks, rank-1 per instruction):
+//   X (reduce over k): block q = rows 4q..4q+3 of the chunk, columns = frames;
+//      A operand lane l = W[f0 + l][k], B operand lane 4q+n = h[k][n].
+//      Result lane 4q+n, register i = x[f0 + 4q + i][n].
+//   num/den (reduce over f): block q = components 4q..4q+3, columns = frames;
+//      A operand lane l = W[f][l] (k = lane), B operand lane 4q+n = r[f][n]
+//      broadcast through LDS.  Result lane 4q+n, register m = num[4q+m][n].
+// Both W operands stay in registers for the whole minibatch (two layouts of
+// the wave's rows of W).  The per-wave num/den partials meet in LDS once per
+// iteration (one barrier); every wave then applies the same h update, so h
+// needs no second exchange.  Rows past the last full chunk (F = 64 m + t,
+// t <= 4: the Nyquist row of an STFT) are handled on the VALU by wave 0.
+#include "common.h"
+#include "devmath.h"
+
+namespace isnmf {
+namespace {
+
+struct FusedArgs {
+    int F, K, b, ldv, ldh, iters, warm;
+    int main_chunks;  // chunks of 64 rows handled on MFMA (last may be partial)
+    int tail;         // rows after them handled on the VALU (<= TAIL_MAX)
+    int FR, KP;
+    float eps;
+    double epsd;
+    const float *V;
+    const float *W;   // F x K, ld F (FP32 working copy)
+    float *Hb;        // caller's K x b (warm start in / fitted h out) or null
+    float *Hi;        // b x KP internal copy of the fitted h
+    float *R1, *R2;   // b x FR
+    double *lossf;    // b
+    int *flags;
+};
+
+__device__ inline floatx4 mfma4(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+// Keep the compiler from hoisting later LDS loads above this point (bounds
+// the registers held by prefetched operands).
+__device__ inline void compiler_fence() { asm volatile("" ::: "memory"); }
+
+// Order LDS traffic between lanes of one wave (no workgroup barrier needed).
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NW, int CPW, int KMAX>
+__global__ __launch_bounds__(NW * 64) void fused_fit_kernel(FusedArgs a) {
+    static_assert(KMAX % 4 == 0 && KMAX <= 64, "K class");
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int q = lane >> 2;
+    const int n = lane & 3;
+    const int fr = blockIdx.x * NF + n;  // frame of this lane's B/C column
+    const bool fvalid = fr < a.b;
+    const int F = a.F, K = a.K;
+    const float eps = a.eps;
+
+    __shared__ floatx4 red[2][NW][64][2];       // per-wave num/den partials
+    __shared__ float rl[NW][2][NF][CHUNK];       // r2/r1 of the current chunk, per wave
+    __shared__ float hs[NW][NF][KMAX];           // per-wave copy of h (X operand)
+    __shared__ double lred[NW][NF];
+
+    // ---- registers: the wave's rows of W in both operand layouts, and v
+    float wx[CPW][KMAX];      // W[f0 + lane][k]
+    float wn[CPW][CHUNK];     // W[f0 + r][lane]
+    float vr[CPW][4];         // v[f0 + 4q + i][fr]
+    bool cval[CPW];
+    int bad = 0;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        const int c = w + NW * j;
+        cval[j] = c < a.main_chunks;
+        const int f0 = c * CHUNK;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int f = f0 + lane;
+            wx[j][k] = (cval[j] && k < K && f < F) ? a.W[f + (size_t)k * F] : 0.f;
+        }
+#pragma unroll
+        for (int r = 0; r < CHUNK; ++r) {
+            const int f = f0 + r;
+            wn[j][r] = (cval[j] && lane < K && f < F) ? a.W[f + (size_t)lane * F] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = f0 + 4 * q + i;
+            float v = 1.f;
+            if (cval[j] && fvalid && f < F) {
+                v = a.V[(size_t)fr * a.ldv + f];
+                bad |= !isfinite(v);
+            }
+            vr[j][i] = v;
+        }
+    }
+    // tail rows (VALU, wave 0): lane 4q+n keeps W[f][4q+m] and v[f][n]
+    float wt[TAIL_MAX][4];
+    float vt[TAIL_MAX];
+#pragma unroll
+    for (int t = 0; t < TAIL_MAX; ++t) {
+        const int f = a.main_chunks * CHUNK + t;
+        const bool tv = (w == 0) && t < a.tail;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int k = 4 * q + m;
+            wt[t][m] = (tv && k < K) ? a.W[f + (size_t)k * F] : 0.f;
+        }
+        float v = 1.f;
+        if (tv && fvalid) {
+            v = a.V[(size_t)fr * a.ldv + f];
+            bad |= !isfinite(v);
+        }
+        vt[t] = v;
+    }
+    if (bad) atomicOr(a.flags, FLAG_NONFINITE_V);
+
+    // ---- h in the "update" layout: lane 4q+n holds h[4q+m][fr]
+    float hu[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int k = 4 * q + m;
+        float h = 0.f;
+        if (k < K) h = (a.warm && fvalid) ? a.Hb[(size_t)fr * a.ldh + k] : 1.f;
+        hu[m] = h;
+    }
+    if (4 * q < KMAX) *reinterpret_cast<floatx4 *>(&hs[w][n][4 * q]) = floatx4{hu[0], hu[1], hu[2], hu[3]};
+    wave_lds_sync();
+
+    // X = eps + W h for chunk j: lane 4q+n gets rows f0+4q+i of frame fr.
+    auto model = [&](int j, float (&xv)[4]) {
+        floatx4 x0 = {0.f, 0.f, 0.f, 0.f}, x1 = {0.f, 0.f, 0.f, 0.f};
+        // h operand through LDS, loads pipelined one group ahead
+        floatx4 hn = *reinterpret_cast<const floatx4 *>(&hs[w][n][0]);
+#pragma unroll
+        for (int k4 = 0; k4 < KMAX; k4 += 4) {
+            if (k4 < K) {
+                const floatx4 h4 = hn;
+                if (k4 + 4 < KMAX && k4 + 4 < K)
+                    hn = *reinterpret_cast<const floatx4 *>(&hs[w][n][k4 + 4]);
+                x0 = mfma4(wx[j][k4 + 0], h4[0], x0);
+                x1 = mfma4(wx[j][k4 + 1], h4[1], x1);
+                x0 = mfma4(wx[j][k4 + 2], h4[2], x0);
+                x1 = mfma4(wx[j][k4 + 3], h4[3], x1);
+                compiler_fence();
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xv[i] = eps + (x0[i] + x1[i]);
+    };
+    // tail row t on the VALU: x for frame fr, identical in the 16 lanes of fr
+    auto tail_model = [&](int t) {
+        float p = 0.f;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) p += wt[t][m] * hu[m];
+        return eps + sum_over_quads(p);
+    };
+
+    int buf = 0;
+    int guard = 0;
+    for (int it = 0; it < a.iters; ++it) {
+        floatx4 num = {0.f, 0.f, 0.f, 0.f}, den = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            if (!cval[j]) continue;
+            const int f0 = (w + NW * j) * CHUNK;
+            float xv[4], r1[4], r2[4];
+            model(j, xv);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool ok = f0 + 4 * q + i < F;
+                const float ir = __builtin_amdgcn_rcpf(xv[i]);
+                r1[i] = ok ? ir : 0.f;
+                r2[i] = ok ? (eps + vr[j][i]) * ir * ir : 0.f;
+            }
+            // broadcast r to the k-major operand layout through LDS
+            *reinterpret_cast<floatx4 *>(&rl[w][0][n][4 * q]) = floatx4{r2[0], r2[1], r2[2], r2[3]};
+            *reinterpret_cast<floatx4 *>(&rl[w][1][n][4 * q]) = floatx4{r1[0], r1[1], r1[2], r1[3]};
+            wave_lds_sync();
+            floatx4 a2n = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][0]);
+            floatx4 a1n = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][0]);
+#pragma unroll
+            for (int qq = 0; qq < CHUNK / 4; ++qq) {
+                const floatx4 a2 = a2n, a1 = a1n;
+                if (qq + 1 < CHUNK / 4) {
+                    a2n = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][4 * qq + 4]);
+                    a1n = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][4 * qq + 4]);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    num = mfma4(wn[j][4 * qq + i], a2[i], num);
+                    den = mfma4(wn[j][4 * qq + i], a1[i], den);
+                }
+                compiler_fence();
+            }
+            wave_lds_sync();
+        }
+        // tail rows on the VALU (wave 0)
+        if (w == 0) {
+#pragma unroll
+            for (int t = 0; t < TAIL_MAX; ++t) {
+                if (t < a.tail) {
+                    const float x = tail_model(t);
+                    const float ir = __builtin_amdgcn_rcpf(x);
+                    const float rr2 = (eps + vt[t]) * ir * ir;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        num[m] += wt[t][m] * rr2;
+                        den[m] += wt[t][m] * ir;
+                    }
+                }
+            }
+        }
+        // ---- combine the waves' partials (one barrier), then update h
+        red[buf][w][lane][0] = num;
+        red[buf][w][lane][1] = den;
+        __syncthreads();
+        floatx4 N = red[buf][0][lane][0], D = red[buf][0][lane][1];
+#pragma unroll
+        for (int v = 1; v < NW; ++v) {
+            N += red[buf][v][lane][0];
+            D += red[buf][v][lane][1];
+        }
+        buf ^= 1;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (4 * q + m < K) {
+                if (D[m] > 0.f && N[m] >= 0.f)
+                    hu[m] *= sqrtf(N[m] / D[m]);
+                else
+                    guard = 1;
+            }
+        }
+        if (4 * q < KMAX)
+            *reinterpret_cast<floatx4 *>(&hs[w][n][4 * q]) = floatx4{hu[0], hu[1], hu[2], hu[3]};
+        wave_lds_sync();
+    }
+
+    // ---- final model with the fitted h: ratios for the fold of eq. (4)
+    float xf[CPW][4];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        if (!cval[j]) continue;
+        const int f0 = (w + NW * j) * CHUNK;
+        model(j, xf[j]);
+        float r1[4], r2[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const bool ok = f0 + 4 * q + i < F;
+            const float ir = __builtin_amdgcn_rcpf(xf[j][i]);
+            r1[i] = ok ? ir : 0.f;
+            r2[i] = ok ? (eps + vr[j][i]) * ir * ir : 0.f;
+        }
+        if (fvalid) {
+            const size_t o = (size_t)fr * a.FR + f0 + 4 * q;
+            *reinterpret_cast<floatx4 *>(a.R1 + o) = floatx4{r1[0], r1[1], r1[2], r1[3]};
+            *reinterpret_cast<floatx4 *>(a.R2 + o) = floatx4{r2[0], r2[1], r2[2], r2[3]};
+        }
+    }
+    float xt[TAIL_MAX];
+#pragma unroll
+    for (int t = 0; t < TAIL_MAX; ++t) {
+        xt[t] = 1.f;
+        if (w == 0 && t < a.tail) {
+            xt[t] = tail_model(t);
+            if (q == 0 && fvalid) {
+                const int f = a.main_chunks * CHUNK + t;
+                const float ir = __builtin_amdgcn_rcpf(xt[t]);
+                a.R1[(size_t)fr * a.FR + f] = ir;
+                a.R2[(size_t)fr * a.FR + f] = (eps + vt[t]) * ir * ir;
+            }
+        }
+    }
+    // frame loss sum_f d_IS(eps + v, x) in FP64 (eq. (5) numerator)
+    double lsum = 0.0;
+    if (fvalid) {
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            if (!cval[j]) continue;
+            const int f0 = (w + NW * j) * CHUNK;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (f0 + 4 * q + i < F) lsum += dis_term(a.epsd + double(vr[j][i]), double(xf[j][i]));
+        }
+        if (w == 0 && q == 0)
+#pragma unroll
+            for (int t = 0; t < TAIL_MAX; ++t)
+                if (t < a.tail) lsum += dis_term(a.epsd + double(vt[t]), double(xt[t]));
+    }
+    if (guard && w == 0) atomicOr(a.flags, FLAG_GUARD_H);
+
+    // ---- outputs: frame loss (fixed order), h
+    lsum = sum_over_quads(lsum);
+    if (q == 0) lred[w][n] = lsum;
+    __syncthreads();
+    if (w == 0 && q == 0 && fvalid) {
+        double s = 0.0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) s += lred[v][n];
+        a.lossf[fr] = s;
+    }
+    if (w == 0 && fvalid) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int k = 4 * q + m;
+            if (k < K) {
+                a.Hi[(size_t)fr * a.KP + k] = hu[m];
+                if (a.Hb) a.Hb[(size_t)fr * a.ldh + k] = hu[m];
+            }
+        }
+    }
+}
+
+struct Plan {
+    int main_chunks, tail, nw;
+};
+
+Plan plan_for(int F) {
+    Plan p;
+    p.main_chunks = F / CHUNK;
+    p.tail = F % CHUNK;
+    if (p.tail > TAIL_MAX) {
+        p.main_chunks += 1;  // last chunk partially valid (masked)
+        p.tail = 0;
+    }
+    int nw = p.main_chunks < 1 ? 1 : p.main_chunks;
+    p.nw = nw <= 1 ? 1 : nw <= 2 ? 2 : nw <= 4 ? 4 : 8;
+    return p;
+}
+
+template <int NW, int KMAX>
+hipError_t launch_t(const FusedArgs &a, int grid, hipStream_t s) {
+    fused_fit_kernel<NW, 1, KMAX><<<grid, NW * 64, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int NW>
+hipError_t launch_k(const FusedArgs &a, int grid, hipStream_t s) {
+    if (a.K <= 16) return launch_t<NW, 16>(a, grid, s);
+    if (a.K <= 32) return launch_t<NW, 32>(a, grid, s);
+    if (a.K <= 52) return launch_t<NW, 52>(a, grid, s);
+    return launch_t<NW, 64>(a, grid, s);
+}
+
+}  // namespace
+
+bool fused_supported(int F, int K) {
+    if (F < 1 || K < 1 || K > 64) return false;
+    const Plan p = plan_for(F);
+    return p.main_chunks <= 8;
+}
+
+hipError_t launch_fused_fit(const OnlineDev &d, const float *V, int ldv, int b, int iters,
+                            double eps, int warm, float *Hb, int ldh, hipStream_t s) {
+    if (!fused_supported(d.F, d.K)) return hipErrorNotSupported;
+    const Plan p = plan_for(d.F);
+    FusedArgs a;
+    a.F = d.F;
+    a.K = d.K;
+    a.b = b;
+    a.ldv = ldv;
+    a.ldh = ldh;
+    a.iters = iters;
+    a.warm = warm;
+    a.main_chunks = p.main_chunks;
+    a.tail = p.tail;
+    a.FR = d.FR;
+    a.KP = d.KP;
+    a.eps = float(eps);
+    a.epsd = eps;
+    a.V = V;
+    a.W = d.W32;
+    a.Hb = Hb;
+    a.Hi = (float *)d.Hi;
+    a.R1 = (float *)d.R1;
+    a.R2 = (float *)d.R2;
+    a.lossf = d.lossf;
+    a.flags = d.flags;
+    const int grid = (b + NF - 1) / NF;
+    switch (p.nw) {
+        case 1: return launch_k<1>(a, grid, s);
+        case 2: return launch_k<2>(a, grid, s);
+        case 4: return launch_k<4>(a, grid, s);
+        default: return launch_k<8>(a, grid, s);
+    }
+}
+
+}  // namespace isnmf

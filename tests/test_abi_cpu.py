@@ -1,0 +1,110 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching a device.  No
+compute runs here (no GPU in this environment)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "isnmf.h")
+LIB = os.path.join(ROOT, "paper_1106_4198_amd", "libisnmf.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(isnmf_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libisnmf.so not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ["isnmf_online_init", "isnmf_online_step", "isnmf_batch_mu", "isnmf_objective",
+                 "isnmf_online_get", "isnmf_online_set", "isnmf_online_destroy",
+                 "isnmf_online_workspace_size", "isnmf_strerror"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_names_match_header():
+    from paper_1106_4198_amd import binding
+    assert sorted(binding.EXPORTED) == _declared()
+
+
+def test_defaults_and_strerror():
+    from paper_1106_4198_amd import binding as bd
+    p = bd.Params()
+    bd.lib().isnmf_params_default(ctypes.byref(p))
+    assert p.eps == 1e-12 and p.inner_iters == 20 and p.rho == 1.0 and p.normalize == 1
+    assert p.h_init == 0 and p.precision == 0 and p.kernel == 0 and p.update_w == 1
+    for code in range(0, -7, -1):
+        assert bd.strerror(code) and bd.strerror(code) != "unknown status"
+    assert bd.strerror(-99) == "unknown status"
+
+
+def test_workspace_sizes_are_host_only_and_grow():
+    from paper_1106_4198_amd import binding as bd
+    L = bd.lib()
+    p = bd.make_params()
+    s1 = L.isnmf_online_workspace_size(513, 50, 128, ctypes.byref(p))
+    s2 = L.isnmf_online_workspace_size(513, 50, 256, ctypes.byref(p))
+    assert s1 > 0 and s2 > s1 and s1 % 256 == 0
+    # F*K state: W64, W32, W16, A, B, Wn at least
+    assert s1 >= 513 * 50 * (8 + 4 + 2 + 8 + 8 + 8)
+    assert L.isnmf_online_workspace_size(0, 50, 128, ctypes.byref(p)) == 0
+    assert L.isnmf_online_workspace_size(513, 0, 128, ctypes.byref(p)) == 0
+    assert L.isnmf_batch_workspace_size(513, 50, 1000, ctypes.byref(p)) > 0
+    assert L.isnmf_objective_workspace_size(513, 50, 1000) >= 8000
+
+
+def test_einval_before_any_device_work():
+    """These argument errors return before any HIP call (no GPU here)."""
+    from paper_1106_4198_amd import binding as bd
+    L = bd.lib()
+    p = bd.make_params()
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(256)            # never dereferenced: rejected first
+    assert L.isnmf_online_init(None, 10, 2, 4, ctypes.byref(p), fake, 10, None, None, fake, 1 << 20, None) == bd.EINVAL
+    assert L.isnmf_online_init(ctypes.byref(h), 0, 2, 4, ctypes.byref(p), fake, 10, None, None, fake, 1 << 20, None) == bd.EINVAL
+    assert L.isnmf_online_init(ctypes.byref(h), 10, 2, 4, ctypes.byref(p), fake, 9, None, None, fake, 1 << 20, None) == bd.EINVAL
+    bad = bd.make_params(rho=1.5)
+    assert L.isnmf_online_init(ctypes.byref(h), 10, 2, 4, ctypes.byref(bad), fake, 10, None, None, fake, 1 << 20, None) == bd.EINVAL
+    bad = bd.make_params(eps=-1.0)
+    assert L.isnmf_online_init(ctypes.byref(h), 10, 2, 4, ctypes.byref(bad), fake, 10, None, None, fake, 1 << 20, None) == bd.EINVAL
+    bad = bd.make_params(inner_iters=-1)
+    assert L.isnmf_online_init(ctypes.byref(h), 10, 2, 4, ctypes.byref(bad), fake, 10, None, None, fake, 1 << 20, None) == bd.EINVAL
+    # misaligned workspace
+    assert L.isnmf_online_init(ctypes.byref(h), 10, 2, 4, ctypes.byref(p), fake, 10, None, None, ctypes.c_void_p(260), 1 << 20, None) == bd.EINVAL
+    # too small workspace
+    assert L.isnmf_online_init(ctypes.byref(h), 10, 2, 4, ctypes.byref(p), fake, 10, None, None, fake, 16, None) == bd.ENOMEM
+    # fused kernel requested for an unsupported shape
+    fz = bd.make_params(kernel="fused")
+    assert L.isnmf_online_init(ctypes.byref(h), 10, 65, 4, ctypes.byref(fz), fake, 10, None, None, fake, 1 << 30, None) == bd.EUNSUPPORTED
+    assert h.value is None
+    # null handle
+    assert L.isnmf_online_step(None, fake, 10, 1, None, 2, None, None, None) == bd.EINVAL
+    assert L.isnmf_batch_mu(None, 10, 10, 5, fake, 10, fake, 2, 2, 1, None, None, fake, 1 << 20, None) == bd.EINVAL
+    assert L.isnmf_objective(fake, 9, fake, 10, fake, 2, 10, 2, 5, 0.0, fake, fake, 1 << 20, None) == bd.EINVAL
+
+
+def test_product_path_does_not_touch_the_oracle():
+    """The package never imports the oracle (the oracle is test infrastructure)."""
+    pkg = os.path.join(ROOT, "paper_1106_4198_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in src and "from oracle" not in src, fn
+                assert "isnmf_ref_" not in src, fn

@@ -1,0 +1,300 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances (norm-wise and elementwise, see helpers.assert_close):
+  FP64 device mode, one step from identical state:   1e-12 (W, A, B)
+  FP32 path, one step from identical state:           1e-5  (W, A, B, H)
+  full pass, running loss and final objective:        1e-3
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1106_4198_amd import synth
+from tests.helpers import assert_close, from_gpu_kf, rel_fro, to_gpu_kf
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1106_4198_amd import binding as bd  # noqa: E402
+
+DEV = "cuda"
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def make_state(F, K, seed, steps_before=0, b=8, iters=5):
+    """An oracle state with nonzero A, B (a few warm-up steps from W0)."""
+    V, W0 = synth.problem(F, K, steps_before * b + 1, seed)
+    st = oracle.OnlineState(W0.astype(np.float64))
+    for s in range(steps_before):
+        st.step(V[:, s * b:(s + 1) * b].astype(np.float64), iters=iters)
+    return st
+
+
+def gpu_from_state(st, b_max, **kw):
+    W32 = to_gpu_kf(st.W, np.float32, torch)
+    A = to_gpu_kf(st.A, np.float64, torch)
+    B = to_gpu_kf(st.B, np.float64, torch)
+    g = bd.OnlineISNMF(W32, b_max, A0=A, B0=B, **kw)
+    g.set_w64(to_gpu_kf(st.W, np.float64, torch))   # exact FP64 state
+    return g
+
+
+def run_step(g, Vb_fn, H0=None):
+    Vb = torch.from_numpy(np.ascontiguousarray(Vb_fn.T)).to(DEV)
+    if H0 is not None:
+        H = torch.from_numpy(np.ascontiguousarray(H0.T).astype(np.float32)).to(DEV)
+    else:
+        H = torch.zeros((Vb.shape[0], g.K), dtype=torch.float32, device=DEV)
+    loss = torch.zeros((), dtype=torch.float64, device=DEV)
+    dw = torch.zeros((), dtype=torch.float64, device=DEV)
+    g.step(Vb, H, loss, dw)
+    torch.cuda.synchronize()
+    return H.cpu().double().numpy().T, float(loss.item()), float(dw.item())
+
+
+def compare_step(F, K, b, iters, precision, kernel, seed, tol, warm=False, rho=1.0,
+                 normalize=True, update_w=True, steps_before=2, b_max=None):
+    say(f"step F={F} K={K} b={b} I={iters} {precision}/{kernel} warm={warm} rho={rho} "
+        f"norm={normalize} upd={update_w} seed={seed}")
+    st = make_state(F, K, seed, steps_before)
+    Vb = synth.frames(F, K, b, seed + 1000)
+    H0 = None
+    if warm:
+        H0 = np.asfortranarray(np.random.default_rng(seed).uniform(0.2, 2.0, size=(K, b)))
+        H0 = H0.astype(np.float32).astype(np.float64)
+    g = gpu_from_state(st, b_max or b, eps=1e-12, inner_iters=iters, rho=rho,
+                       normalize=normalize, warm=warm, precision=precision, kernel=kernel,
+                       update_w=update_w)
+    if kernel == "fused":
+        assert g.kernel_used == "fused"
+    Hg, lg, dwg = run_step(g, Vb, H0)
+    ref = st.copy()
+    Hr, dwr, fl = ref.step(Vb.astype(np.float64), iters=iters, rho=rho, normalize=normalize,
+                           H=H0, update_w=update_w)
+    assert fl == 0
+    W64 = from_gpu_kf(g.get_w64())
+    Wg, Ag, Bg, t = g.get()
+    assert t == b
+    assert_close(W64, ref.W, tol, "W")
+    assert_close(from_gpu_kf(Ag), ref.A, tol, "A")
+    assert_close(from_gpu_kf(Bg), ref.B, tol, "B")
+    assert_close(from_gpu_kf(Wg), ref.W, max(tol, 1e-7), "W32")
+    assert_close(Hg, Hr, max(tol, 2e-7), "H")
+    assert abs(lg - ref.last_loss) <= max(tol, 1e-9) * abs(ref.last_loss) + 1e-12, (lg, ref.last_loss)
+    if update_w:
+        assert abs(dwg - dwr) <= max(100 * tol, 1e-6) * max(dwr, 1e-30) + 1e-14, (dwg, dwr)
+    assert g.status() == 0
+    g.close()
+
+
+# ---------------------------------------------------------------- one step, FP64 logic check
+
+@pytest.mark.parametrize("F,K,b", [(129, 8, 1), (17, 5, 3), (513, 50, 16), (66, 64, 5), (3, 2, 4)])
+def test_step_fp64_plain(F, K, b):
+    compare_step(F, K, b, 10, "fp64", "plain", seed=11, tol=1e-12)
+
+
+def test_step_fp64_variants():
+    compare_step(40, 6, 7, 4, "fp64", "plain", seed=12, tol=1e-12, warm=True)
+    compare_step(40, 6, 7, 4, "fp64", "plain", seed=13, tol=1e-12, rho=0.5)
+    compare_step(40, 6, 7, 4, "fp64", "plain", seed=14, tol=1e-12, normalize=False)
+    compare_step(40, 6, 7, 4, "fp64", "plain", seed=15, tol=1e-12, update_w=False)
+    compare_step(40, 6, 7, 0, "fp64", "plain", seed=16, tol=1e-12)
+
+
+# ---------------------------------------------------------------- one step, FP32
+
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+@pytest.mark.parametrize("F,K,b", [(129, 8, 1), (513, 50, 128), (257, 64, 7), (65, 16, 9),
+                                   (64, 3, 4), (68, 33, 6), (3, 2, 5), (200, 52, 13)])
+def test_step_fp32(F, K, b, kernel):
+    compare_step(F, K, b, 20, "fp32", kernel, seed=21, tol=1e-5)
+
+
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_step_fp32_variants(kernel):
+    compare_step(130, 10, 11, 6, "fp32", kernel, seed=22, tol=1e-5, warm=True)
+    compare_step(130, 10, 11, 6, "fp32", kernel, seed=23, tol=1e-5, rho=0.7)
+    compare_step(130, 10, 11, 6, "fp32", kernel, seed=24, tol=1e-5, normalize=False)
+    compare_step(130, 10, 11, 6, "fp32", kernel, seed=25, tol=1e-5, update_w=False)
+    compare_step(130, 10, 5, 6, "fp32", kernel, seed=26, tol=1e-5, b_max=16)   # ragged batch
+
+
+def test_auto_falls_back_to_plain_for_wide_K():
+    W0 = torch.rand((80, 70), dtype=torch.float32, device=DEV) + 0.5
+    g = bd.OnlineISNMF(W0, 4, kernel="auto")
+    assert g.kernel_used == "plain"
+    with pytest.raises(bd.IsnmfError):
+        bd.OnlineISNMF(W0, 4, kernel="fused")
+
+
+# ---------------------------------------------------------------- sequences and passes
+
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_per_step_parity_over_a_sequence(kernel):
+    """Ten consecutive steps, each compared from the oracle's state at that step."""
+    F, K, b, I = 257, 20, 32, 20
+    say(f"sequence F={F} K={K} b={b} {kernel}")
+    V, W0 = synth.problem(F, K, 10 * b, seed=31)
+    st = oracle.OnlineState(W0.astype(np.float64))
+    g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b, kernel=kernel,
+                       inner_iters=I)
+    for s in range(10):
+        g.set_w64(to_gpu_kf(st.W, np.float64, torch))
+        g.set(A=to_gpu_kf(st.A, np.float64, torch), B=to_gpu_kf(st.B, np.float64, torch), t=st.t)
+        Vb = V[:, s * b:(s + 1) * b]
+        run_step(g, Vb)
+        st.step(Vb.astype(np.float64), iters=I)
+        assert_close(from_gpu_kf(g.get_w64()), st.W, 1e-5, f"W step {s}")
+        _, A, B, _ = g.get()
+        assert_close(from_gpu_kf(A), st.A, 1e-5, f"A step {s}")
+        assert_close(from_gpu_kf(B), st.B, 1e-5, f"B step {s}")
+
+
+@pytest.mark.parametrize("precision,kernel,tol", [("fp64", "plain", 1e-9), ("fp32", "plain", 1e-3),
+                                                  ("fp32", "fused", 1e-3)])
+def test_full_pass_small_config(precision, kernel, tol):
+    """F=129, K=8, N=2000, b=1, I=10, one pass (the FP64 correctness workload)."""
+    F, K, N, b, I = 129, 8, 2000, 1, 10
+    say(f"full pass F={F} K={K} N={N} b={b} {precision}/{kernel}")
+    V, W0 = synth.problem(F, K, N, seed=41)
+    ref = oracle.online_pass(V.astype(np.float64), W0.astype(np.float64), b, iters=I)
+    g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b, inner_iters=I,
+                       precision=precision, kernel=kernel)
+    Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+    loss = torch.zeros((), dtype=torch.float64, device=DEV)
+    for s in range(0, N, b):
+        g.step(Vt[s:s + b], None, loss)
+    torch.cuda.synchronize()
+    assert abs(loss.item() - ref.loss_sum) <= tol * ref.loss_sum
+    W64 = from_gpu_kf(g.get_w64())
+    assert rel_fro(W64, ref.W) <= tol
+    _, A, B, t = g.get()
+    assert t == N
+    assert rel_fro(from_gpu_kf(A), ref.A) <= tol and rel_fro(from_gpu_kf(B), ref.B) <= tol
+    # final objective of the learned dictionary, activations refit by the oracle
+    Hfit = np.column_stack([oracle.fit_h(V[:, n].astype(np.float64), W64, iters=I)[0] for n in range(0, N, 20)])
+    Href = np.column_stack([oracle.fit_h(V[:, n].astype(np.float64), ref.W, iters=I)[0] for n in range(0, N, 20)])
+    og = oracle.objective(V[:, ::20].astype(np.float64), W64, Hfit)
+    orf = oracle.objective(V[:, ::20].astype(np.float64), ref.W, Href)
+    assert abs(og - orf) <= tol * orf
+
+
+def test_large_config_one_step_fused():
+    """The benchmark shape F=513, K=50, b=128, I=20 from a mid-stream state, with
+    a ragged final minibatch of 64 (1e6 mod 128)."""
+    compare_step(513, 50, 128, 20, "fp32", "fused", seed=51, tol=1e-5, steps_before=3)
+    compare_step(513, 50, 64, 20, "fp32", "fused", seed=52, tol=1e-5, steps_before=3, b_max=128)
+
+
+# ---------------------------------------------------------------- batch MU and objective
+
+# W and H cross the batch ABI in FP32 between cycles, so even the FP64 device
+# mode carries FP32 rounding from one cycle to the next.
+@pytest.mark.parametrize("precision,kernel,tol", [("fp64", "plain", 1e-6), ("fp32", "plain", 1e-5),
+                                                  ("fp32", "fused", 1e-5)])
+def test_batch_mu_matches_oracle(precision, kernel, tol):
+    F, K, N, C = 129, 8, 300, 6
+    say(f"batch MU F={F} K={K} N={N} cycles={C} {precision}/{kernel}")
+    V, W0 = synth.problem(F, K, N, seed=61)
+    Wr, Hr = W0.astype(np.float64), np.ones((K, N))
+    objs = []
+    for _ in range(C):
+        Wr, Hr, o, fl = oracle.batch_cycle(V.astype(np.float64), Wr, Hr)
+        assert fl == 0
+        objs.append(o)
+    Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+    W = torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV)
+    H = torch.ones((N, K), dtype=torch.float32, device=DEV)
+    tr = bd.batch_mu(Vt, W, H, C, precision=precision, kernel=kernel)
+    torch.cuda.synchronize()
+    tr = tr.cpu().numpy()
+    otol = max(tol, 1e-6) if precision == "fp32" else tol
+    for c in range(C):
+        assert abs(tr[c] - objs[c]) <= otol * objs[c], (c, tr[c], objs[c])
+        if c:
+            assert tr[c] <= tr[c - 1] * (1 + 1e-6)
+    assert_close(from_gpu_kf(W), Wr, max(tol, 1e-5) * (10 if precision == "fp32" else 1), "W")
+    assert rel_fro(H.cpu().double().numpy().T, Hr) <= max(tol, 1e-5) * 10
+
+
+def test_objective_matches_oracle():
+    F, K, N = 200, 12, 77
+    say("objective")
+    V, W0 = synth.problem(F, K, N, seed=71)
+    H = np.random.default_rng(1).gamma(0.5, 1.0, size=(K, N)).astype(np.float32)
+    ref = oracle.objective(V.astype(np.float64), W0.astype(np.float64), H.astype(np.float64))
+    got = bd.objective(torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV),
+                       torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV),
+                       torch.from_numpy(np.ascontiguousarray(H.T)).to(DEV)).item()
+    assert abs(got - ref) <= 1e-6 * ref
+
+
+# ---------------------------------------------------------------- robustness
+
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_nonfinite_input_sets_flag(kernel):
+    F, K, b = 70, 4, 4
+    say(f"nonfinite {kernel}")
+    V, W0 = synth.problem(F, K, b, seed=81)
+    V[5, 2] = np.nan
+    g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b, kernel=kernel)
+    g.step(torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV))
+    assert g.status() & 1
+    assert g.status() == 0   # cleared by the read
+
+
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_checkpoint_resume_is_bitwise(kernel):
+    F, K, b = 130, 9, 8
+    say(f"checkpoint {kernel}")
+    V, W0 = synth.problem(F, K, 5 * b, seed=91)
+    Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+    Wt = torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV)
+    a = bd.OnlineISNMF(Wt, b, kernel=kernel)
+    for s in range(5):
+        a.step(Vt[s * b:(s + 1) * b])
+    Wa, Aa, Ba, ta = a.get()
+    Wa64 = a.get_w64()
+    c = bd.OnlineISNMF(Wt, b, kernel=kernel)
+    for s in range(3):
+        c.step(Vt[s * b:(s + 1) * b])
+    Wc, Ac, Bc, tc = c.get()
+    Wc64 = c.get_w64()
+    d = bd.OnlineISNMF(Wc, b, kernel=kernel, A0=Ac, B0=Bc)
+    d.set_w64(Wc64)
+    d.set(t=tc)
+    for s in range(3, 5):
+        d.step(Vt[s * b:(s + 1) * b])
+    Wd, Ad, Bd, td = d.get()
+    torch.cuda.synchronize()
+    assert td == ta == 5 * b
+    assert torch.equal(Wd, Wa) and torch.equal(Ad, Aa) and torch.equal(Bd, Ba)
+    assert torch.equal(d.get_w64(), Wa64)
+
+
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_repeatable_bitwise(kernel):
+    F, K, b = 513, 50, 128
+    say(f"repeatable {kernel}")
+    V, W0 = synth.problem(F, K, b, seed=101)
+    outs = []
+    for _ in range(2):
+        g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b, kernel=kernel)
+        H = torch.zeros((b, K), dtype=torch.float32, device=DEV)
+        g.step(torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV), H)
+        W, A, B, _ = g.get()
+        outs.append((W, A, B, H))
+    torch.cuda.synchronize()
+    for x, y in zip(*outs):
+        assert torch.equal(x, y)
