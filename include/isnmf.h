@@ -131,6 +131,38 @@ int isnmf_online_init(isnmf_online **out, int F, int K, int b_max, const isnmf_p
 int isnmf_online_step(isnmf_online *h, const float *Vb, int ldv, int b,
                       float *Hb, int ldh, double *d_loss_sum, double *d_dw, void *stream);
 
+/*
+ * A pass of Algorithm 1 over n_frames frames already resident on the device:
+ * consecutive minibatches of b frames (the last one shorter when b does not
+ * divide n_frames), each exactly one isnmf_online_step.  V: device F x
+ * n_frames FP32 (ldv >= F).  H: NULL or device K x n_frames (ldh >= K)
+ * receiving every fitted h (required under ISNMF_H_WARM, where it is also
+ * the starting point).  d_loss_sum as in isnmf_online_step (the pass total is
+ * added).  1 <= b <= b_max.
+ */
+int isnmf_online_pass(isnmf_online *h, const float *V, int ldv, long long n_frames, int b,
+                      float *H, int ldh, double *d_loss_sum, void *stream);
+
+/*
+ * Fit activations only (the inner argmin of Algorithm 1 at the current W, no
+ * change to A, B or W): e.g. held-out evaluation, or timing of the fit.
+ * Vb, b, Hb, ldh as in isnmf_online_step (Hb may be NULL); d_loss_sum
+ * receives += sum_n sum_f d_IS(eps + v_n, eps + W h_n).
+ */
+int isnmf_online_fit(isnmf_online *h, const float *Vb, int ldv, int b, float *Hb, int ldh,
+                     double *d_loss_sum, void *stream);
+
+/*
+ * Per-launch timing of the fit kernel with HIP events on the launch stream.
+ * enable != 0 starts recording an event pair around every fit launch of this
+ * handle (up to `capacity` launches; later launches are not timed);
+ * enable == 0 stops.  isnmf_online_timing synchronizes, returns the number
+ * of timed launches and their total duration in milliseconds, and clears
+ * the record.
+ */
+int isnmf_online_set_timing(isnmf_online *h, int enable, int capacity);
+int isnmf_online_timing(isnmf_online *h, long long *host_launches, double *host_total_ms);
+
 /* Copy the state out: W (device F x K FP32, ld F) or NULL, A, B (device
  * F x K FP64) or NULL, host_t (host) or NULL.  Enqueued on `stream`. */
 int isnmf_online_get(const isnmf_online *h, float *W, double *A, double *B,

@@ -59,6 +59,10 @@ def _load():
         "isnmf_online_info": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
                                   ctypes.POINTER(i)]),
         "isnmf_online_destroy": (i, [vp]),
+        "isnmf_online_pass": (i, [vp, vp, i, ctypes.c_longlong, i, vp, i, vp, vp]),
+        "isnmf_online_fit": (i, [vp, vp, i, i, vp, i, vp, vp]),
+        "isnmf_online_set_timing": (i, [vp, i, i]),
+        "isnmf_online_timing": (i, [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(d)]),
         "isnmf_batch_workspace_size": (sz, [i, i, i, P]),
         "isnmf_batch_mu": (i, [vp, i, i, i, vp, i, vp, i, i, i, P, vp, vp, sz, vp]),
         "isnmf_objective_workspace_size": (sz, [i, i, i]),
@@ -75,7 +79,9 @@ _lib = _load()
 EXPORTED = ("isnmf_params_default", "isnmf_strerror", "isnmf_online_workspace_size",
             "isnmf_online_init", "isnmf_online_step", "isnmf_online_get", "isnmf_online_get_w64",
             "isnmf_online_set", "isnmf_online_set_w64", "isnmf_online_status", "isnmf_online_info",
-            "isnmf_online_destroy", "isnmf_batch_workspace_size", "isnmf_batch_mu",
+            "isnmf_online_destroy", "isnmf_online_pass", "isnmf_online_fit",
+            "isnmf_online_set_timing", "isnmf_online_timing",
+            "isnmf_batch_workspace_size", "isnmf_batch_mu",
             "isnmf_objective_workspace_size", "isnmf_objective")
 
 
@@ -182,6 +188,37 @@ class OnlineISNMF:
                                       _ld(H) if H is not None else self.K,
                                       _ptr(loss_sum), _ptr(dw), _stream(stream)),
                "isnmf_online_step")
+
+    def run_pass(self, V: torch.Tensor, b: int, H: torch.Tensor | None = None, loss_sum=None,
+                 stream=None):
+        """Consecutive minibatches of b frames over all rows of V (N, F)."""
+        _req(V, torch.float32, name="V")
+        N = V.shape[0]
+        if H is not None:
+            _req(H, torch.float32, (N, self.K), "H")
+        _check(_lib.isnmf_online_pass(self._h, _ptr(V), _ld(V), int(N), int(b), _ptr(H),
+                                      _ld(H) if H is not None else self.K, _ptr(loss_sum),
+                                      _stream(stream)), "isnmf_online_pass")
+
+    def fit(self, Vb: torch.Tensor, H: torch.Tensor | None = None, loss_sum=None, stream=None):
+        """Inner fit only at the current W (A, B, W unchanged)."""
+        _req(Vb, torch.float32, name="Vb")
+        b = Vb.shape[0]
+        if H is not None:
+            _req(H, torch.float32, (b, self.K), "H")
+        _check(_lib.isnmf_online_fit(self._h, _ptr(Vb), _ld(Vb), b, _ptr(H),
+                                     _ld(H) if H is not None else self.K, _ptr(loss_sum),
+                                     _stream(stream)), "isnmf_online_fit")
+
+    def set_timing(self, enable: bool, capacity: int = 1 << 14):
+        _check(_lib.isnmf_online_set_timing(self._h, int(bool(enable)), int(capacity)), "set_timing")
+
+    def timing(self):
+        """(timed fit launches, total milliseconds) since the last call."""
+        n = ctypes.c_longlong()
+        ms = ctypes.c_double()
+        _check(_lib.isnmf_online_timing(self._h, ctypes.byref(n), ctypes.byref(ms)), "timing")
+        return n.value, ms.value
 
     def get(self, stream=None):
         W = torch.empty((self.K, self.F), dtype=torch.float32, device=self.device)

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "common.h"
 
@@ -17,6 +18,10 @@ struct isnmf_online {
     hipStream_t last;
     int kernel_used;
     int w16_kind;  // 0 none, 1 bf16, 2 fp16
+    // per-launch timing of the fit kernel (isnmf_online_set_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> ev0, ev1;
+    size_t timed = 0;
 };
 
 namespace {
@@ -75,6 +80,8 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
     t.Hi = take((size_t)b_max * KP * es);
     t.Xt = nullptr;
     t.lossel = with_lossel ? (double *)take((size_t)b_max * FR * 8) : nullptr;
+    const size_t pb = fold_partial_bytes(F, K, b_max);
+    t.part = pb ? (float *)take(pb) : nullptr;
     if (d) *d = t;
     return off;
 }
@@ -88,6 +95,8 @@ int use_fused(const isnmf_params &p, int F, int K) {
 int run_fit(isnmf_online *h, const float *V, int ldv, int b, int iters, int warm, float *Hb,
             int ldh, hipStream_t s) {
     const isnmf_params &p = h->p;
+    const bool timed = h->timing && h->timed < h->ev0.size();
+    if (timed && hipEventRecord(h->ev0[h->timed], s) != hipSuccess) return ISNMF_EDEVICE;
     hipError_t e;
     if (p.precision == ISNMF_FP64)
         e = launch_plain_fit<double>(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
@@ -95,7 +104,36 @@ int run_fit(isnmf_online *h, const float *V, int ldv, int b, int iters, int warm
         e = launch_fused_fit(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
     else
         e = launch_plain_fit<float>(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
+    if (e != hipSuccess) return ISNMF_EDEVICE;
+    if (timed) {
+        if (hipEventRecord(h->ev1[h->timed], s) != hipSuccess) return ISNMF_EDEVICE;
+        ++h->timed;
+    }
+    return ISNMF_OK;
+}
+
+// Fold, W = sqrt(A/B) and rescale (the "if t = 0 mod beta" body of Algorithm 1).
+int run_update(isnmf_online *h, int b, double rho, int update_w, int normalize, int warm,
+               float *Hb, int ldh, double *d_loss_sum, double *d_dw, hipStream_t s) {
+    const isnmf_params &p = h->p;
+    hipError_t e;
+    if (h->kernel_used == ISNMF_KERNEL_FUSED && p.precision != ISNMF_FP64) {
+        e = launch_fold_mfma(h->d, b, rho, update_w, h->d.part, d_loss_sum, s);
+    } else {
+        e = launch_fold(h->d, b, rho, update_w, p.precision == ISNMF_FP64, s);
+        if (e == hipSuccess && d_loss_sum) e = launch_loss_total(h->d.lossf, b, d_loss_sum, s);
+    }
+    if (e == hipSuccess)
+        e = launch_rescale(h->d, b, update_w, normalize, warm, Hb, ldh, d_dw, h->w16_kind, s);
     return e == hipSuccess ? ISNMF_OK : ISNMF_EDEVICE;
+}
+
+void free_events(isnmf_online *h) {
+    for (auto e : h->ev0) hipEventDestroy(e);
+    for (auto e : h->ev1) hipEventDestroy(e);
+    h->ev0.clear();
+    h->ev1.clear();
+    h->timed = 0;
 }
 
 }  // namespace
@@ -185,13 +223,86 @@ int isnmf_online_step(isnmf_online *h, const float *Vb, int ldv, int b, float *H
     hipStream_t s = (hipStream_t)stream;
     int st = run_fit(h, Vb, ldv, b, p.inner_iters, warm, Hb, ldh, s);
     if (st != ISNMF_OK) return st;
-    if (launch_fold(h->d, b, p.rho, p.update_w, p.precision == ISNMF_FP64, s) != hipSuccess)
-        return ISNMF_EDEVICE;
-    if (launch_rescale(h->d, b, p.update_w, p.normalize, warm, Hb, ldh, d_loss_sum, d_dw,
-                       h->w16_kind, s) != hipSuccess)
-        return ISNMF_EDEVICE;
+    st = run_update(h, b, p.rho, p.update_w, p.normalize, warm, Hb, ldh, d_loss_sum, d_dw, s);
+    if (st != ISNMF_OK) return st;
     h->t += b;
     h->last = s;
+    return ISNMF_OK;
+}
+
+int isnmf_online_pass(isnmf_online *h, const float *V, int ldv, long long n_frames, int b,
+                      float *H, int ldh, double *d_loss_sum, void *stream) {
+    if (!h || !V || n_frames < 1 || b < 1 || b > h->d.b_max || ldv < h->d.F) return ISNMF_EINVAL;
+    if (h->p.h_init == ISNMF_H_WARM && !H) return ISNMF_EINVAL;
+    if (H && ldh < h->d.K) return ISNMF_EINVAL;
+    for (long long s0 = 0; s0 < n_frames; s0 += b) {
+        const int bb = (int)(n_frames - s0 < b ? n_frames - s0 : b);
+        const int st = isnmf_online_step(h, V + (size_t)s0 * ldv, ldv, bb,
+                                         H ? H + (size_t)s0 * ldh : nullptr, ldh, d_loss_sum,
+                                         nullptr, stream);
+        if (st != ISNMF_OK) return st;
+    }
+    return ISNMF_OK;
+}
+
+int isnmf_online_fit(isnmf_online *h, const float *Vb, int ldv, int b, float *Hb, int ldh,
+                     double *d_loss_sum, void *stream) {
+    if (!h) return ISNMF_EINVAL;
+    const int warm = h->p.h_init == ISNMF_H_WARM;
+    if (!Vb || b < 1 || b > h->d.b_max || ldv < h->d.F) return ISNMF_EINVAL;
+    if (warm && !Hb) return ISNMF_EINVAL;
+    if (Hb && ldh < h->d.K) return ISNMF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int st = run_fit(h, Vb, ldv, b, h->p.inner_iters, warm, Hb, ldh, s);
+    if (st != ISNMF_OK) return st;
+    if (d_loss_sum && launch_loss_total(h->d.lossf, b, d_loss_sum, s) != hipSuccess)
+        return ISNMF_EDEVICE;
+    h->last = s;
+    return ISNMF_OK;
+}
+
+int isnmf_online_set_timing(isnmf_online *h, int enable, int capacity) {
+    if (!h || (enable && capacity < 1)) return ISNMF_EINVAL;
+    if (!enable) {
+        h->timing = false;
+        return ISNMF_OK;
+    }
+    if (hipStreamSynchronize(h->last) != hipSuccess) return ISNMF_EDEVICE;
+    free_events(h);
+    try {
+        h->ev0.resize(capacity);
+        h->ev1.resize(capacity);
+    } catch (...) {
+        h->ev0.clear();
+        h->ev1.clear();
+        return ISNMF_ENOMEM;
+    }
+    for (int i = 0; i < capacity; ++i) {
+        if (hipEventCreate(&h->ev0[i]) != hipSuccess || hipEventCreate(&h->ev1[i]) != hipSuccess) {
+            h->ev0.resize(i);
+            h->ev1.resize(i);
+            free_events(h);
+            return ISNMF_EDEVICE;
+        }
+    }
+    h->timed = 0;
+    h->timing = true;
+    return ISNMF_OK;
+}
+
+int isnmf_online_timing(isnmf_online *h, long long *host_launches, double *host_total_ms) {
+    if (!h) return ISNMF_EINVAL;
+    if (hipStreamSynchronize(h->last) != hipSuccess) return ISNMF_EDEVICE;
+    double tot = 0.0;
+    for (size_t i = 0; i < h->timed; ++i) {
+        if (hipEventSynchronize(h->ev1[i]) != hipSuccess) return ISNMF_EDEVICE;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->ev0[i], h->ev1[i]) != hipSuccess) return ISNMF_EDEVICE;
+        tot += ms;
+    }
+    if (host_launches) *host_launches = (long long)h->timed;
+    if (host_total_ms) *host_total_ms = tot;
+    h->timed = 0;
     return ISNMF_OK;
 }
 
@@ -263,6 +374,7 @@ int isnmf_online_info(const isnmf_online *h, int *F, int *K, int *b_max, int *ke
 int isnmf_online_destroy(isnmf_online *h) {
     if (!h) return ISNMF_EINVAL;
     hipError_t e = hipStreamSynchronize(h->last);
+    free_events(h);
     delete h;
     return e == hipSuccess ? ISNMF_OK : ISNMF_EDEVICE;
 }
@@ -305,11 +417,8 @@ int isnmf_batch_mu(const float *V, int ldv, int F, int N, float *W, int ldw, flo
     for (int c = 0; c < cycles; ++c) {
         int st = run_fit(&h, V, ldv, N, 1, 1, H, ldh, s);
         if (st != ISNMF_OK) return st;
-        if (launch_fold(h.d, N, 0.0, 1, p.precision == ISNMF_FP64, s) != hipSuccess)
-            return ISNMF_EDEVICE;
-        if (launch_rescale(h.d, N, 1, p.normalize, 1, H, ldh, nullptr, nullptr, 0, s) !=
-            hipSuccess)
-            return ISNMF_EDEVICE;
+        st = run_update(&h, N, 0.0, 1, p.normalize, 1, H, ldh, nullptr, nullptr, s);
+        if (st != ISNMF_OK) return st;
         if (d_obj_trace &&
             launch_objective(V, ldv, h.d.W32, F, H, ldh, F, K, N, p.eps, h.d.lossf,
                              d_obj_trace + c, s) != hipSuccess)

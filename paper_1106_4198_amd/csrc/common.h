@@ -45,8 +45,9 @@ struct OnlineDev {
     void *Hi;            // b_max x KP (float or double): fitted h of the minibatch
     void *Xt;            // plain path scratch: b_max x FR model values / loss terms
     double *lossel;      // plain path: b_max x FR per-element loss terms
+    float *part;         // fold slice partials (b_max > 512) or null
     int *flags;          // sticky flags
-    unsigned *counter;   // last-block counter of the rescale kernel
+    unsigned *counter;   // spare device word (zeroed at init)
 };
 
 // ---------------------------------------------------------------- launchers
@@ -67,10 +68,19 @@ bool fused_supported(int F, int K);
 hipError_t launch_fold(const OnlineDev &d, int b, double rho, int update_w, int is_double,
                        hipStream_t s);
 
-// Column rescale, W copies, dW, warm-H compensation, loss and diagnostics.
+// MFMA fold (FP32 R and H).  part: slice partials when b > 512 (see
+// fold_partial_bytes), else unused.  Adds the minibatch loss to d_loss_sum.
+hipError_t launch_fold_mfma(const OnlineDev &d, int b, double rho, int update_w, float *part,
+                            double *d_loss_sum, hipStream_t s);
+size_t fold_partial_bytes(int F, int K, int b);
+
+// Column rescale (when update_w), W copies, warm-H compensation; d_dw (if
+// not null) receives ||W_new - W_old||_F.
 hipError_t launch_rescale(const OnlineDev &d, int b, int update_w, int normalize, int warm,
-                          float *Hb, int ldh, double *d_loss_sum, double *d_dw, int w16_kind,
-                          hipStream_t s);
+                          float *Hb, int ldh, double *d_dw, int w16_kind, hipStream_t s);
+
+// *d_loss_sum += sum of lossf[0..b) in index order (one block).
+hipError_t launch_loss_total(const double *lossf, int b, double *d_loss_sum, hipStream_t s);
 
 // Copy helpers.
 hipError_t launch_set_w(const OnlineDev &d, const float *W, int ldw, const double *W64,

@@ -1,0 +1,170 @@
+// Fold of a minibatch into the running statistics on gfx950 MFMA (FP32
+// products, FP64 statistics).  Eq. (4) summed over the minibatch with the
+// past scaled by rho (section 2.3):
+//   dA' = R2 H^T,  dB = R1 H^T          (F x K, reduction over the b frames)
+//   A <- rho A + dA' o W^2,  B <- rho B + dB,  Wn = sqrt(A / B)
+// with R2 = (eps + v)/x^2 and R1 = 1/x of the final inner-fit model.
+//
+// Mapping: one wave per 16 x 16 tile of (f, k), v_mfma_f32_16x16x4f32 with
+// the frames as the contraction dimension (4 per instruction):
+//   A operand lane l = R2[frame n0 + l/16][f0 + l%16]
+//   B operand lane l = H[frame n0 + l/16][k0 + l%16]
+//   result lane l, register r = dA'[f0 + 4(l/16) + r][k0 + l%16]
+// Minibatches longer than SLICE frames are cut into slices whose FP32 partial
+// tiles are summed in slice order (FP64) by a second kernel.
+#include "common.h"
+
+namespace isnmf {
+namespace {
+
+constexpr int SLICE = 512;
+
+struct FoldArgs {
+    int F, K, b, FR, KP;
+    const float *R1, *R2, *H;
+    const double *W64;
+    double *A, *B, *Wn;
+    double rho;
+    int update_w;
+    int tiles_f;           // ceil(F / 16)
+    float *part;           // slices x 2 x F x K partials (multi-slice only)
+    const double *lossf;   // frame losses of the minibatch (may be null)
+    double *d_loss_sum;    // += sum of lossf (may be null)
+    int *flags;
+};
+
+__device__ inline floatx4 mfma16(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ inline void epilogue(const FoldArgs &a, int f, int k, double sa, double sb) {
+    const size_t e = (size_t)f + (size_t)k * a.F;
+    const double w = a.W64[e];
+    const double av = a.rho * a.A[e] + sa * (w * w);
+    const double bv = a.rho * a.B[e] + sb;
+    a.A[e] = av;
+    a.B[e] = bv;
+    if (a.update_w) {
+        double wn = w;
+        if (bv > 0.0 && av >= 0.0)
+            wn = sqrt(av / bv);
+        else
+            atomicOr(a.flags, FLAG_GUARD_W);
+        a.Wn[e] = wn;
+    }
+}
+
+// grid.x = tiles (one wave each), grid.y = slices.
+__global__ __launch_bounds__(64) void fold_mfma_kernel(FoldArgs a) {
+    const int lane = threadIdx.x;
+    const int tile = blockIdx.x;
+    const int f0 = (tile % a.tiles_f) * 16;
+    const int k0 = (tile / a.tiles_f) * 16;
+    const int slice = blockIdx.y;
+    const int n_lo = slice * SLICE;
+    const int n_hi = min(a.b, n_lo + SLICE);
+    const int fa = f0 + (lane & 15);       // A operand row
+    const int kb = k0 + (lane & 15);       // B operand column
+    const int sub = lane >> 4;             // frame within the group of 4
+    const bool fok = fa < a.F, kok = kb < a.K;
+
+    if (a.d_loss_sum && tile == 0 && slice == 0 && lane == 0) {
+        double s = 0.0;
+        for (int n = 0; n < a.b; ++n) s += a.lossf[n];
+        *a.d_loss_sum += s;
+    }
+
+    floatx4 ca = {0.f, 0.f, 0.f, 0.f}, cb = {0.f, 0.f, 0.f, 0.f};
+    // 8 frame groups per round: all loads of a round are issued before its MFMAs
+    for (int n0 = n_lo; n0 < n_hi; n0 += 32) {
+        float r2[8], r1[8], hh[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            const int n = n0 + 4 * g + sub;
+            const bool ok = n < n_hi;
+            r2[g] = (ok && fok) ? a.R2[(size_t)n * a.FR + fa] : 0.f;
+            r1[g] = (ok && fok) ? a.R1[(size_t)n * a.FR + fa] : 0.f;
+            hh[g] = (ok && kok) ? a.H[(size_t)n * a.KP + kb] : 0.f;
+        }
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            ca = mfma16(r2[g], hh[g], ca);
+            cb = mfma16(r1[g], hh[g], cb);
+        }
+    }
+    const int kc = k0 + (lane & 15);
+    if (gridDim.y == 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = f0 + 4 * sub + r;
+            if (f < a.F && kc < a.K) epilogue(a, f, kc, double(ca[r]), double(cb[r]));
+        }
+    } else {
+        const size_t fk = (size_t)a.F * a.K;
+        float *pa = a.part + (size_t)slice * 2 * fk;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = f0 + 4 * sub + r;
+            if (f < a.F && kc < a.K) {
+                pa[f + (size_t)kc * a.F] = ca[r];
+                pa[fk + f + (size_t)kc * a.F] = cb[r];
+            }
+        }
+    }
+}
+
+// Multi-slice: sum the slice partials in slice order, then the epilogue.
+__global__ void fold_reduce_kernel(FoldArgs a, int slices) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t fk = (size_t)a.F * a.K;
+    if (e >= (long)fk) return;
+    double sa = 0.0, sb = 0.0;
+    for (int s = 0; s < slices; ++s) {
+        sa += double(a.part[(size_t)s * 2 * fk + e]);
+        sb += double(a.part[(size_t)s * 2 * fk + fk + e]);
+    }
+    epilogue(a, (int)(e % a.F), (int)(e / a.F), sa, sb);
+}
+
+}  // namespace
+
+size_t fold_partial_bytes(int F, int K, int b) {
+    const int slices = (b + SLICE - 1) / SLICE;
+    return slices > 1 ? (size_t)slices * 2 * F * K * sizeof(float) : 0;
+}
+
+hipError_t launch_fold_mfma(const OnlineDev &d, int b, double rho, int update_w, float *part,
+                            double *d_loss_sum, hipStream_t s) {
+    FoldArgs a;
+    a.F = d.F;
+    a.K = d.K;
+    a.b = b;
+    a.FR = d.FR;
+    a.KP = d.KP;
+    a.R1 = (const float *)d.R1;
+    a.R2 = (const float *)d.R2;
+    a.H = (const float *)d.Hi;
+    a.W64 = d.W64;
+    a.A = d.A;
+    a.B = d.B;
+    a.Wn = d.Wn;
+    a.rho = rho;
+    a.update_w = update_w;
+    a.tiles_f = (d.F + 15) / 16;
+    a.part = part;
+    a.lossf = d.lossf;
+    a.d_loss_sum = d_loss_sum;
+    a.flags = d.flags;
+    const int tiles = a.tiles_f * ((d.K + 15) / 16);
+    const int slices = (b + SLICE - 1) / SLICE;
+    if (slices > 1 && !part) return hipErrorInvalidValue;
+    fold_mfma_kernel<<<dim3(tiles, slices), 64, 0, s>>>(a);
+    if (slices > 1) {
+        a.d_loss_sum = nullptr;
+        const long fk = (long)d.F * d.K;
+        fold_reduce_kernel<<<(int)((fk + 255) / 256), 256, 0, s>>>(a, slices);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace isnmf

@@ -48,9 +48,10 @@ __device__ inline floatx4 mfma4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
 }
 
-// Keep the compiler from hoisting later LDS loads above this point (bounds
-// the registers held by prefetched operands).
-__device__ inline void compiler_fence() { asm volatile("" ::: "memory"); }
+// Scheduling fence: the operand loads issued before it stay ahead of the
+// MFMAs after it (the scheduler would otherwise sink them and expose the LDS
+// latency), and no later load is hoisted above it (bounds live registers).
+__device__ inline void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
 // Order LDS traffic between lanes of one wave (no workgroup barrier needed).
 __device__ inline void wave_lds_sync() {
@@ -71,9 +72,11 @@ __global__ __launch_bounds__(NW * 64) void fused_fit_kernel(FusedArgs a) {
     const int F = a.F, K = a.K;
     const float eps = a.eps;
 
-    __shared__ floatx4 red[2][NW][64][2];       // per-wave num/den partials
-    __shared__ float rl[NW][2][NF][CHUNK];       // r2/r1 of the current chunk, per wave
-    __shared__ float hs[NW][NF][KMAX];           // per-wave copy of h (X operand)
+    // Rows of rl and hs are padded by 4 floats so that the four frames a
+    // b128 read touches fall in different LDS banks.
+    __shared__ floatx4 red[2][NW][2][64];       // per-wave num/den partials
+    __shared__ float rl[NW][2][NF][CHUNK + 4];   // r2/r1 of the current chunk, per wave
+    __shared__ float hs[NW][NF][KMAX + 4];       // per-wave copy of h (X operand)
     __shared__ double lred[NW][NF];
 
     // ---- registers: the wave's rows of W in both operand layouts, and v
@@ -144,20 +147,18 @@ __global__ __launch_bounds__(NW * 64) void fused_fit_kernel(FusedArgs a) {
     // X = eps + W h for chunk j: lane 4q+n gets rows f0+4q+i of frame fr.
     auto model = [&](int j, float (&xv)[4]) {
         floatx4 x0 = {0.f, 0.f, 0.f, 0.f}, x1 = {0.f, 0.f, 0.f, 0.f};
-        // h operand through LDS, loads pipelined one group ahead
+        // h operand through LDS, one group of 4 components ahead of the MFMAs.
+        // Components k >= K hold h = 0 and W = 0, so all KMAX/4 groups run.
         floatx4 hn = *reinterpret_cast<const floatx4 *>(&hs[w][n][0]);
 #pragma unroll
         for (int k4 = 0; k4 < KMAX; k4 += 4) {
-            if (k4 < K) {
-                const floatx4 h4 = hn;
-                if (k4 + 4 < KMAX && k4 + 4 < K)
-                    hn = *reinterpret_cast<const floatx4 *>(&hs[w][n][k4 + 4]);
-                x0 = mfma4(wx[j][k4 + 0], h4[0], x0);
-                x1 = mfma4(wx[j][k4 + 1], h4[1], x1);
-                x0 = mfma4(wx[j][k4 + 2], h4[2], x0);
-                x1 = mfma4(wx[j][k4 + 3], h4[3], x1);
-                compiler_fence();
-            }
+            const floatx4 h4 = hn;
+            if (k4 + 4 < KMAX) hn = *reinterpret_cast<const floatx4 *>(&hs[w][n][k4 + 4]);
+            sched_fence();
+            x0 = mfma4(wx[j][k4 + 0], h4[0], x0);
+            x1 = mfma4(wx[j][k4 + 1], h4[1], x1);
+            x0 = mfma4(wx[j][k4 + 2], h4[2], x0);
+            x1 = mfma4(wx[j][k4 + 3], h4[3], x1);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) xv[i] = eps + (x0[i] + x1[i]);
@@ -191,21 +192,25 @@ __global__ __launch_bounds__(NW * 64) void fused_fit_kernel(FusedArgs a) {
             *reinterpret_cast<floatx4 *>(&rl[w][0][n][4 * q]) = floatx4{r2[0], r2[1], r2[2], r2[3]};
             *reinterpret_cast<floatx4 *>(&rl[w][1][n][4 * q]) = floatx4{r1[0], r1[1], r1[2], r1[3]};
             wave_lds_sync();
-            floatx4 a2n = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][0]);
-            floatx4 a1n = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][0]);
+            // r operands through LDS, two row-quads ahead of the MFMAs
+            floatx4 a2p[3], a1p[3];
+            a2p[0] = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][0]);
+            a1p[0] = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][0]);
+            a2p[1] = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][4]);
+            a1p[1] = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][4]);
 #pragma unroll
             for (int qq = 0; qq < CHUNK / 4; ++qq) {
-                const floatx4 a2 = a2n, a1 = a1n;
-                if (qq + 1 < CHUNK / 4) {
-                    a2n = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][4 * qq + 4]);
-                    a1n = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][4 * qq + 4]);
+                if (qq + 2 < CHUNK / 4) {
+                    a2p[(qq + 2) % 3] = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][4 * qq + 8]);
+                    a1p[(qq + 2) % 3] = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][4 * qq + 8]);
                 }
+                sched_fence();
+                const floatx4 a2 = a2p[qq % 3], a1 = a1p[qq % 3];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     num = mfma4(wn[j][4 * qq + i], a2[i], num);
                     den = mfma4(wn[j][4 * qq + i], a1[i], den);
                 }
-                compiler_fence();
             }
             wave_lds_sync();
         }
@@ -226,21 +231,21 @@ __global__ __launch_bounds__(NW * 64) void fused_fit_kernel(FusedArgs a) {
             }
         }
         // ---- combine the waves' partials (one barrier), then update h
-        red[buf][w][lane][0] = num;
-        red[buf][w][lane][1] = den;
+        red[buf][w][0][lane] = num;
+        red[buf][w][1][lane] = den;
         __syncthreads();
-        floatx4 N = red[buf][0][lane][0], D = red[buf][0][lane][1];
+        floatx4 N = red[buf][0][0][lane], D = red[buf][0][1][lane];
 #pragma unroll
         for (int v = 1; v < NW; ++v) {
-            N += red[buf][v][lane][0];
-            D += red[buf][v][lane][1];
+            N += red[buf][v][0][lane];
+            D += red[buf][v][1][lane];
         }
         buf ^= 1;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             if (4 * q + m < K) {
                 if (D[m] > 0.f && N[m] >= 0.f)
-                    hu[m] *= sqrtf(N[m] / D[m]);
+                    hu[m] *= __builtin_amdgcn_sqrtf(N[m] * __builtin_amdgcn_rcpf(D[m]));
                 else
                     guard = 1;
             }
@@ -350,8 +355,11 @@ hipError_t launch_t(const FusedArgs &a, int grid, hipStream_t s) {
 
 template <int NW>
 hipError_t launch_k(const FusedArgs &a, int grid, hipStream_t s) {
+    if (a.K <= 8) return launch_t<NW, 8>(a, grid, s);
     if (a.K <= 16) return launch_t<NW, 16>(a, grid, s);
+    if (a.K <= 24) return launch_t<NW, 24>(a, grid, s);
     if (a.K <= 32) return launch_t<NW, 32>(a, grid, s);
+    if (a.K <= 40) return launch_t<NW, 40>(a, grid, s);
     if (a.K <= 52) return launch_t<NW, 52>(a, grid, s);
     return launch_t<NW, 64>(a, grid, s);
 }

@@ -56,81 +56,65 @@ __device__ inline uint16_t to_half_bits(double v, int kind) {
     return *reinterpret_cast<uint16_t *>(&h);
 }
 
-// Block per column k.  The last block to finish (ticket counter) writes the
-// scalar diagnostics, summing the per-column and per-frame partials in index
-// order.
-__global__ void rescale_kernel(int F, int K, int b, const double *__restrict__ Wn,
-                               double *__restrict__ W64, float *__restrict__ W32,
-                               uint16_t *__restrict__ W16, int w16_kind, double *__restrict__ A,
-                               double *__restrict__ B, int update_w, int normalize, int warm,
-                               float *__restrict__ Hb, int ldh, double *__restrict__ dwpart,
-                               const double *__restrict__ lossf, double *__restrict__ d_loss_sum,
-                               double *__restrict__ d_dw, unsigned *__restrict__ counter,
-                               int *__restrict__ flags) {
-    __shared__ double red[256];
-    __shared__ bool last;
+// Sum over a 256-thread block in a fixed order: per-wave xor butterfly (the
+// same value in every lane), then the four wave sums in index order.
+__device__ inline double block_sum256(double v, double *red4) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((red4[0] + red4[1]) + red4[2]) + red4[3];
+}
+
+// Block (256 threads) per column k: s_k = sum_f Wn_fk, W = Wn / s, A /= s,
+// B *= s, warm H[k,:] *= s, and the column's squared change of W.
+__global__ __launch_bounds__(256) void rescale_kernel(
+    int F, int K, int b, const double *__restrict__ Wn, double *__restrict__ W64,
+    float *__restrict__ W32, uint16_t *__restrict__ W16, int w16_kind, double *__restrict__ A,
+    double *__restrict__ B, int normalize, int warm, float *__restrict__ Hb, int ldh,
+    double *__restrict__ dwpart, int *__restrict__ flags) {
+    __shared__ double red4[4];
     const int k = blockIdx.x;
     const int tid = threadIdx.x;
     const size_t col = (size_t)k * F;
-    if (update_w) {
-        double s = 0.0;
-        for (int f = tid; f < F; f += 256) s += Wn[col + f];
-        red[tid] = s;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w) red[tid] += red[tid + w];
-            __syncthreads();
-        }
-        double scale = 1.0;
-        if (normalize) {
-            if (red[0] > 0.0)
-                scale = red[0];
-            else if (tid == 0)
-                atomicOr(flags, FLAG_GUARD_W);
-        }
-        __syncthreads();
-        double dw = 0.0;
-        for (int f = tid; f < F; f += 256) {
-            const double wn = Wn[col + f] / scale;
-            const double dlt = wn - W64[col + f];
-            dw += dlt * dlt;
-            W64[col + f] = wn;
-            W32[col + f] = float(wn);
-            if (W16) W16[col + f] = to_half_bits(wn, w16_kind);
-            if (normalize) {
-                A[col + f] /= scale;
-                B[col + f] *= scale;
-            }
-        }
-        if (warm && Hb && normalize)
-            for (int n = tid; n < b; n += 256) Hb[(size_t)n * ldh + k] *= float(scale);
-        red[tid] = dw;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w) red[tid] += red[tid + w];
-            __syncthreads();
-        }
-        if (tid == 0) dwpart[k] = red[0];
-    } else if (tid == 0) {
-        dwpart[k] = 0.0;
+    double s = 0.0;
+    for (int f = tid; f < F; f += 256) s += Wn[col + f];
+    s = block_sum256(s, red4);
+    double scale = 1.0;
+    if (normalize) {
+        if (s > 0.0)
+            scale = s;
+        else if (tid == 0)
+            atomicOr(flags, FLAG_GUARD_W);
     }
-    // last-block diagnostics.  The agent-scope fences write back / invalidate
-    // the per-XCD L2 so the partials of blocks on other XCDs are visible.
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) last = atomicAdd(counter, 1u) == (unsigned)(gridDim.x - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (tid == 0) {
-        double dw2 = 0.0;
-        for (int j = 0; j < K; ++j) dw2 += dwpart[j];
-        double ls = 0.0;
-        if (d_loss_sum && lossf)
-            for (int n = 0; n < b; ++n) ls += lossf[n];
-        if (d_dw) *d_dw = sqrt(dw2);
-        if (d_loss_sum) *d_loss_sum += ls;
-        *counter = 0u;
+    double dw = 0.0;
+    for (int f = tid; f < F; f += 256) {
+        const double wn = Wn[col + f] / scale;
+        const double dlt = wn - W64[col + f];
+        dw += dlt * dlt;
+        W64[col + f] = wn;
+        W32[col + f] = float(wn);
+        if (W16) W16[col + f] = to_half_bits(wn, w16_kind);
+        if (normalize) {
+            A[col + f] /= scale;
+            B[col + f] *= scale;
+        }
+    }
+    if (warm && Hb && normalize)
+        for (int n = tid; n < b; n += 256) Hb[(size_t)n * ldh + k] *= float(scale);
+    dw = block_sum256(dw, red4);
+    if (tid == 0) dwpart[k] = dw;
+}
+
+// ||W_new - W_old||_F from the per-column partials, in column order.
+__global__ void dw_total_kernel(int K, const double *__restrict__ dwpart, int update_w,
+                                double *__restrict__ out) {
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        if (update_w)
+            for (int k = 0; k < K; ++k) s += dwpart[k];
+        *out = sqrt(s);
     }
 }
 
@@ -147,7 +131,21 @@ __global__ void set_w_kernel(int F, int K, const float *__restrict__ W, int ldw,
     if (W16) W16[e] = to_half_bits(v, w16_kind);
 }
 
+__global__ void loss_total_kernel(const double *__restrict__ lossf, int b,
+                                  double *__restrict__ out) {
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int n = 0; n < b; ++n) s += lossf[n];
+        *out += s;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_loss_total(const double *lossf, int b, double *d_loss_sum, hipStream_t s) {
+    loss_total_kernel<<<1, 64, 0, s>>>(lossf, b, d_loss_sum);
+    return hipGetLastError();
+}
 
 hipError_t launch_fold(const OnlineDev &d, int b, double rho, int update_w, int is_double,
                        hipStream_t s) {
@@ -165,11 +163,12 @@ hipError_t launch_fold(const OnlineDev &d, int b, double rho, int update_w, int 
 }
 
 hipError_t launch_rescale(const OnlineDev &d, int b, int update_w, int normalize, int warm,
-                          float *Hb, int ldh, double *d_loss_sum, double *d_dw, int w16_kind,
-                          hipStream_t s) {
-    rescale_kernel<<<d.K, 256, 0, s>>>(d.F, d.K, b, d.Wn, d.W64, d.W32, w16_kind ? d.W16 : nullptr,
-                                       w16_kind, d.A, d.B, update_w, normalize, warm, Hb, ldh,
-                                       d.dwpart, d.lossf, d_loss_sum, d_dw, d.counter, d.flags);
+                          float *Hb, int ldh, double *d_dw, int w16_kind, hipStream_t s) {
+    if (update_w)
+        rescale_kernel<<<d.K, 256, 0, s>>>(d.F, d.K, b, d.Wn, d.W64, d.W32,
+                                           w16_kind ? d.W16 : nullptr, w16_kind, d.A, d.B,
+                                           normalize, warm, Hb, ldh, d.dwpart, d.flags);
+    if (d_dw) dw_total_kernel<<<1, 64, 0, s>>>(d.K, d.dwpart, update_w, d_dw);
     return hipGetLastError();
 }
 

@@ -41,28 +41,43 @@ def initial_dictionary(F: int, K: int, seed: int) -> np.ndarray:
     return np.asfortranarray(_rng(seed, 1).uniform(0.5, 1.5, size=(K, F)).T.astype(np.float32))
 
 
-def frames(F: int, K: int, N: int, seed: int, start: int = 0, with_h: bool = False):
+def _chunk(Wt: np.ndarray, F: int, K: int, seed: int, c: int):
+    g = _rng(seed, 2, c)
+    Ht = g.gamma(0.3, 1.0, size=(CHUNK, K)).T       # K x CHUNK
+    E = g.exponential(1.0, size=(CHUNK, F)).T        # F x CHUNK
+    return Ht, E
+
+
+def frames(F: int, K: int, N: int, seed: int, start: int = 0, with_h: bool = False,
+           threads: int = 0):
     """Frames [start, start+N) of stream `seed`: float32 F x N (Fortran).
 
-    With with_h, also returns the float64 H_true columns used (K x N)."""
+    With with_h, also returns the float64 H_true columns used (K x N).
+    threads > 1 draws the chunks in parallel (same values)."""
     Wt = true_dictionary(F, K, seed)
     out = np.empty((F, N), dtype=np.float32, order="F")
     hs = np.empty((K, N), dtype=np.float64, order="F") if with_h else None
     c0 = start // CHUNK
     c1 = (start + N + CHUNK - 1) // CHUNK
-    pos = 0
-    for c in range(c0, c1):
-        g = _rng(seed, 2, c)
-        Ht = g.gamma(0.3, 1.0, size=(CHUNK, K)).T       # K x CHUNK
-        E = g.exponential(1.0, size=(CHUNK, F)).T        # F x CHUNK
+
+    def fill(c):
+        Ht, E = _chunk(Wt, F, K, seed, c)
         lo = max(start - c * CHUNK, 0)
         hi = min(start + N - c * CHUNK, CHUNK)
+        pos = c * CHUNK + lo - start
         blk = (Wt @ Ht[:, lo:hi]) * E[:, lo:hi]
         np.maximum(blk, FLOOR, out=blk)
         out[:, pos:pos + hi - lo] = blk
         if with_h:
             hs[:, pos:pos + hi - lo] = Ht[:, lo:hi]
-        pos += hi - lo
+
+    if threads > 1 and c1 - c0 > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(fill, range(c0, c1)))
+    else:
+        for c in range(c0, c1):
+            fill(c)
     if with_h:
         return out, hs
     return out
