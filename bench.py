@@ -39,7 +39,11 @@ def flops_per_frame(F: int, K: int, iters: int) -> float:
 # HBM traffic of the fit kernel measured with rocprofv3 --pmc (FETCH_SIZE,
 # WRITE_SIZE), keyed by the sha1 of the kernel source it was measured on.
 # A changed kernel has no entry, and its traffic is reported as null.
-TRAFFIC = {}
+TRAFFIC = {
+    # FETCH_SIZE 707.9 KiB x 2.0 + WRITE_SIZE 547.0 KiB x 1.0 per b=128 launch
+    # (profiles/fused_fit_F513_K50_b128_pmc.md)
+    "69c549109c00391bd413404f3696582ba3f5306d": 1962.8 * 1024,
+}
 
 
 def _src_hash() -> str:
@@ -90,6 +94,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=2011)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a kernel of "
+                         "known traffic, to scale rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -108,6 +115,12 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
+    if args.copy_calib_mib > 0:
+        src = torch.ones(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     N = args.frames
     steps_full = (N + B - 1) // B
     steps = steps_full if args.steps is None else max(1, min(args.steps, steps_full))

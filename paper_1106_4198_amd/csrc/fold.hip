@@ -5,8 +5,9 @@
 //   A <- rho A + dA' o W^2,  B <- rho B + dB,  Wn = sqrt(A / B)
 // with R2 = (eps + v)/x^2 and R1 = 1/x of the final inner-fit model.
 //
-// Mapping: one wave per 16 x 16 tile of (f, k), v_mfma_f32_16x16x4f32 with
-// the frames as the contraction dimension (4 per instruction):
+// Mapping: one block of 4 waves per 16 x 16 tile of (f, k),
+// v_mfma_f32_16x16x4f32 with the frames as the contraction dimension (4 per
+// instruction, groups of 4 frames dealt round-robin to the waves):
 //   A operand lane l = R2[frame n0 + l/16][f0 + l%16]
 //   B operand lane l = H[frame n0 + l/16][k0 + l%16]
 //   result lane l, register r = dA'[f0 + 4(l/16) + r][k0 + l%16]
@@ -54,9 +55,12 @@ __device__ inline void epilogue(const FoldArgs &a, int f, int k, double sa, doub
     }
 }
 
-// grid.x = tiles (one wave each), grid.y = slices.
-__global__ __launch_bounds__(64) void fold_mfma_kernel(FoldArgs a) {
-    const int lane = threadIdx.x;
+// grid.x = tiles, grid.y = slices; 4 waves per tile, frame groups of 4
+// dealt round-robin to the waves, partial tiles summed in wave order.
+__global__ __launch_bounds__(256) void fold_mfma_kernel(FoldArgs a) {
+    __shared__ floatx4 red[4][2][64];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
     const int tile = blockIdx.x;
     const int f0 = (tile % a.tiles_f) * 16;
     const int k0 = (tile / a.tiles_f) * 16;
@@ -68,19 +72,19 @@ __global__ __launch_bounds__(64) void fold_mfma_kernel(FoldArgs a) {
     const int sub = lane >> 4;             // frame within the group of 4
     const bool fok = fa < a.F, kok = kb < a.K;
 
-    if (a.d_loss_sum && tile == 0 && slice == 0 && lane == 0) {
+    if (a.d_loss_sum && tile == 0 && slice == 0 && threadIdx.x == 0) {
         double s = 0.0;
         for (int n = 0; n < a.b; ++n) s += a.lossf[n];
         *a.d_loss_sum += s;
     }
 
     floatx4 ca = {0.f, 0.f, 0.f, 0.f}, cb = {0.f, 0.f, 0.f, 0.f};
-    // 8 frame groups per round: all loads of a round are issued before its MFMAs
-    for (int n0 = n_lo; n0 < n_hi; n0 += 32) {
+    // rounds of 8 groups per wave: every load of a round is issued before its MFMAs
+    for (int g0 = n_lo + 4 * w; g0 < n_hi; g0 += 4 * 4 * 8) {
         float r2[8], r1[8], hh[8];
 #pragma unroll
         for (int g = 0; g < 8; ++g) {
-            const int n = n0 + 4 * g + sub;
+            const int n = g0 + 16 * g + sub;
             const bool ok = n < n_hi;
             r2[g] = (ok && fok) ? a.R2[(size_t)n * a.FR + fa] : 0.f;
             r1[g] = (ok && fok) ? a.R1[(size_t)n * a.FR + fa] : 0.f;
@@ -92,6 +96,12 @@ __global__ __launch_bounds__(64) void fold_mfma_kernel(FoldArgs a) {
             cb = mfma16(r1[g], hh[g], cb);
         }
     }
+    red[w][0][lane] = ca;
+    red[w][1][lane] = cb;
+    __syncthreads();
+    if (w != 0) return;
+    ca = ((red[0][0][lane] + red[1][0][lane]) + red[2][0][lane]) + red[3][0][lane];
+    cb = ((red[0][1][lane] + red[1][1][lane]) + red[2][1][lane]) + red[3][1][lane];
     const int kc = k0 + (lane & 15);
     if (gridDim.y == 1) {
 #pragma unroll
@@ -158,7 +168,7 @@ hipError_t launch_fold_mfma(const OnlineDev &d, int b, double rho, int update_w,
     const int tiles = a.tiles_f * ((d.K + 15) / 16);
     const int slices = (b + SLICE - 1) / SLICE;
     if (slices > 1 && !part) return hipErrorInvalidValue;
-    fold_mfma_kernel<<<dim3(tiles, slices), 64, 0, s>>>(a);
+    fold_mfma_kernel<<<dim3(tiles, slices), 256, 0, s>>>(a);
     if (slices > 1) {
         a.d_loss_sum = nullptr;
         const long fk = (long)d.F * d.K;

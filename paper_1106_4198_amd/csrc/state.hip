@@ -78,8 +78,22 @@ __global__ __launch_bounds__(256) void rescale_kernel(
     const int k = blockIdx.x;
     const int tid = threadIdx.x;
     const size_t col = (size_t)k * F;
+    // all loads first (one memory round trip), then the column sum
+    constexpr int RMAX = 8;   // rows per thread held in registers (F <= 2048)
+    double wn[RMAX], wo[RMAX], av[RMAX], bv[RMAX];
     double s = 0.0;
-    for (int f = tid; f < F; f += 256) s += Wn[col + f];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+        const int f = tid + 256 * r;
+        const bool ok = f < F;
+        wn[r] = ok ? Wn[col + f] : 0.0;
+        wo[r] = ok ? W64[col + f] : 0.0;
+        av[r] = ok ? A[col + f] : 0.0;
+        bv[r] = ok ? B[col + f] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) s += wn[r];
+    for (int f = tid + 256 * RMAX; f < F; f += 256) s += Wn[col + f];
     s = block_sum256(s, red4);
     double scale = 1.0;
     if (normalize) {
@@ -89,13 +103,29 @@ __global__ __launch_bounds__(256) void rescale_kernel(
             atomicOr(flags, FLAG_GUARD_W);
     }
     double dw = 0.0;
-    for (int f = tid; f < F; f += 256) {
-        const double wn = Wn[col + f] / scale;
-        const double dlt = wn - W64[col + f];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+        const int f = tid + 256 * r;
+        if (f < F) {
+            const double w = wn[r] / scale;
+            const double dlt = w - wo[r];
+            dw += dlt * dlt;
+            W64[col + f] = w;
+            W32[col + f] = float(w);
+            if (W16) W16[col + f] = to_half_bits(w, w16_kind);
+            if (normalize) {
+                A[col + f] = av[r] / scale;
+                B[col + f] = bv[r] * scale;
+            }
+        }
+    }
+    for (int f = tid + 256 * RMAX; f < F; f += 256) {
+        const double w = Wn[col + f] / scale;
+        const double dlt = w - W64[col + f];
         dw += dlt * dlt;
-        W64[col + f] = wn;
-        W32[col + f] = float(wn);
-        if (W16) W16[col + f] = to_half_bits(wn, w16_kind);
+        W64[col + f] = w;
+        W32[col + f] = float(w);
+        if (W16) W16[col + f] = to_half_bits(w, w16_kind);
         if (normalize) {
             A[col + f] /= scale;
             B[col + f] *= scale;
