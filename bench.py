@@ -91,6 +91,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--frames", type=int, default=1_000_000)
     ap.add_argument("--plain-steps", type=int, default=100)
+    ap.add_argument("--form-steps", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=2011)
@@ -177,6 +178,25 @@ def main() -> int:
                 "avg_launch_us": fit_ms * 1e3 / max(launches, 1),
                 "flops_per_launch": flops_per_frame(F, K, ITERS) * B}
 
+    # precision forms: BF16 / FP16 products, same stream prefix
+    def time_form(precision, nsteps):
+        gw = bd.OnlineISNMF(Wt, B, inner_iters=ITERS, precision=precision)
+        gw.run_pass(Vt[:B * 4], B)
+        gw.close()
+        gf = bd.OnlineISNMF(Wt, B, inner_iters=ITERS, precision=precision)
+        torch.cuda.synchronize()
+        e0.record()
+        gf.run_pass(Vt[:nsteps * B], B)
+        e1.record()
+        torch.cuda.synchronize()
+        v = nsteps * B / (e0.elapsed_time(e1) / 1e3)
+        gf.close()
+        return v
+
+    f_steps = max(1, min(args.form_steps, steps))
+    forms = {p: {"value": time_form(p, f_steps), "unit": "frames/s", "steps": f_steps}
+             for p in ("bf16", "fp16")}
+
     # the plain FP32 path (one op per launch) over a prefix, same shapes
     p_steps = max(1, min(args.plain_steps, steps))
     gp = bd.OnlineISNMF(Wt, B, inner_iters=ITERS, kernel="plain")
@@ -213,6 +233,7 @@ def main() -> int:
         "plain_fp32": {"value": plain_fps, "unit": "frames/s", "steps": p_steps,
                        "speedup_fused": fps / plain_fps},
         "online_loss_per_entry": online_loss,
+        "forms": forms,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(V, W0, args.cpu_seconds)

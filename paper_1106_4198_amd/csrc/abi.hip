@@ -87,10 +87,13 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
 }
 
 int use_fused(const isnmf_params &p, int F, int K) {
-    if (p.precision != ISNMF_FP32) return 0;
+    if (p.precision == ISNMF_FP64) return 0;
     if (p.kernel == ISNMF_KERNEL_PLAIN) return 0;
     return fused_supported(F, K) ? 1 : 0;
 }
+
+// 16-bit product forms exist only as fused kernels.
+bool is16(const isnmf_params &p) { return p.precision == ISNMF_BF16 || p.precision == ISNMF_FP16; }
 
 int run_fit(isnmf_online *h, const float *V, int ldv, int b, int iters, int warm, float *Hb,
             int ldh, hipStream_t s) {
@@ -101,7 +104,8 @@ int run_fit(isnmf_online *h, const float *V, int ldv, int b, int iters, int warm
     if (p.precision == ISNMF_FP64)
         e = launch_plain_fit<double>(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
     else if (h->kernel_used == ISNMF_KERNEL_FUSED)
-        e = launch_fused_fit(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
+        e = launch_fused_fit(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh,
+                             p.precision == ISNMF_BF16 ? 1 : p.precision == ISNMF_FP16 ? 2 : 0, s);
     else
         e = launch_plain_fit<float>(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
     if (e != hipSuccess) return ISNMF_EDEVICE;
@@ -180,8 +184,9 @@ int isnmf_online_init(isnmf_online **out, int F, int K, int b_max, const isnmf_p
     if (F < 1 || K < 1 || b_max < 1 || !W0 || ldw < F || !workspace || !params_ok(p))
         return ISNMF_EINVAL;
     if (((uintptr_t)workspace & 255) != 0) return ISNMF_EINVAL;
-    if (p.precision == ISNMF_BF16 || p.precision == ISNMF_FP16) return ISNMF_EUNSUPPORTED;
-    if (p.kernel == ISNMF_KERNEL_FUSED && !use_fused(p, F, K)) return ISNMF_EUNSUPPORTED;
+    if ((p.kernel == ISNMF_KERNEL_FUSED || is16(p)) && !use_fused(p, F, K))
+        return ISNMF_EUNSUPPORTED;
+    if (is16(p) && p.kernel == ISNMF_KERNEL_PLAIN) return ISNMF_EUNSUPPORTED;
     const size_t need = carve_online(F, K, b_max, p, true, nullptr, nullptr);
     if (ws_bytes < need) return ISNMF_ENOMEM;
     isnmf_online *h = new (std::nothrow) isnmf_online;
@@ -384,7 +389,6 @@ int isnmf_online_destroy(isnmf_online *h) {
 size_t isnmf_batch_workspace_size(int F, int K, int N, const isnmf_params *pp) {
     if (F < 1 || K < 1 || N < 1) return 0;
     isnmf_params p = resolve(pp);
-    if (p.precision != ISNMF_FP64) p.precision = ISNMF_FP32;
     // the online layout with b_max = N, without the per-element loss buffer
     return carve_online(F, K, N, p, false, nullptr, nullptr);
 }
@@ -397,7 +401,8 @@ int isnmf_batch_mu(const float *V, int ldv, int F, int N, float *W, int ldw, flo
         ldw < F || ldh < K || !params_ok(p))
         return ISNMF_EINVAL;
     if (((uintptr_t)workspace & 255) != 0) return ISNMF_EINVAL;
-    if (p.precision == ISNMF_BF16 || p.precision == ISNMF_FP16) return ISNMF_EUNSUPPORTED;
+    if (is16(p) && (p.kernel == ISNMF_KERNEL_PLAIN || !use_fused(p, F, K)))
+        return ISNMF_EUNSUPPORTED;
     if (ws_bytes < isnmf_batch_workspace_size(F, K, N, &p)) return ISNMF_ENOMEM;
     // an online handle over the whole set: beta = N, rho = 0, warm restarts,
     // one h update per cycle (section 2.3, overview).

@@ -58,9 +58,10 @@ template <typename T>
 hipError_t launch_plain_fit(const OnlineDev &d, const float *V, int ldv, int b, int iters,
                             double eps, int warm, float *Hb, int ldh, hipStream_t s);
 
-// Fused MFMA fit (FP32).  Returns hipErrorNotSupported for shapes it does not cover.
+// Fused MFMA fit; prec 0 = FP32, 1 = BF16, 2 = FP16 products.  Returns
+// hipErrorNotSupported for shapes it does not cover.
 hipError_t launch_fused_fit(const OnlineDev &d, const float *V, int ldv, int b, int iters,
-                            double eps, int warm, float *Hb, int ldh, hipStream_t s);
+                            double eps, int warm, float *Hb, int ldh, int prec, hipStream_t s);
 bool fused_supported(int F, int K);
 
 // Fold the minibatch into A, B and (optionally) form sqrt(A/B).

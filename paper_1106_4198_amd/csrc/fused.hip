@@ -21,7 +21,14 @@
 // the wave's rows of W).  The per-wave num/den partials meet in LDS once per
 // iteration (one barrier); every wave then applies the same h update, so h
 // needs no second exchange.  Rows past the last full chunk (F = 64 m + t,
-// t <= 4: the Nyquist row of an STFT) are handled on the VALU by wave 0.
+// t <= 2: the Nyquist row of an STFT) are handled on the VALU by wave 0.
+//
+// Precision forms (PREC 1 = BF16, 2 = FP16): the same mapping on
+// v_mfma_f32_4x4x4_16b_{bf16,f16}, four contraction steps per instruction,
+// FP32 accumulation.  W is rounded to 16 bits as W * 2^s and h as h * 2^-s
+// (s = round(log2 F), exact power-of-two scales, so W h is unchanged) which
+// keeps L1-normalised columns and large activations inside FP16's range.  The
+// IS ratios, the h update, the tail rows and the loss stay FP32/FP64.
 #include "common.h"
 #include "devmath.h"
 
@@ -35,6 +42,7 @@ struct FusedArgs {
     int FR, KP;
     float eps;
     double epsd;
+    float wscale, hscale;   // 16-bit forms: W * wscale and h * hscale (powers of two)
     const float *V;
     const float *W;   // F x K, ld F (FP32 working copy)
     float *Hb;        // caller's K x b (warm start in / fitted h out) or null
@@ -46,6 +54,35 @@ struct FusedArgs {
 
 __device__ inline floatx4 mfma4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+typedef short v4h __attribute__((ext_vector_type(4)));      // four 16-bit values
+typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
+
+// Round to nearest even (finite inputs).
+__device__ inline unsigned short to_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+template <int PREC>
+__device__ inline unsigned short to16(float f) {
+    if constexpr (PREC == 1) return to_bf16(f);
+    return __builtin_bit_cast(unsigned short, (_Float16)f);
+}
+
+template <int PREC>
+__device__ inline v4h pack4(float a, float b, float c, float d) {
+    return v4h{(short)to16<PREC>(a), (short)to16<PREC>(b), (short)to16<PREC>(c),
+               (short)to16<PREC>(d)};
+}
+
+template <int PREC>
+__device__ inline floatx4 mfma16b(v4h a, v4h b, floatx4 c) {
+    if constexpr (PREC == 1) return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_4x4x4f16(__builtin_bit_cast(halfx4, a),
+                                             __builtin_bit_cast(halfx4, b), c, 0, 0, 0);
 }
 
 // Scheduling fence: the operand loads issued before it stay ahead of the
@@ -60,9 +97,10 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int NW, int CPW, int KMAX>
+template <int NW, int CPW, int KMAX, int PREC>
 __global__ __launch_bounds__(NW * 64) void fused_fit_kernel(FusedArgs a) {
     static_assert(KMAX % 4 == 0 && KMAX <= 64, "K class");
+    constexpr bool H16 = PREC != 0;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int q = lane >> 2;
@@ -75,13 +113,17 @@ __global__ __launch_bounds__(NW * 64) void fused_fit_kernel(FusedArgs a) {
     // Rows of rl and hs are padded by 4 floats so that the four frames a
     // b128 read touches fall in different LDS banks.
     __shared__ floatx4 red[2][NW][2][64];       // per-wave num/den partials
-    __shared__ float rl[NW][2][NF][CHUNK + 4];   // r2/r1 of the current chunk, per wave
-    __shared__ float hs[NW][NF][KMAX + 4];       // per-wave copy of h (X operand)
+    __shared__ float rl[NW][2][NF][H16 ? 4 : CHUNK + 4];   // r2/r1 of the current chunk
+    __shared__ float hs[NW][NF][H16 ? 4 : KMAX + 4];       // per-wave copy of h (X operand)
+    __shared__ unsigned short rl16[NW][2][NF][H16 ? CHUNK + 8 : 4];
+    __shared__ unsigned short hs16[NW][NF][H16 ? KMAX + 8 : 4];
     __shared__ double lred[NW][NF];
 
     // ---- registers: the wave's rows of W in both operand layouts, and v
-    float wx[CPW][KMAX];      // W[f0 + lane][k]
-    float wn[CPW][CHUNK];     // W[f0 + r][lane]
+    float wx[CPW][H16 ? 1 : KMAX];          // W[f0 + lane][k]
+    float wn[CPW][H16 ? 1 : CHUNK];         // W[f0 + r][lane]
+    v4h wx16[CPW][H16 ? KMAX / 4 : 1];      // W[f0 + lane][4g .. 4g+3] * wscale
+    v4h wn16[CPW][H16 ? CHUNK / 4 : 1];     // W[f0 + 4g .. 4g+3][lane] * wscale
     float vr[CPW][4];         // v[f0 + 4q + i][fr]
     bool cval[CPW];
     int bad = 0;
@@ -90,15 +132,29 @@ __global__ __launch_bounds__(NW * 64) void fused_fit_kernel(FusedArgs a) {
         const int c = w + NW * j;
         cval[j] = c < a.main_chunks;
         const int f0 = c * CHUNK;
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
+        auto wxv = [&](int k) {
             const int f = f0 + lane;
-            wx[j][k] = (cval[j] && k < K && f < F) ? a.W[f + (size_t)k * F] : 0.f;
-        }
-#pragma unroll
-        for (int r = 0; r < CHUNK; ++r) {
+            return (cval[j] && k < K && f < F) ? a.W[f + (size_t)k * F] : 0.f;
+        };
+        auto wnv = [&](int r) {
             const int f = f0 + r;
-            wn[j][r] = (cval[j] && lane < K && f < F) ? a.W[f + (size_t)lane * F] : 0.f;
+            return (cval[j] && lane < K && f < F) ? a.W[f + (size_t)lane * F] : 0.f;
+        };
+        if constexpr (!H16) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) wx[j][k] = wxv(k);
+#pragma unroll
+            for (int r = 0; r < CHUNK; ++r) wn[j][r] = wnv(r);
+        } else {
+            const float sc = a.wscale;
+#pragma unroll
+            for (int g = 0; g < KMAX / 4; ++g)
+                wx16[j][g] = pack4<PREC>(wxv(4 * g) * sc, wxv(4 * g + 1) * sc,
+                                         wxv(4 * g + 2) * sc, wxv(4 * g + 3) * sc);
+#pragma unroll
+            for (int g = 0; g < CHUNK / 4; ++g)
+                wn16[j][g] = pack4<PREC>(wnv(4 * g) * sc, wnv(4 * g + 1) * sc,
+                                         wnv(4 * g + 2) * sc, wnv(4 * g + 3) * sc);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -141,7 +197,18 @@ __global__ __launch_bounds__(NW * 64) void fused_fit_kernel(FusedArgs a) {
         if (k < K) h = (a.warm && fvalid) ? a.Hb[(size_t)fr * a.ldh + k] : 1.f;
         hu[m] = h;
     }
-    if (4 * q < KMAX) *reinterpret_cast<floatx4 *>(&hs[w][n][4 * q]) = floatx4{hu[0], hu[1], hu[2], hu[3]};
+    // the X operand copy of h (FP32, or 16-bit scaled by hscale)
+    auto store_h = [&]() {
+        if (4 * q < KMAX) {
+            if constexpr (!H16)
+                *reinterpret_cast<floatx4 *>(&hs[w][n][4 * q]) = floatx4{hu[0], hu[1], hu[2], hu[3]};
+            else
+                *reinterpret_cast<v4h *>(&hs16[w][n][4 * q]) =
+                    pack4<PREC>(hu[0] * a.hscale, hu[1] * a.hscale, hu[2] * a.hscale,
+                                hu[3] * a.hscale);
+        }
+    };
+    store_h();
     wave_lds_sync();
 
     // X = eps + W h for chunk j: lane 4q+n gets rows f0+4q+i of frame fr.
@@ -149,16 +216,31 @@ __global__ __launch_bounds__(NW * 64) void fused_fit_kernel(FusedArgs a) {
         floatx4 x0 = {0.f, 0.f, 0.f, 0.f}, x1 = {0.f, 0.f, 0.f, 0.f};
         // h operand through LDS, one group of 4 components ahead of the MFMAs.
         // Components k >= K hold h = 0 and W = 0, so all KMAX/4 groups run.
-        floatx4 hn = *reinterpret_cast<const floatx4 *>(&hs[w][n][0]);
+        if constexpr (!H16) {
+            floatx4 hn = *reinterpret_cast<const floatx4 *>(&hs[w][n][0]);
 #pragma unroll
-        for (int k4 = 0; k4 < KMAX; k4 += 4) {
-            const floatx4 h4 = hn;
-            if (k4 + 4 < KMAX) hn = *reinterpret_cast<const floatx4 *>(&hs[w][n][k4 + 4]);
-            sched_fence();
-            x0 = mfma4(wx[j][k4 + 0], h4[0], x0);
-            x1 = mfma4(wx[j][k4 + 1], h4[1], x1);
-            x0 = mfma4(wx[j][k4 + 2], h4[2], x0);
-            x1 = mfma4(wx[j][k4 + 3], h4[3], x1);
+            for (int k4 = 0; k4 < KMAX; k4 += 4) {
+                const floatx4 h4 = hn;
+                if (k4 + 4 < KMAX) hn = *reinterpret_cast<const floatx4 *>(&hs[w][n][k4 + 4]);
+                sched_fence();
+                x0 = mfma4(wx[j][k4 + 0], h4[0], x0);
+                x1 = mfma4(wx[j][k4 + 1], h4[1], x1);
+                x0 = mfma4(wx[j][k4 + 2], h4[2], x0);
+                x1 = mfma4(wx[j][k4 + 3], h4[3], x1);
+            }
+        } else {
+            v4h hp[3];
+            hp[0] = *reinterpret_cast<const v4h *>(&hs16[w][n][0]);
+            if (KMAX > 4) hp[1] = *reinterpret_cast<const v4h *>(&hs16[w][n][4]);
+#pragma unroll
+            for (int g = 0; g < KMAX / 4; ++g) {
+                if (g + 2 < KMAX / 4) hp[(g + 2) % 3] = *reinterpret_cast<const v4h *>(&hs16[w][n][4 * g + 8]);
+                sched_fence();
+                if (g & 1)
+                    x1 = mfma16b<PREC>(wx16[j][g], hp[g % 3], x1);
+                else
+                    x0 = mfma16b<PREC>(wx16[j][g], hp[g % 3], x0);
+            }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) xv[i] = eps + (x0[i] + x1[i]);
@@ -189,27 +271,48 @@ __global__ __launch_bounds__(NW * 64) void fused_fit_kernel(FusedArgs a) {
                 r2[i] = ok ? (eps + vr[j][i]) * ir * ir : 0.f;
             }
             // broadcast r to the k-major operand layout through LDS
-            *reinterpret_cast<floatx4 *>(&rl[w][0][n][4 * q]) = floatx4{r2[0], r2[1], r2[2], r2[3]};
-            *reinterpret_cast<floatx4 *>(&rl[w][1][n][4 * q]) = floatx4{r1[0], r1[1], r1[2], r1[3]};
-            wave_lds_sync();
-            // r operands through LDS, two row-quads ahead of the MFMAs
-            floatx4 a2p[3], a1p[3];
-            a2p[0] = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][0]);
-            a1p[0] = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][0]);
-            a2p[1] = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][4]);
-            a1p[1] = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][4]);
+            if constexpr (!H16) {
+                *reinterpret_cast<floatx4 *>(&rl[w][0][n][4 * q]) = floatx4{r2[0], r2[1], r2[2], r2[3]};
+                *reinterpret_cast<floatx4 *>(&rl[w][1][n][4 * q]) = floatx4{r1[0], r1[1], r1[2], r1[3]};
+                wave_lds_sync();
+                // r operands through LDS, two row-quads ahead of the MFMAs
+                floatx4 a2p[3], a1p[3];
+                a2p[0] = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][0]);
+                a1p[0] = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][0]);
+                a2p[1] = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][4]);
+                a1p[1] = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][4]);
 #pragma unroll
-            for (int qq = 0; qq < CHUNK / 4; ++qq) {
-                if (qq + 2 < CHUNK / 4) {
-                    a2p[(qq + 2) % 3] = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][4 * qq + 8]);
-                    a1p[(qq + 2) % 3] = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][4 * qq + 8]);
+                for (int qq = 0; qq < CHUNK / 4; ++qq) {
+                    if (qq + 2 < CHUNK / 4) {
+                        a2p[(qq + 2) % 3] = *reinterpret_cast<const floatx4 *>(&rl[w][0][n][4 * qq + 8]);
+                        a1p[(qq + 2) % 3] = *reinterpret_cast<const floatx4 *>(&rl[w][1][n][4 * qq + 8]);
+                    }
+                    sched_fence();
+                    const floatx4 a2 = a2p[qq % 3], a1 = a1p[qq % 3];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        num = mfma4(wn[j][4 * qq + i], a2[i], num);
+                        den = mfma4(wn[j][4 * qq + i], a1[i], den);
+                    }
                 }
-                sched_fence();
-                const floatx4 a2 = a2p[qq % 3], a1 = a1p[qq % 3];
+            } else {
+                *reinterpret_cast<v4h *>(&rl16[w][0][n][4 * q]) = pack4<PREC>(r2[0], r2[1], r2[2], r2[3]);
+                *reinterpret_cast<v4h *>(&rl16[w][1][n][4 * q]) = pack4<PREC>(r1[0], r1[1], r1[2], r1[3]);
+                wave_lds_sync();
+                v4h a2p[3], a1p[3];
+                a2p[0] = *reinterpret_cast<const v4h *>(&rl16[w][0][n][0]);
+                a1p[0] = *reinterpret_cast<const v4h *>(&rl16[w][1][n][0]);
+                a2p[1] = *reinterpret_cast<const v4h *>(&rl16[w][0][n][4]);
+                a1p[1] = *reinterpret_cast<const v4h *>(&rl16[w][1][n][4]);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    num = mfma4(wn[j][4 * qq + i], a2[i], num);
-                    den = mfma4(wn[j][4 * qq + i], a1[i], den);
+                for (int qq = 0; qq < CHUNK / 4; ++qq) {
+                    if (qq + 2 < CHUNK / 4) {
+                        a2p[(qq + 2) % 3] = *reinterpret_cast<const v4h *>(&rl16[w][0][n][4 * qq + 8]);
+                        a1p[(qq + 2) % 3] = *reinterpret_cast<const v4h *>(&rl16[w][1][n][4 * qq + 8]);
+                    }
+                    sched_fence();
+                    num = mfma16b<PREC>(wn16[j][qq], a2p[qq % 3], num);
+                    den = mfma16b<PREC>(wn16[j][qq], a1p[qq % 3], den);
                 }
             }
             wave_lds_sync();
@@ -250,8 +353,7 @@ __global__ __launch_bounds__(NW * 64) void fused_fit_kernel(FusedArgs a) {
                     guard = 1;
             }
         }
-        if (4 * q < KMAX)
-            *reinterpret_cast<floatx4 *>(&hs[w][n][4 * q]) = floatx4{hu[0], hu[1], hu[2], hu[3]};
+        store_h();
         wave_lds_sync();
     }
 
@@ -347,21 +449,31 @@ Plan plan_for(int F) {
     return p;
 }
 
-template <int NW, int KMAX>
+template <int NW, int KMAX, int PREC>
 hipError_t launch_t(const FusedArgs &a, int grid, hipStream_t s) {
-    fused_fit_kernel<NW, 1, KMAX><<<grid, NW * 64, 0, s>>>(a);
+    fused_fit_kernel<NW, 1, KMAX, PREC><<<grid, NW * 64, 0, s>>>(a);
     return hipGetLastError();
 }
 
-template <int NW>
+template <int NW, int PREC>
 hipError_t launch_k(const FusedArgs &a, int grid, hipStream_t s) {
-    if (a.K <= 8) return launch_t<NW, 8>(a, grid, s);
-    if (a.K <= 16) return launch_t<NW, 16>(a, grid, s);
-    if (a.K <= 24) return launch_t<NW, 24>(a, grid, s);
-    if (a.K <= 32) return launch_t<NW, 32>(a, grid, s);
-    if (a.K <= 40) return launch_t<NW, 40>(a, grid, s);
-    if (a.K <= 52) return launch_t<NW, 52>(a, grid, s);
-    return launch_t<NW, 64>(a, grid, s);
+    if (a.K <= 8) return launch_t<NW, 8, PREC>(a, grid, s);
+    if (a.K <= 16) return launch_t<NW, 16, PREC>(a, grid, s);
+    if (a.K <= 24) return launch_t<NW, 24, PREC>(a, grid, s);
+    if (a.K <= 32) return launch_t<NW, 32, PREC>(a, grid, s);
+    if (a.K <= 40) return launch_t<NW, 40, PREC>(a, grid, s);
+    if (a.K <= 52) return launch_t<NW, 52, PREC>(a, grid, s);
+    return launch_t<NW, 64, PREC>(a, grid, s);
+}
+
+template <int PREC>
+hipError_t launch_p(const FusedArgs &a, int nw, int grid, hipStream_t s) {
+    switch (nw) {
+        case 1: return launch_k<1, PREC>(a, grid, s);
+        case 2: return launch_k<2, PREC>(a, grid, s);
+        case 4: return launch_k<4, PREC>(a, grid, s);
+        default: return launch_k<8, PREC>(a, grid, s);
+    }
 }
 
 }  // namespace
@@ -373,7 +485,7 @@ bool fused_supported(int F, int K) {
 }
 
 hipError_t launch_fused_fit(const OnlineDev &d, const float *V, int ldv, int b, int iters,
-                            double eps, int warm, float *Hb, int ldh, hipStream_t s) {
+                            double eps, int warm, float *Hb, int ldh, int prec, hipStream_t s) {
     if (!fused_supported(d.F, d.K)) return hipErrorNotSupported;
     const Plan p = plan_for(d.F);
     FusedArgs a;
@@ -398,13 +510,13 @@ hipError_t launch_fused_fit(const OnlineDev &d, const float *V, int ldv, int b, 
     a.R2 = (float *)d.R2;
     a.lossf = d.lossf;
     a.flags = d.flags;
+    const int sexp = (int)lrint(log2((double)d.F));
+    a.wscale = ldexpf(1.f, sexp);
+    a.hscale = ldexpf(1.f, -sexp);
     const int grid = (b + NF - 1) / NF;
-    switch (p.nw) {
-        case 1: return launch_k<1>(a, grid, s);
-        case 2: return launch_k<2>(a, grid, s);
-        case 4: return launch_k<4>(a, grid, s);
-        default: return launch_k<8>(a, grid, s);
-    }
+    if (prec == 1) return launch_p<1>(a, p.nw, grid, s);
+    if (prec == 2) return launch_p<2>(a, p.nw, grid, s);
+    return launch_p<0>(a, p.nw, grid, s);
 }
 
 }  // namespace isnmf

@@ -1,0 +1,95 @@
+"""Precision forms (BF16 / FP16 products, FP32 ratios, FP64 statistics)
+against the FP64 oracle.
+
+Gate (the stated accuracy of the forms): the online loss over a pass and the
+final objective within rel 1e-3 of the oracle.  Per-step errors of W, A, B
+are reported (printed) and bounded loosely (2e-2), not gated at 1e-5.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1106_4198_amd import synth
+from tests.helpers import from_gpu_kf, rel_fro, to_gpu_kf
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1106_4198_amd import binding as bd  # noqa: E402
+
+DEV = "cuda"
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+@pytest.mark.parametrize("F,K,b", [(513, 50, 128), (129, 8, 16), (257, 64, 33), (70, 5, 6)])
+def test_one_step_error_is_small(precision, F, K, b):
+    say(f"precision step {precision} F={F} K={K} b={b}")
+    V, W0 = synth.problem(F, K, 3 * b, seed=5)
+    st = oracle.OnlineState(W0.astype(np.float64))
+    st.step(V[:, :b].astype(np.float64), iters=20)
+    st.step(V[:, b:2 * b].astype(np.float64), iters=20)
+    g = bd.OnlineISNMF(to_gpu_kf(st.W, np.float32, torch), b, precision=precision,
+                       A0=to_gpu_kf(st.A, np.float64, torch), B0=to_gpu_kf(st.B, np.float64, torch))
+    assert g.kernel_used == "fused"
+    g.set_w64(to_gpu_kf(st.W, np.float64, torch))
+    Vb = V[:, 2 * b:3 * b]
+    loss = torch.zeros((), dtype=torch.float64, device=DEV)
+    g.step(torch.from_numpy(np.ascontiguousarray(Vb.T)).to(DEV), None, loss)
+    st.step(Vb.astype(np.float64), iters=20)
+    eW = rel_fro(from_gpu_kf(g.get_w64()), st.W)
+    _, A, B, _ = g.get()
+    eA = rel_fro(from_gpu_kf(A), st.A)
+    eB = rel_fro(from_gpu_kf(B), st.B)
+    el = abs(loss.item() - st.last_loss) / st.last_loss
+    print(f"[precision] {precision} F={F} K={K} b={b}: W {eW:.2e} A {eA:.2e} B {eB:.2e} loss {el:.2e}")
+    assert eW < 2e-2 and eA < 2e-2 and eB < 2e-2
+    assert el < 1e-3
+    assert g.status() == 0
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16", "fp32"])
+def test_pass_accuracy_matches_stated_tolerance(precision):
+    """F=513, K=50, b=128, I=20 over 24 minibatches (a prefix of the benchmark
+    stream), with checkpoints of the relative error of W, A, B and the online
+    loss against the FP64 oracle."""
+    F, K, b, I, steps = 513, 50, 128, 20, 24
+    say(f"precision pass {precision}")
+    V, W0 = synth.problem(F, K, steps * b, seed=2011)
+    st = oracle.OnlineState(W0.astype(np.float64))
+    oracle.set_threads(8)
+    g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b,
+                       precision=precision, inner_iters=I)
+    Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+    loss = torch.zeros((), dtype=torch.float64, device=DEV)
+    report = []
+    for s in range(steps):
+        g.step(Vt[s * b:(s + 1) * b], None, loss)
+        st.step(V[:, s * b:(s + 1) * b].astype(np.float64), iters=I)
+        if s + 1 in (1, 4, 12, 24):
+            _, A, B, _ = g.get()
+            report.append((s + 1, rel_fro(from_gpu_kf(g.get_w64()), st.W),
+                           rel_fro(from_gpu_kf(A), st.A), rel_fro(from_gpu_kf(B), st.B),
+                           abs(loss.item() - st.loss_sum) / st.loss_sum))
+    oracle.set_threads(1)
+    for r in report:
+        print(f"[precision] {precision} step {r[0]:3d}: W {r[1]:.2e} A {r[2]:.2e} B {r[3]:.2e} loss {r[4]:.2e}")
+    assert report[-1][4] < 1e-3            # online loss (eq. 5) over the pass
+    # final objective of the learned dictionary on the pass's frames, refit by the oracle
+    W = from_gpu_kf(g.get_w64())
+    idx = range(0, steps * b, 97)
+    Hg = np.column_stack([oracle.fit_h(V[:, n].astype(np.float64), W, iters=I)[0] for n in idx])
+    Hr = np.column_stack([oracle.fit_h(V[:, n].astype(np.float64), st.W, iters=I)[0] for n in idx])
+    og = oracle.objective(V[:, ::97].astype(np.float64), W, Hg)
+    orf = oracle.objective(V[:, ::97].astype(np.float64), st.W, Hr)
+    print(f"[precision] {precision} final objective rel {abs(og - orf) / orf:.2e}")
+    assert abs(og - orf) <= 1e-3 * orf
