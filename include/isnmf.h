@@ -192,6 +192,68 @@ int isnmf_online_info(const isnmf_online *h, int *F, int *K, int *b_max, int *ke
 /* Free the handle (not the workspace). Waits for the handle's last stream. */
 int isnmf_online_destroy(isnmf_online *h);
 
+/* ------------------------------------------------------------ batched form */
+
+/*
+ * Many independent online streams advanced together: each step fits one
+ * minibatch of every stream that has frames left (fresh restarts), folds it
+ * into that stream's A and B and updates its W -- exactly
+ * isnmf_online_step on each handle, with one fit launch per kernel variant
+ * in use and one fold and one rescale launch for all streams.  The frame
+ * cursors live on the device, so a step can be captured into a hipGraph and
+ * replayed (isnmf_multi_run with use_graph).
+ *
+ * handles: S distinct online handles (FUSED kernel, ISNMF_H_ONES), owned by
+ *   the caller and not stepped otherwise while the plan is in use.
+ * V[s]: device F_s x n_frames[s] FP32 (ldv[s] >= F_s) -- stream s's frames,
+ *   consumed in order, b[s] per step (1 <= b[s] <= min(b_max_s, 512)).
+ * d_loss: NULL or device double[S]; stream s's minibatch losses are added.
+ * workspace: device memory of isnmf_multi_workspace_size() bytes, 256-byte
+ *   aligned, caller-owned.  The per-stream descriptors are copied in at
+ *   creation (the call synchronizes `stream`).
+ */
+typedef struct isnmf_multi isnmf_multi;
+
+size_t isnmf_multi_workspace_size(isnmf_online *const *handles, int S, const int *b);
+
+int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
+                       const float *const *V, const int *ldv, const long long *n_frames,
+                       const int *b, double *d_loss, void *workspace, size_t ws_bytes,
+                       void *stream);
+
+/* One step for every stream with frames left.  The handles' frame counters
+ * advance on the host. */
+int isnmf_multi_step(isnmf_multi *m, void *stream);
+
+/* `steps` steps; use_graph != 0 captures one step into a hipGraph on first
+ * use (on a private stream) and replays it on `stream`. */
+int isnmf_multi_run(isnmf_multi *m, int steps, int use_graph, void *stream);
+
+/* Largest number of frames any stream has left (host bookkeeping). */
+int isnmf_multi_frames_left(const isnmf_multi *m, long long *host_max_left);
+
+int isnmf_multi_destroy(isnmf_multi *m);
+
+/* ------------------------------------------------------------- autotuner */
+
+/*
+ * Time every fused-fit kernel variant valid for (F, K, precision) on
+ * synthetic frames (b per launch, `trials` launches each) and record the
+ * fastest in the process-wide tuning table; handles created afterwards with
+ * that shape use it.  Allocates scratch device memory itself and
+ * synchronizes `stream`.  out_variant: index of the chosen variant (0 is the
+ * default); out_us: its average launch time in microseconds.
+ */
+int isnmf_autotune(int F, int K, int b, const isnmf_params *p, int trials, int *out_variant,
+                   double *out_us, void *stream);
+
+/* Read / set / clear the tuning table (for persisting it between processes):
+ * nw = waves per workgroup, cpw = 64-row chunks per wave, wg = W read from
+ * its 16-bit copies in memory instead of registers. */
+int isnmf_tune_get(int F, int K, int precision, int *nw, int *cpw, int *wg);
+int isnmf_tune_set(int F, int K, int precision, int nw, int cpw, int wg);
+void isnmf_tune_clear(void);
+
 /* ------------------------------------------------------------------- batch */
 
 /* Bytes of device workspace isnmf_batch_mu needs. */

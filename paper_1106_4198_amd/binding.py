@@ -63,6 +63,18 @@ def _load():
         "isnmf_online_fit": (i, [vp, vp, i, i, vp, i, vp, vp]),
         "isnmf_online_set_timing": (i, [vp, i, i]),
         "isnmf_online_timing": (i, [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(d)]),
+        "isnmf_multi_workspace_size": (sz, [ctypes.POINTER(vp), i, ctypes.POINTER(i)]),
+        "isnmf_multi_create": (i, [ctypes.POINTER(vp), ctypes.POINTER(vp), i, ctypes.POINTER(vp),
+                                   ctypes.POINTER(i), ctypes.POINTER(ctypes.c_longlong),
+                                   ctypes.POINTER(i), vp, vp, sz, vp]),
+        "isnmf_multi_step": (i, [vp, vp]),
+        "isnmf_multi_run": (i, [vp, i, i, vp]),
+        "isnmf_multi_frames_left": (i, [vp, ctypes.POINTER(ctypes.c_longlong)]),
+        "isnmf_multi_destroy": (i, [vp]),
+        "isnmf_autotune": (i, [i, i, i, P, i, ctypes.POINTER(i), ctypes.POINTER(d), vp]),
+        "isnmf_tune_get": (i, [i, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
+        "isnmf_tune_set": (i, [i, i, i, i, i, i]),
+        "isnmf_tune_clear": (None, []),
         "isnmf_batch_workspace_size": (sz, [i, i, i, P]),
         "isnmf_batch_mu": (i, [vp, i, i, i, vp, i, vp, i, i, i, P, vp, vp, sz, vp]),
         "isnmf_objective_workspace_size": (sz, [i, i, i]),
@@ -81,6 +93,9 @@ EXPORTED = ("isnmf_params_default", "isnmf_strerror", "isnmf_online_workspace_si
             "isnmf_online_set", "isnmf_online_set_w64", "isnmf_online_status", "isnmf_online_info",
             "isnmf_online_destroy", "isnmf_online_pass", "isnmf_online_fit",
             "isnmf_online_set_timing", "isnmf_online_timing",
+            "isnmf_multi_workspace_size", "isnmf_multi_create", "isnmf_multi_step",
+            "isnmf_multi_run", "isnmf_multi_frames_left", "isnmf_multi_destroy",
+            "isnmf_autotune", "isnmf_tune_get", "isnmf_tune_set", "isnmf_tune_clear",
             "isnmf_batch_workspace_size", "isnmf_batch_mu",
             "isnmf_objective_workspace_size", "isnmf_objective")
 
@@ -262,6 +277,106 @@ class OnlineISNMF:
             self.close()
         except Exception:
             pass
+
+
+class MultiISNMF:
+    """Batched form: several OnlineISNMF streams advanced one minibatch per step
+    in shared launches (optionally one replayed hipGraph per step)."""
+
+    def __init__(self, streams, V, b, loss=True, stream=None):
+        S = len(streams)
+        if S < 1 or len(V) != S or len(b) != S:
+            raise ValueError("need one V and one b per stream")
+        for g, v in zip(streams, V):
+            _req(v, torch.float32, name="V")
+            if v.shape[1] != g.F:
+                raise ValueError("frame length != F")
+        self.streams = list(streams)
+        self.V = list(V)
+        H = (ctypes.c_void_p * S)(*[g._h for g in streams])
+        Vp = (ctypes.c_void_p * S)(*[v.data_ptr() for v in V])
+        ld = (ctypes.c_int * S)(*[_ld(v) for v in V])
+        nf = (ctypes.c_longlong * S)(*[v.shape[0] for v in V])
+        bb = (ctypes.c_int * S)(*[int(x) for x in b])
+        dev = V[0].device
+        self.loss = torch.zeros(S, dtype=torch.float64, device=dev) if loss else None
+        nbytes = _lib.isnmf_multi_workspace_size(H, S, bb)
+        if nbytes == 0:
+            raise IsnmfError(EINVAL, "isnmf_multi_workspace_size")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        m = ctypes.c_void_p()
+        _check(_lib.isnmf_multi_create(ctypes.byref(m), H, S, Vp, ld, nf, bb, _ptr(self.loss),
+                                       _ptr(self.workspace), nbytes, _stream(stream)),
+               "isnmf_multi_create")
+        self._m = m
+
+    def step(self, stream=None):
+        _check(_lib.isnmf_multi_step(self._m, _stream(stream)), "isnmf_multi_step")
+
+    def run(self, steps: int, graph: bool = True, stream=None):
+        _check(_lib.isnmf_multi_run(self._m, int(steps), int(bool(graph)), _stream(stream)),
+               "isnmf_multi_run")
+
+    def frames_left(self) -> int:
+        n = ctypes.c_longlong()
+        _check(_lib.isnmf_multi_frames_left(self._m, ctypes.byref(n)), "frames_left")
+        return n.value
+
+    def close(self):
+        if getattr(self, "_m", None):
+            _lib.isnmf_multi_destroy(self._m)
+            self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(F: int, K: int, b: int, precision="bf16", inner_iters=20, trials=5, stream=None):
+    """Time the fit kernel variants for this shape; the fastest is used by
+    handles created afterwards.  Returns (variant index, microseconds)."""
+    p = make_params(inner_iters=inner_iters, precision=precision)
+    v = ctypes.c_int()
+    us = ctypes.c_double()
+    _check(_lib.isnmf_autotune(int(F), int(K), int(b), ctypes.byref(p), int(trials),
+                               ctypes.byref(v), ctypes.byref(us), _stream(stream)), "isnmf_autotune")
+    return v.value, us.value
+
+
+def tune_get(F: int, K: int, precision="bf16"):
+    nw, cpw, wg = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(_lib.isnmf_tune_get(int(F), int(K), PREC[precision], ctypes.byref(nw), ctypes.byref(cpw),
+                               ctypes.byref(wg)), "isnmf_tune_get")
+    return nw.value, cpw.value, wg.value
+
+
+def tune_set(F: int, K: int, precision: str, nw: int, cpw: int, wg: int):
+    _check(_lib.isnmf_tune_set(int(F), int(K), PREC[precision], int(nw), int(cpw), int(wg)),
+           "isnmf_tune_set")
+
+
+def tune_clear():
+    _lib.isnmf_tune_clear()
+
+
+def save_tuning(path: str, shapes):
+    """Write the tuning table entries for `shapes` [(F, K, precision)] as JSON."""
+    import json
+    rows = []
+    for F, K, pr in shapes:
+        nw, cpw, wg = tune_get(F, K, pr)
+        rows.append({"F": F, "K": K, "precision": pr, "nw": nw, "cpw": cpw, "wg": wg})
+    with open(path, "w") as f:
+        json.dump(rows, f, indent=1)
+
+
+def load_tuning(path: str):
+    import json
+    with open(path) as f:
+        for r in json.load(f):
+            tune_set(r["F"], r["K"], r["precision"], r["nw"], r["cpw"], r["wg"])
 
 
 def batch_mu(V: torch.Tensor, W: torch.Tensor, H: torch.Tensor, cycles: int, *, eps=1e-12,

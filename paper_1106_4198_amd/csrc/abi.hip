@@ -17,7 +17,7 @@ struct isnmf_online {
     long long t;
     hipStream_t last;
     int kernel_used;
-    int w16_kind;  // 0 none, 1 bf16, 2 fp16
+    FitClass cls;   // fused fit variant (tuned or default)
     // per-launch timing of the fit kernel (isnmf_online_set_timing)
     bool timing = false;
     std::vector<hipEvent_t> ev0, ev1;
@@ -27,6 +27,11 @@ struct isnmf_online {
 namespace {
 
 int elem_size(const isnmf_params &p) { return p.precision == ISNMF_FP64 ? 8 : 4; }
+
+// Product precision of the fused kernels: 0 FP32, 1 BF16, 2 FP16.
+int prec_code(const isnmf_params &p) {
+    return p.precision == ISNMF_BF16 ? 1 : p.precision == ISNMF_FP16 ? 2 : 0;
+}
 
 bool params_ok(const isnmf_params &p) {
     if (!(p.eps >= 0.0) || !isfinite(p.eps)) return false;
@@ -69,7 +74,10 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
     t.counter = (unsigned *)take(sizeof(unsigned));
     t.W64 = (double *)take(fk * 8);
     t.W32 = (float *)take(fk * 4);
-    t.W16 = (uint16_t *)take(fk * 2);
+    t.W16r = (uint16_t *)take((size_t)F * KP * 2);
+    t.W16c = (uint16_t *)take((size_t)K * FR * 2);
+    t.w16_kind = prec_code(p);
+    t.wexp = (int)lrint(log2((double)F));
     t.A = (double *)take(fk * 8);
     t.B = (double *)take(fk * 8);
     t.Wn = (double *)take(fk * 8);
@@ -89,7 +97,19 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
 int use_fused(const isnmf_params &p, int F, int K) {
     if (p.precision == ISNMF_FP64) return 0;
     if (p.kernel == ISNMF_KERNEL_PLAIN) return 0;
-    return fused_supported(F, K) ? 1 : 0;
+    return fused_supported(F, K, prec_code(p)) ? 1 : 0;
+}
+
+// Zero the 16-bit copies once (their padding rows/columns are never written),
+// then write W into every copy.
+hipError_t init_w(const OnlineDev &d, const float *W, int ldw, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (d.w16_kind) {
+        e = hipMemsetAsync(d.W16r, 0, (size_t)d.F * d.KP * 2, s);
+        if (e == hipSuccess) e = hipMemsetAsync(d.W16c, 0, (size_t)d.K * d.FR * 2, s);
+    }
+    if (e == hipSuccess) e = launch_set_w(d, W, ldw, nullptr, s);
+    return e;
 }
 
 // 16-bit product forms exist only as fused kernels.
@@ -104,8 +124,7 @@ int run_fit(isnmf_online *h, const float *V, int ldv, int b, int iters, int warm
     if (p.precision == ISNMF_FP64)
         e = launch_plain_fit<double>(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
     else if (h->kernel_used == ISNMF_KERNEL_FUSED)
-        e = launch_fused_fit(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh,
-                             p.precision == ISNMF_BF16 ? 1 : p.precision == ISNMF_FP16 ? 2 : 0, s);
+        e = launch_fused_fit(h->d, h->cls, V, ldv, b, iters, p.eps, warm, Hb, ldh, prec_code(p), s);
     else
         e = launch_plain_fit<float>(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
     if (e != hipSuccess) return ISNMF_EDEVICE;
@@ -128,7 +147,7 @@ int run_update(isnmf_online *h, int b, double rho, int update_w, int normalize, 
         if (e == hipSuccess && d_loss_sum) e = launch_loss_total(h->d.lossf, b, d_loss_sum, s);
     }
     if (e == hipSuccess)
-        e = launch_rescale(h->d, b, update_w, normalize, warm, Hb, ldh, d_dw, h->w16_kind, s);
+        e = launch_rescale(h->d, b, update_w, normalize, warm, Hb, ldh, d_dw, s);
     return e == hipSuccess ? ISNMF_OK : ISNMF_EDEVICE;
 }
 
@@ -141,6 +160,16 @@ void free_events(isnmf_online *h) {
 }
 
 }  // namespace
+
+// Accessors used by the batched form (multi.hip).
+const OnlineDev *isnmf_handle_dev(const isnmf_online *h) { return &h->d; }
+const FitClass *isnmf_handle_class(const isnmf_online *h) { return &h->cls; }
+const isnmf_params *isnmf_handle_params(const isnmf_online *h) { return &h->p; }
+int isnmf_handle_kernel(const isnmf_online *h) { return h->kernel_used; }
+void isnmf_handle_advance(isnmf_online *h, long long frames, hipStream_t s) {
+    h->t += frames;
+    h->last = s;
+}
 
 extern "C" {
 
@@ -196,13 +225,13 @@ int isnmf_online_init(isnmf_online **out, int F, int K, int b_max, const isnmf_p
     h->t = 0;
     h->last = (hipStream_t)stream;
     h->kernel_used = use_fused(p, F, K) ? ISNMF_KERNEL_FUSED : ISNMF_KERNEL_PLAIN;
-    h->w16_kind = 0;
+    h->cls = tuned_class(F, K, prec_code(p), b_max);
     hipStream_t s = (hipStream_t)stream;
     const size_t fk8 = sizeof(double) * (size_t)F * K;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemsetAsync(h->d.flags, 0, sizeof(int), s);
     if (e == hipSuccess) e = hipMemsetAsync(h->d.counter, 0, sizeof(unsigned), s);
-    if (e == hipSuccess) e = launch_set_w(h->d, W0, ldw, nullptr, h->w16_kind, s);
+    if (e == hipSuccess) e = init_w(h->d, W0, ldw, s);
     if (e == hipSuccess)
         e = A0 ? hipMemcpyAsync(h->d.A, A0, fk8, hipMemcpyDeviceToDevice, s)
                : hipMemsetAsync(h->d.A, 0, fk8, s);
@@ -339,7 +368,7 @@ int isnmf_online_set(isnmf_online *h, const float *W, const double *A, const dou
     hipStream_t s = (hipStream_t)stream;
     const size_t fk = (size_t)h->d.F * h->d.K;
     hipError_t e = hipSuccess;
-    if (W) e = launch_set_w(h->d, W, h->d.F, nullptr, h->w16_kind, s);
+    if (W) e = launch_set_w(h->d, W, h->d.F, nullptr, s);
     if (A && e == hipSuccess) e = hipMemcpyAsync(h->d.A, A, fk * 8, hipMemcpyDeviceToDevice, s);
     if (B && e == hipSuccess) e = hipMemcpyAsync(h->d.B, B, fk * 8, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return ISNMF_EDEVICE;
@@ -351,7 +380,7 @@ int isnmf_online_set(isnmf_online *h, const float *W, const double *A, const dou
 int isnmf_online_set_w64(isnmf_online *h, const double *W, void *stream) {
     if (!h || !W) return ISNMF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    if (launch_set_w(h->d, nullptr, h->d.F, W, h->w16_kind, s) != hipSuccess) return ISNMF_EDEVICE;
+    if (launch_set_w(h->d, nullptr, h->d.F, W, s) != hipSuccess) return ISNMF_EDEVICE;
     h->last = s;
     return ISNMF_OK;
 }
@@ -413,12 +442,12 @@ int isnmf_batch_mu(const float *V, int ldv, int F, int N, float *W, int ldw, flo
     h.p.h_init = ISNMF_H_WARM;
     h.p.update_w = 1;
     h.t = 0;
-    h.w16_kind = 0;
     h.kernel_used = use_fused(p, F, K) ? ISNMF_KERNEL_FUSED : ISNMF_KERNEL_PLAIN;
+    h.cls = fit_class(F, K, prec_code(p));
     hipStream_t s = (hipStream_t)stream;
     if (hipMemsetAsync(h.d.flags, 0, sizeof(int), s) != hipSuccess) return ISNMF_EDEVICE;
     if (hipMemsetAsync(h.d.counter, 0, sizeof(unsigned), s) != hipSuccess) return ISNMF_EDEVICE;
-    if (launch_set_w(h.d, W, ldw, nullptr, 0, s) != hipSuccess) return ISNMF_EDEVICE;
+    if (init_w(h.d, W, ldw, s) != hipSuccess) return ISNMF_EDEVICE;
     for (int c = 0; c < cycles; ++c) {
         int st = run_fit(&h, V, ldv, N, 1, 1, H, ldh, s);
         if (st != ISNMF_OK) return st;

@@ -36,7 +36,10 @@ struct OnlineDev {
     int KP;              // padded row stride of the internal H buffer
     double *W64;         // F x K, ld F: master W (FP64)
     float *W32;          // F x K, ld F: working copy (FP32)
-    uint16_t *W16;       // F x K, ld F: BF16/FP16 copy (precision forms)
+    uint16_t *W16r;      // F x KP row-major: W * 2^wexp in BF16/FP16 (precision forms)
+    uint16_t *W16c;      // K x FR (column k at k*FR): the same values, column-major
+    int w16_kind;        // 0 none, 1 BF16, 2 FP16
+    int wexp;            // s = round(log2 F): 16-bit copies hold W * 2^s
     double *A, *B;       // F x K, ld F
     double *Wn;          // F x K: sqrt(A/B) before rescaling
     double *dwpart;      // K: per-column sum of squared change of W
@@ -50,6 +53,43 @@ struct OnlineDev {
     unsigned *counter;   // spare device word (zeroed at init)
 };
 
+// One stream's fit problem for the fused kernels (by value for a single
+// stream, an array in device memory for the batched form).
+struct FitDesc {
+    int F, K, b, ldv, ldh, iters, warm;
+    int main_chunks;   // chunks of 64 rows on MFMA (the last may be partial)
+    int tail;          // rows after them on the VALU (<= TAIL_MAX)
+    int FR, KP;
+    float eps, wscale, hscale;
+    double epsd;
+    const float *V;            // frame 0 of the minibatch
+    const float *W;            // F x K, ld F (FP32 working copy)
+    const uint16_t *W16r;      // F x KP, 16-bit W * wscale
+    const uint16_t *W16c;      // K x FR, 16-bit W * wscale
+    float *Hb;                 // caller's K x b (warm start in / fitted h out) or null
+    float *Hi;                 // b x KP internal copy of the fitted h
+    float *R1, *R2;            // b x FR
+    double *lossf;             // b
+    int *flags;
+};
+
+// Kernel variant of the fused fit for a shape (see fit_body.h).
+struct FitClass {
+    int ok;
+    int nw, cpw, kmax, wg;
+    int main_chunks, tail;
+};
+FitClass fit_class(int F, int K, int prec);
+FitDesc make_fit_desc(const OnlineDev &d, const float *V, int ldv, int b, int iters, double eps,
+                      int warm, float *Hb, int ldh);
+
+// Single-stream and batched launches of one fit class, per product precision.
+template <int PREC>
+hipError_t launch_fit_single_p(const FitDesc &a, const FitClass &c, int grid, hipStream_t s);
+template <int PREC>
+hipError_t launch_fit_multi_p(const FitClass &c, const FitDesc *descs, const int2 *items,
+                              int nitems, const long long *cursor, const int *beff, hipStream_t s);
+
 // ---------------------------------------------------------------- launchers
 
 // Plain (unfused) fit of all frames of a minibatch; T = float or double.
@@ -60,9 +100,14 @@ hipError_t launch_plain_fit(const OnlineDev &d, const float *V, int ldv, int b, 
 
 // Fused MFMA fit; prec 0 = FP32, 1 = BF16, 2 = FP16 products.  Returns
 // hipErrorNotSupported for shapes it does not cover.
-hipError_t launch_fused_fit(const OnlineDev &d, const float *V, int ldv, int b, int iters,
-                            double eps, int warm, float *Hb, int ldh, int prec, hipStream_t s);
-bool fused_supported(int F, int K);
+hipError_t launch_fused_fit(const OnlineDev &d, const FitClass &c, const float *V, int ldv, int b,
+                            int iters, double eps, int warm, float *Hb, int ldh, int prec,
+                            hipStream_t s);
+bool fused_supported(int F, int K, int prec);
+// Every fit variant valid for the shape (the default first); returns the count.
+int fit_candidates(int F, int K, int prec, FitClass *out, int max_out);
+// The variant the autotuner chose for (F, K, prec, b), or the default.
+FitClass tuned_class(int F, int K, int prec, int b);
 
 // Fold the minibatch into A, B and (optionally) form sqrt(A/B).
 // Rin/Hin element type: float (is_double = 0) or double (1).
@@ -78,14 +123,14 @@ size_t fold_partial_bytes(int F, int K, int b);
 // Column rescale (when update_w), W copies, warm-H compensation; d_dw (if
 // not null) receives ||W_new - W_old||_F.
 hipError_t launch_rescale(const OnlineDev &d, int b, int update_w, int normalize, int warm,
-                          float *Hb, int ldh, double *d_dw, int w16_kind, hipStream_t s);
+                          float *Hb, int ldh, double *d_dw, hipStream_t s);
 
 // *d_loss_sum += sum of lossf[0..b) in index order (one block).
 hipError_t launch_loss_total(const double *lossf, int b, double *d_loss_sum, hipStream_t s);
 
 // Copy helpers.
 hipError_t launch_set_w(const OnlineDev &d, const float *W, int ldw, const double *W64,
-                        int w16_kind, hipStream_t s);
+                        hipStream_t s);
 hipError_t launch_get_w(const OnlineDev &d, float *W, hipStream_t s);
 
 // Objective of eq. (1): per-frame sums into frame_out (double, N entries) then a

@@ -14,114 +14,15 @@
 // Minibatches longer than SLICE frames are cut into slices whose FP32 partial
 // tiles are summed in slice order (FP64) by a second kernel.
 #include "common.h"
+#include "fold_body.h"
 
 namespace isnmf {
 namespace {
 
-constexpr int SLICE = 512;
-
-struct FoldArgs {
-    int F, K, b, FR, KP;
-    const float *R1, *R2, *H;
-    const double *W64;
-    double *A, *B, *Wn;
-    double rho;
-    int update_w;
-    int tiles_f;           // ceil(F / 16)
-    float *part;           // slices x 2 x F x K partials (multi-slice only)
-    const double *lossf;   // frame losses of the minibatch (may be null)
-    double *d_loss_sum;    // += sum of lossf (may be null)
-    int *flags;
-};
-
-__device__ inline floatx4 mfma16(float a, float b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-__device__ inline void epilogue(const FoldArgs &a, int f, int k, double sa, double sb) {
-    const size_t e = (size_t)f + (size_t)k * a.F;
-    const double w = a.W64[e];
-    const double av = a.rho * a.A[e] + sa * (w * w);
-    const double bv = a.rho * a.B[e] + sb;
-    a.A[e] = av;
-    a.B[e] = bv;
-    if (a.update_w) {
-        double wn = w;
-        if (bv > 0.0 && av >= 0.0)
-            wn = sqrt(av / bv);
-        else
-            atomicOr(a.flags, FLAG_GUARD_W);
-        a.Wn[e] = wn;
-    }
-}
-
-// grid.x = tiles, grid.y = slices; 4 waves per tile, frame groups of 4
-// dealt round-robin to the waves, partial tiles summed in wave order.
 __global__ __launch_bounds__(256) void fold_mfma_kernel(FoldArgs a) {
-    __shared__ floatx4 red[4][2][64];
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int tile = blockIdx.x;
-    const int f0 = (tile % a.tiles_f) * 16;
-    const int k0 = (tile / a.tiles_f) * 16;
-    const int slice = blockIdx.y;
-    const int n_lo = slice * SLICE;
-    const int n_hi = min(a.b, n_lo + SLICE);
-    const int fa = f0 + (lane & 15);       // A operand row
-    const int kb = k0 + (lane & 15);       // B operand column
-    const int sub = lane >> 4;             // frame within the group of 4
-    const bool fok = fa < a.F, kok = kb < a.K;
-
-    if (a.d_loss_sum && tile == 0 && slice == 0 && threadIdx.x == 0) {
-        double s = 0.0;
-        for (int n = 0; n < a.b; ++n) s += a.lossf[n];
-        *a.d_loss_sum += s;
-    }
-
-    floatx4 ca = {0.f, 0.f, 0.f, 0.f}, cb = {0.f, 0.f, 0.f, 0.f};
-    // rounds of 8 groups per wave: every load of a round is issued before its MFMAs
-    for (int g0 = n_lo + 4 * w; g0 < n_hi; g0 += 4 * 4 * 8) {
-        float r2[8], r1[8], hh[8];
-#pragma unroll
-        for (int g = 0; g < 8; ++g) {
-            const int n = g0 + 16 * g + sub;
-            const bool ok = n < n_hi;
-            r2[g] = (ok && fok) ? a.R2[(size_t)n * a.FR + fa] : 0.f;
-            r1[g] = (ok && fok) ? a.R1[(size_t)n * a.FR + fa] : 0.f;
-            hh[g] = (ok && kok) ? a.H[(size_t)n * a.KP + kb] : 0.f;
-        }
-#pragma unroll
-        for (int g = 0; g < 8; ++g) {
-            ca = mfma16(r2[g], hh[g], ca);
-            cb = mfma16(r1[g], hh[g], cb);
-        }
-    }
-    red[w][0][lane] = ca;
-    red[w][1][lane] = cb;
-    __syncthreads();
-    if (w != 0) return;
-    ca = ((red[0][0][lane] + red[1][0][lane]) + red[2][0][lane]) + red[3][0][lane];
-    cb = ((red[0][1][lane] + red[1][1][lane]) + red[2][1][lane]) + red[3][1][lane];
-    const int kc = k0 + (lane & 15);
-    if (gridDim.y == 1) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int f = f0 + 4 * sub + r;
-            if (f < a.F && kc < a.K) epilogue(a, f, kc, double(ca[r]), double(cb[r]));
-        }
-    } else {
-        const size_t fk = (size_t)a.F * a.K;
-        float *pa = a.part + (size_t)slice * 2 * fk;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int f = f0 + 4 * sub + r;
-            if (f < a.F && kc < a.K) {
-                pa[f + (size_t)kc * a.F] = ca[r];
-                pa[fk + f + (size_t)kc * a.F] = cb[r];
-            }
-        }
-    }
+    fold_tile_body(a, blockIdx.x, blockIdx.y, gridDim.y);
 }
+
 
 // Multi-slice: sum the slice partials in slice order, then the epilogue.
 __global__ void fold_reduce_kernel(FoldArgs a, int slices) {
@@ -145,30 +46,10 @@ size_t fold_partial_bytes(int F, int K, int b) {
 
 hipError_t launch_fold_mfma(const OnlineDev &d, int b, double rho, int update_w, float *part,
                             double *d_loss_sum, hipStream_t s) {
-    FoldArgs a;
-    a.F = d.F;
-    a.K = d.K;
-    a.b = b;
-    a.FR = d.FR;
-    a.KP = d.KP;
-    a.R1 = (const float *)d.R1;
-    a.R2 = (const float *)d.R2;
-    a.H = (const float *)d.Hi;
-    a.W64 = d.W64;
-    a.A = d.A;
-    a.B = d.B;
-    a.Wn = d.Wn;
-    a.rho = rho;
-    a.update_w = update_w;
-    a.tiles_f = (d.F + 15) / 16;
-    a.part = part;
-    a.lossf = d.lossf;
-    a.d_loss_sum = d_loss_sum;
-    a.flags = d.flags;
-    const int tiles = a.tiles_f * ((d.K + 15) / 16);
+    FoldArgs a = fold_args(d, b, rho, update_w, part, d_loss_sum);
     const int slices = (b + SLICE - 1) / SLICE;
     if (slices > 1 && !part) return hipErrorInvalidValue;
-    fold_mfma_kernel<<<dim3(tiles, slices), 256, 0, s>>>(a);
+    fold_mfma_kernel<<<dim3(fold_tiles(d), slices), 256, 0, s>>>(a);
     if (slices > 1) {
         a.d_loss_sum = nullptr;
         const long fk = (long)d.F * d.K;

@@ -1,0 +1,482 @@
+// Batched form: many independent online streams (each its own W, A, B, F, K,
+// minibatch size) advanced by one minibatch per step with one fit launch per
+// kernel variant in use, one fold launch and one rescale launch for all
+// streams.  A step reads its per-stream frame cursors on the device, so it can
+// be captured once into a hipGraph and replayed.  Also the autotuner that picks
+// the fit variant for a shape.
+//
+// Each stream's arithmetic is exactly that of isnmf_online_step with the same
+// handle (same kernel bodies, same variant, fixed-order sums), so a stream's
+// result does not depend on which other streams share the launch.
+#include <math.h>
+
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "common.h"
+#include "fold_body.h"
+#include "state_body.h"
+
+using namespace isnmf;
+
+// ----------------------------------------------------------------- tuning cache
+
+namespace isnmf {
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, FitClass> g_tune;
+}  // namespace
+
+FitClass tuned_class(int F, int K, int prec, int /*b*/) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find({F, K, prec});
+    if (it != g_tune.end()) return it->second;
+    return fit_class(F, K, prec);
+}
+}  // namespace isnmf
+
+// ----------------------------------------------------------------- kernels
+
+namespace {
+
+__global__ void prepare_kernel(int S, const int *__restrict__ b, const long long *__restrict__ nf,
+                               const long long *__restrict__ cursor, int *__restrict__ beff) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const long long left = nf[s] - cursor[s];
+    beff[s] = left <= 0 ? 0 : (int)(left < b[s] ? left : b[s]);
+}
+
+__global__ void advance_kernel(int S, const int *__restrict__ beff, long long *__restrict__ cursor) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S) cursor[s] += beff[s];
+}
+
+__global__ __launch_bounds__(256) void fold_multi_kernel(const FoldArgs *__restrict__ fa,
+                                                         const int2 *__restrict__ items,
+                                                         const int *__restrict__ beff) {
+    const int2 it = items[blockIdx.x];
+    const int b = beff[it.x];
+    if (b == 0) return;
+    FoldArgs a = fa[it.x];
+    a.b = b;
+    fold_tile_body(a, it.y, 0, 1);
+}
+
+__global__ __launch_bounds__(256) void rescale_multi_kernel(const RescaleArgs *__restrict__ ra,
+                                                            const int *__restrict__ upd,
+                                                            const int2 *__restrict__ items,
+                                                            const int *__restrict__ beff) {
+    const int2 it = items[blockIdx.x];
+    const int b = beff[it.x];
+    if (b == 0 || !upd[it.x]) return;
+    rescale_body(ra[it.x], it.y, b);
+}
+
+// Positive pseudo-random fill (splitmix hash of the index) for tuning inputs.
+__global__ void fill_kernel(float *x, long n, float lo, float span, unsigned seed) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long z = (unsigned long long)i * 0x9E3779B97F4A7C15ull + seed;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = lo + span * (float)(z >> 40) * (1.0f / 16777216.0f);
+}
+
+}  // namespace
+
+struct isnmf_multi {
+    int S = 0;
+    std::vector<isnmf_online *> hs;
+    std::vector<long long> nframes, cursor;
+    std::vector<int> b;
+    FitDesc *d_fit = nullptr;
+    FoldArgs *d_fold = nullptr;
+    RescaleArgs *d_rs = nullptr;
+    int *d_upd = nullptr, *d_b = nullptr, *d_beff = nullptr;
+    long long *d_cursor = nullptr, *d_nf = nullptr;
+    int2 *d_items = nullptr;
+    struct Group {
+        FitClass c;
+        int prec, off, n;
+    };
+    std::vector<Group> groups;
+    int fold_off = 0, fold_n = 0, rs_off = 0, rs_n = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last = nullptr;
+};
+
+// Host accessors of the online handle (defined in abi.hip).
+extern "C++" {
+const OnlineDev *isnmf_handle_dev(const isnmf_online *h);
+const FitClass *isnmf_handle_class(const isnmf_online *h);
+const isnmf_params *isnmf_handle_params(const isnmf_online *h);
+int isnmf_handle_kernel(const isnmf_online *h);
+void isnmf_handle_advance(isnmf_online *h, long long frames, hipStream_t s);
+}
+
+namespace {
+
+int prec_of(const isnmf_params &p) {
+    return p.precision == ISNMF_BF16 ? 1 : p.precision == ISNMF_FP16 ? 2 : 0;
+}
+
+struct Layout {
+    size_t fit, fold, rs, upd, b, beff, cur, nf, items, total;
+};
+
+Layout layout(int S, size_t nitems) {
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.fit = take(sizeof(FitDesc) * S);
+    L.fold = take(sizeof(FoldArgs) * S);
+    L.rs = take(sizeof(RescaleArgs) * S);
+    L.upd = take(sizeof(int) * S);
+    L.b = take(sizeof(int) * S);
+    L.beff = take(sizeof(int) * S);
+    L.cur = take(sizeof(long long) * S);
+    L.nf = take(sizeof(long long) * S);
+    L.items = take(sizeof(int2) * (nitems ? nitems : 1));
+    L.total = off;
+    return L;
+}
+
+size_t count_items(isnmf_online *const *h, const int *b, int S) {
+    size_t n = 0;
+    for (int s = 0; s < S; ++s) {
+        const OnlineDev &d = *isnmf_handle_dev(h[s]);
+        n += (size_t)((b[s] + NF - 1) / NF) + fold_tiles(d) + d.K;
+    }
+    return n;
+}
+
+hipError_t enqueue_step(isnmf_multi *m, hipStream_t s) {
+    const int blocks = (m->S + 255) / 256;
+    prepare_kernel<<<blocks, 256, 0, s>>>(m->S, m->d_b, m->d_nf, m->d_cursor, m->d_beff);
+    for (const auto &g : m->groups) {
+        hipError_t e;
+        if (g.prec == 1)
+            e = launch_fit_multi_p<1>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
+        else if (g.prec == 2)
+            e = launch_fit_multi_p<2>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
+        else
+            e = launch_fit_multi_p<0>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
+        if (e != hipSuccess) return e;
+    }
+    if (m->fold_n) fold_multi_kernel<<<m->fold_n, 256, 0, s>>>(m->d_fold, m->d_items + m->fold_off, m->d_beff);
+    if (m->rs_n)
+        rescale_multi_kernel<<<m->rs_n, 256, 0, s>>>(m->d_rs, m->d_upd, m->d_items + m->rs_off, m->d_beff);
+    advance_kernel<<<blocks, 256, 0, s>>>(m->S, m->d_beff, m->d_cursor);
+    return hipGetLastError();
+}
+
+void host_advance(isnmf_multi *m, hipStream_t s) {
+    for (int i = 0; i < m->S; ++i) {
+        const long long left = m->nframes[i] - m->cursor[i];
+        const long long step = left <= 0 ? 0 : (left < m->b[i] ? left : m->b[i]);
+        m->cursor[i] += step;
+        if (step) isnmf_handle_advance(m->hs[i], step, s);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t isnmf_multi_workspace_size(isnmf_online *const *handles, int S, const int *b) {
+    if (!handles || !b || S < 1) return 0;
+    for (int s = 0; s < S; ++s)
+        if (!handles[s] || b[s] < 1) return 0;
+    return layout(S, count_items(handles, b, S)).total;
+}
+
+int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
+                       const float *const *V, const int *ldv, const long long *n_frames,
+                       const int *b, double *d_loss, void *workspace, size_t ws_bytes,
+                       void *stream) {
+    if (!out) return ISNMF_EINVAL;
+    *out = nullptr;
+    if (!handles || !V || !ldv || !n_frames || !b || S < 1 || !workspace) return ISNMF_EINVAL;
+    if (((uintptr_t)workspace & 255) != 0) return ISNMF_EINVAL;
+    for (int s = 0; s < S; ++s) {
+        if (!handles[s] || !V[s] || n_frames[s] < 0 || b[s] < 1) return ISNMF_EINVAL;
+        const OnlineDev &d = *isnmf_handle_dev(handles[s]);
+        const isnmf_params &p = *isnmf_handle_params(handles[s]);
+        if (ldv[s] < d.F || b[s] > d.b_max) return ISNMF_EINVAL;
+        if (p.h_init == ISNMF_H_WARM) return ISNMF_EINVAL;            // fresh restarts only
+        if (isnmf_handle_kernel(handles[s]) != ISNMF_KERNEL_FUSED) return ISNMF_EUNSUPPORTED;
+        if (b[s] > 512) return ISNMF_EUNSUPPORTED;                   // single fold slice
+        for (int r = 0; r < s; ++r)
+            if (handles[r] == handles[s]) return ISNMF_EINVAL;        // one entry per stream
+    }
+    const size_t nitems = count_items(handles, b, S);
+    const Layout L = layout(S, nitems);
+    if (ws_bytes < L.total) return ISNMF_ENOMEM;
+
+    isnmf_multi *m = new (std::nothrow) isnmf_multi;
+    if (!m) return ISNMF_ENOMEM;
+    char *base = (char *)workspace;
+    m->S = S;
+    m->hs.assign(handles, handles + S);
+    m->nframes.assign(n_frames, n_frames + S);
+    m->cursor.assign(S, 0);
+    m->b.assign(b, b + S);
+    m->d_fit = (FitDesc *)(base + L.fit);
+    m->d_fold = (FoldArgs *)(base + L.fold);
+    m->d_rs = (RescaleArgs *)(base + L.rs);
+    m->d_upd = (int *)(base + L.upd);
+    m->d_b = (int *)(base + L.b);
+    m->d_beff = (int *)(base + L.beff);
+    m->d_cursor = (long long *)(base + L.cur);
+    m->d_nf = (long long *)(base + L.nf);
+    m->d_items = (int2 *)(base + L.items);
+    m->last = (hipStream_t)stream;
+
+    std::vector<FitDesc> fit(S);
+    std::vector<FoldArgs> fold(S);
+    std::vector<RescaleArgs> rs(S);
+    std::vector<int> upd(S);
+    std::vector<long long> zero(S, 0);
+    std::vector<int2> items;
+    items.reserve(nitems);
+    // fit items grouped by (variant, precision)
+    std::vector<std::pair<std::tuple<int, int, int, int, int>, std::vector<int2>>> groups;
+    for (int s = 0; s < S; ++s) {
+        const OnlineDev &d = *isnmf_handle_dev(handles[s]);
+        const isnmf_params &p = *isnmf_handle_params(handles[s]);
+        const FitClass &c = *isnmf_handle_class(handles[s]);
+        fit[s] = make_fit_desc(d, V[s], ldv[s], b[s], p.inner_iters, p.eps, 0, nullptr, d.K);
+        fold[s] = fold_args(d, b[s], p.rho, p.update_w, nullptr, d_loss ? d_loss + s : nullptr);
+        rs[s] = rescale_args(d, p.normalize, 0, nullptr, d.K);
+        upd[s] = p.update_w;
+        const auto key = std::make_tuple(c.nw, c.cpw, c.kmax, c.wg, prec_of(p));
+        size_t gi = 0;
+        while (gi < groups.size() && groups[gi].first != key) ++gi;
+        if (gi == groups.size()) groups.push_back({key, {}});
+        for (int t = 0; t < (b[s] + NF - 1) / NF; ++t) groups[gi].second.push_back(int2{s, t});
+    }
+    for (auto &g : groups) {
+        isnmf_multi::Group G;
+        G.c = *isnmf_handle_class(handles[g.second.front().x]);
+        G.prec = std::get<4>(g.first);
+        G.off = (int)items.size();
+        G.n = (int)g.second.size();
+        items.insert(items.end(), g.second.begin(), g.second.end());
+        m->groups.push_back(G);
+    }
+    m->fold_off = (int)items.size();
+    for (int s = 0; s < S; ++s) {
+        const int nt = fold_tiles(*isnmf_handle_dev(handles[s]));
+        for (int t = 0; t < nt; ++t) items.push_back(int2{s, t});
+    }
+    m->fold_n = (int)items.size() - m->fold_off;
+    m->rs_off = (int)items.size();
+    for (int s = 0; s < S; ++s) {
+        const int K = isnmf_handle_dev(handles[s])->K;
+        for (int k = 0; k < K; ++k) items.push_back(int2{s, k});
+    }
+    m->rs_n = (int)items.size() - m->rs_off;
+
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    auto cp = [&](void *dst, const void *src, size_t n) {
+        if (e == hipSuccess) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
+    };
+    cp(m->d_fit, fit.data(), sizeof(FitDesc) * S);
+    cp(m->d_fold, fold.data(), sizeof(FoldArgs) * S);
+    cp(m->d_rs, rs.data(), sizeof(RescaleArgs) * S);
+    cp(m->d_upd, upd.data(), sizeof(int) * S);
+    cp(m->d_b, b, sizeof(int) * S);
+    cp(m->d_cursor, zero.data(), sizeof(long long) * S);
+    cp(m->d_nf, n_frames, sizeof(long long) * S);
+    cp(m->d_items, items.data(), sizeof(int2) * items.size());
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // host vectors go out of scope
+    if (e != hipSuccess) {
+        delete m;
+        return ISNMF_EDEVICE;
+    }
+    *out = m;
+    return ISNMF_OK;
+}
+
+int isnmf_multi_step(isnmf_multi *m, void *stream) {
+    if (!m) return ISNMF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (enqueue_step(m, s) != hipSuccess) return ISNMF_EDEVICE;
+    host_advance(m, s);
+    m->last = s;
+    return ISNMF_OK;
+}
+
+int isnmf_multi_run(isnmf_multi *m, int steps, int use_graph, void *stream) {
+    if (!m || steps < 0) return ISNMF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (!use_graph) {
+        for (int i = 0; i < steps; ++i) {
+            const int st = isnmf_multi_step(m, stream);
+            if (st != ISNMF_OK) return st;
+        }
+        return ISNMF_OK;
+    }
+    if (!m->exec) {
+        if (!m->cap && hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking) != hipSuccess)
+            return ISNMF_EDEVICE;
+        if (hipStreamBeginCapture(m->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return ISNMF_EDEVICE;
+        const hipError_t e1 = enqueue_step(m, m->cap);
+        const hipError_t e2 = hipStreamEndCapture(m->cap, &m->graph);
+        if (e1 != hipSuccess || e2 != hipSuccess) return ISNMF_EDEVICE;
+        if (hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0) != hipSuccess) {
+            m->exec = nullptr;
+            return ISNMF_EDEVICE;
+        }
+    }
+    for (int i = 0; i < steps; ++i) {
+        if (hipGraphLaunch(m->exec, s) != hipSuccess) return ISNMF_EDEVICE;
+        host_advance(m, s);
+    }
+    m->last = s;
+    return ISNMF_OK;
+}
+
+int isnmf_multi_frames_left(const isnmf_multi *m, long long *host_max_left) {
+    if (!m || !host_max_left) return ISNMF_EINVAL;
+    long long mx = 0;
+    for (int i = 0; i < m->S; ++i) {
+        const long long left = m->nframes[i] - m->cursor[i];
+        if (left > mx) mx = left;
+    }
+    *host_max_left = mx;
+    return ISNMF_OK;
+}
+
+int isnmf_multi_destroy(isnmf_multi *m) {
+    if (!m) return ISNMF_EINVAL;
+    hipError_t e = hipStreamSynchronize(m->last);
+    if (m->exec) hipGraphExecDestroy(m->exec);
+    if (m->graph) hipGraphDestroy(m->graph);
+    if (m->cap) hipStreamDestroy(m->cap);
+    delete m;
+    return e == hipSuccess ? ISNMF_OK : ISNMF_EDEVICE;
+}
+
+// ----------------------------------------------------------------- autotuner
+
+int isnmf_autotune(int F, int K, int b, const isnmf_params *pp, int trials, int *out_variant,
+                   double *out_us, void *stream) {
+    isnmf_params p;
+    isnmf_params_default(&p);
+    if (pp) p = *pp;
+    if (F < 1 || K < 1 || b < 1 || trials < 1) return ISNMF_EINVAL;
+    if (p.precision == ISNMF_FP64) return ISNMF_EUNSUPPORTED;
+    const int prec = prec_of(p);
+    FitClass cand[8];
+    const int nc = fit_candidates(F, K, prec, cand, 8);
+    if (nc == 0) return ISNMF_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    // a scratch stream state on the device
+    const size_t wsz = isnmf_online_workspace_size(F, K, b, &p);
+    void *ws = nullptr;
+    float *V = nullptr, *W0 = nullptr;
+    if (hipMalloc(&ws, wsz) != hipSuccess) return ISNMF_ENOMEM;
+    if (hipMalloc((void **)&V, sizeof(float) * (size_t)F * b) != hipSuccess ||
+        hipMalloc((void **)&W0, sizeof(float) * (size_t)F * K) != hipSuccess) {
+        hipFree(ws);
+        hipFree(V);
+        return ISNMF_ENOMEM;
+    }
+    const long nv = (long)F * b, nw = (long)F * K;
+    fill_kernel<<<(int)((nv + 255) / 256), 256, 0, s>>>(V, nv, 0.01f, 10.f, 7u);
+    fill_kernel<<<(int)((nw + 255) / 256), 256, 0, s>>>(W0, nw, 0.5f, 1.f, 11u);
+    isnmf_online *h = nullptr;
+    int st = isnmf_online_init(&h, F, K, b, &p, W0, F, nullptr, nullptr, ws, wsz, stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = -1;
+    double best_us = 1e30;
+    if (st == ISNMF_OK && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+        const OnlineDev &d = *isnmf_handle_dev(h);
+        for (int c = 0; c < nc && st == ISNMF_OK; ++c) {
+            float ms = 0.f;
+            hipError_t e = launch_fused_fit(d, cand[c], V, F, b, p.inner_iters, p.eps, 0, nullptr,
+                                            K, prec, s);   // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int t = 0; t < trials && e == hipSuccess; ++t)
+                e = launch_fused_fit(d, cand[c], V, F, b, p.inner_iters, p.eps, 0, nullptr, K, prec, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                st = ISNMF_EDEVICE;
+                break;
+            }
+            const double us = 1e3 * ms / trials;
+            if (us < best_us) {
+                best_us = us;
+                best = c;
+            }
+        }
+    } else if (st == ISNMF_OK) {
+        st = ISNMF_EDEVICE;
+    }
+    if (h) isnmf_online_destroy(h);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipStreamSynchronize(s);
+    hipFree(ws);
+    hipFree(V);
+    hipFree(W0);
+    if (st != ISNMF_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[{F, K, prec}] = cand[best];
+    }
+    if (out_variant) *out_variant = best;
+    if (out_us) *out_us = best_us;
+    return ISNMF_OK;
+}
+
+int isnmf_tune_get(int F, int K, int precision, int *nw, int *cpw, int *wg) {
+    isnmf_params p;
+    isnmf_params_default(&p);
+    p.precision = precision;
+    const FitClass c = tuned_class(F, K, prec_of(p), 0);
+    if (!c.ok) return ISNMF_EUNSUPPORTED;
+    if (nw) *nw = c.nw;
+    if (cpw) *cpw = c.cpw;
+    if (wg) *wg = c.wg;
+    return ISNMF_OK;
+}
+
+int isnmf_tune_set(int F, int K, int precision, int nw, int cpw, int wg) {
+    isnmf_params p;
+    isnmf_params_default(&p);
+    p.precision = precision;
+    const int prec = prec_of(p);
+    FitClass cand[8];
+    const int nc = fit_candidates(F, K, prec, cand, 8);
+    for (int c = 0; c < nc; ++c)
+        if (cand[c].nw == nw && cand[c].cpw == cpw && cand[c].wg == wg) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[{F, K, prec}] = cand[c];
+            return ISNMF_OK;
+        }
+    return ISNMF_EINVAL;
+}
+
+void isnmf_tune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+}  // extern "C"

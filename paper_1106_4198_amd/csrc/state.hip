@@ -7,10 +7,8 @@
 //            dW = ||W_new - W_old||_F;  loss_sum += sum_n loss_n
 // A, B and the master W are FP64.  Every sum runs in a fixed order, so the
 // results are bitwise repeatable.
-#include <hip/hip_bf16.h>
-#include <hip/hip_fp16.h>
-
 #include "common.h"
+#include "state_body.h"
 
 namespace isnmf {
 namespace {
@@ -47,94 +45,8 @@ __global__ void fold_kernel(int F, int K, int b, int FR, int KP, const TR *__res
     }
 }
 
-__device__ inline uint16_t to_half_bits(double v, int kind) {
-    if (kind == 1) {
-        __hip_bfloat16 h = __float2bfloat16(float(v));
-        return *reinterpret_cast<uint16_t *>(&h);
-    }
-    __half h = __float2half(float(v));
-    return *reinterpret_cast<uint16_t *>(&h);
-}
-
-// Sum over a 256-thread block in a fixed order: per-wave xor butterfly (the
-// same value in every lane), then the four wave sums in index order.
-__device__ inline double block_sum256(double v, double *red4) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
-    __syncthreads();
-    return ((red4[0] + red4[1]) + red4[2]) + red4[3];
-}
-
-// Block (256 threads) per column k: s_k = sum_f Wn_fk, W = Wn / s, A /= s,
-// B *= s, warm H[k,:] *= s, and the column's squared change of W.
-__global__ __launch_bounds__(256) void rescale_kernel(
-    int F, int K, int b, const double *__restrict__ Wn, double *__restrict__ W64,
-    float *__restrict__ W32, uint16_t *__restrict__ W16, int w16_kind, double *__restrict__ A,
-    double *__restrict__ B, int normalize, int warm, float *__restrict__ Hb, int ldh,
-    double *__restrict__ dwpart, int *__restrict__ flags) {
-    __shared__ double red4[4];
-    const int k = blockIdx.x;
-    const int tid = threadIdx.x;
-    const size_t col = (size_t)k * F;
-    // all loads first (one memory round trip), then the column sum
-    constexpr int RMAX = 8;   // rows per thread held in registers (F <= 2048)
-    double wn[RMAX], wo[RMAX], av[RMAX], bv[RMAX];
-    double s = 0.0;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-        const int f = tid + 256 * r;
-        const bool ok = f < F;
-        wn[r] = ok ? Wn[col + f] : 0.0;
-        wo[r] = ok ? W64[col + f] : 0.0;
-        av[r] = ok ? A[col + f] : 0.0;
-        bv[r] = ok ? B[col + f] : 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) s += wn[r];
-    for (int f = tid + 256 * RMAX; f < F; f += 256) s += Wn[col + f];
-    s = block_sum256(s, red4);
-    double scale = 1.0;
-    if (normalize) {
-        if (s > 0.0)
-            scale = s;
-        else if (tid == 0)
-            atomicOr(flags, FLAG_GUARD_W);
-    }
-    double dw = 0.0;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-        const int f = tid + 256 * r;
-        if (f < F) {
-            const double w = wn[r] / scale;
-            const double dlt = w - wo[r];
-            dw += dlt * dlt;
-            W64[col + f] = w;
-            W32[col + f] = float(w);
-            if (W16) W16[col + f] = to_half_bits(w, w16_kind);
-            if (normalize) {
-                A[col + f] = av[r] / scale;
-                B[col + f] = bv[r] * scale;
-            }
-        }
-    }
-    for (int f = tid + 256 * RMAX; f < F; f += 256) {
-        const double w = Wn[col + f] / scale;
-        const double dlt = w - W64[col + f];
-        dw += dlt * dlt;
-        W64[col + f] = w;
-        W32[col + f] = float(w);
-        if (W16) W16[col + f] = to_half_bits(w, w16_kind);
-        if (normalize) {
-            A[col + f] /= scale;
-            B[col + f] *= scale;
-        }
-    }
-    if (warm && Hb && normalize)
-        for (int n = tid; n < b; n += 256) Hb[(size_t)n * ldh + k] *= float(scale);
-    dw = block_sum256(dw, red4);
-    if (tid == 0) dwpart[k] = dw;
+__global__ __launch_bounds__(256) void rescale_kernel(RescaleArgs a, int b) {
+    rescale_body(a, blockIdx.x, b);
 }
 
 // ||W_new - W_old||_F from the per-column partials, in column order.
@@ -150,7 +62,7 @@ __global__ void dw_total_kernel(int K, const double *__restrict__ dwpart, int up
 
 __global__ void set_w_kernel(int F, int K, const float *__restrict__ W, int ldw,
                              const double *__restrict__ Wd, double *__restrict__ W64,
-                             float *__restrict__ W32, uint16_t *__restrict__ W16, int w16_kind) {
+                             float *__restrict__ W32, W16Out w16) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)F * K) return;
     const int f = (int)(e % F);
@@ -158,7 +70,7 @@ __global__ void set_w_kernel(int F, int K, const float *__restrict__ W, int ldw,
     const double v = Wd ? Wd[e] : double(W[f + (size_t)k * ldw]);
     W64[e] = v;
     W32[e] = float(v);
-    if (W16) W16[e] = to_half_bits(v, w16_kind);
+    store_w16(w16, f, k, v);
 }
 
 __global__ void loss_total_kernel(const double *__restrict__ lossf, int b,
@@ -193,20 +105,18 @@ hipError_t launch_fold(const OnlineDev &d, int b, double rho, int update_w, int 
 }
 
 hipError_t launch_rescale(const OnlineDev &d, int b, int update_w, int normalize, int warm,
-                          float *Hb, int ldh, double *d_dw, int w16_kind, hipStream_t s) {
+                          float *Hb, int ldh, double *d_dw, hipStream_t s) {
     if (update_w)
-        rescale_kernel<<<d.K, 256, 0, s>>>(d.F, d.K, b, d.Wn, d.W64, d.W32,
-                                           w16_kind ? d.W16 : nullptr, w16_kind, d.A, d.B,
-                                           normalize, warm, Hb, ldh, d.dwpart, d.flags);
+        rescale_kernel<<<d.K, 256, 0, s>>>(rescale_args(d, normalize, warm, Hb, ldh), b);
     if (d_dw) dw_total_kernel<<<1, 64, 0, s>>>(d.K, d.dwpart, update_w, d_dw);
     return hipGetLastError();
 }
 
 hipError_t launch_set_w(const OnlineDev &d, const float *W, int ldw, const double *W64,
-                        int w16_kind, hipStream_t s) {
+                        hipStream_t s) {
     const long n = (long)d.F * d.K;
     set_w_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(d.F, d.K, W, ldw, W64, d.W64, d.W32,
-                                                        w16_kind ? d.W16 : nullptr, w16_kind);
+                                                        w16_out(d));
     return hipGetLastError();
 }
 

@@ -1,0 +1,146 @@
+"""Batched form: many streams of uneven F, K, b in shared launches.
+
+A stream's result must not depend on which other streams share its launches:
+each stream of a mixed batch is compared bitwise with the same stream run
+alone through isnmf_online_step (same kernel variant, fixed-order sums).
+The hipGraph replay is checked against eager execution after every replay.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1106_4198_amd import synth
+from tests.helpers import from_gpu_kf, rel_fro
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1106_4198_amd import binding as bd  # noqa: E402
+
+DEV = "cuda"
+
+# (F, K, b, precision, frames)
+MIX = [(257, 16, 32, "bf16", 160), (513, 50, 64, "bf16", 256), (1025, 40, 32, "bf16", 96),
+       (1025, 100, 16, "bf16", 64), (513, 128, 32, "fp16", 80), (257, 64, 128, "fp32", 384),
+       (129, 8, 4, "fp32", 14), (513, 50, 128, "fp32", 200)]
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def inputs(seed0=300):
+    out = []
+    for i, (F, K, b, prec, N) in enumerate(MIX):
+        V, W0 = synth.problem(F, K, N, seed=seed0 + i)
+        out.append((torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV),
+                    torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV), b, prec))
+    return out
+
+
+def handles(data):
+    return [bd.OnlineISNMF(W0, b, precision=prec) for (W0, V, b, prec) in data]
+
+
+def state(g):
+    W, A, B, t = g.get()
+    return g.get_w64(), A, B, t
+
+
+def test_batched_equals_alone_bitwise():
+    data = inputs()
+    steps = 4
+    say("batched vs alone, %d streams, %d steps" % (len(data), steps))
+    alone = handles(data)
+    loss_alone = []
+    for g, (W0, V, b, prec) in zip(alone, data):
+        ls = torch.zeros((), dtype=torch.float64, device=DEV)
+        for s in range(steps):
+            lo, hi = s * b, min((s + 1) * b, V.shape[0])
+            if lo < hi:
+                g.step(V[lo:hi], None, ls)
+        loss_alone.append(ls)
+    mixed = handles(data)
+    m = bd.MultiISNMF(mixed, [d[1] for d in data], [d[2] for d in data])
+    m.run(steps, graph=False)
+    torch.cuda.synchronize()
+    for i, (ga, gm) in enumerate(zip(alone, mixed)):
+        sa, sm = state(ga), state(gm)
+        assert sa[3] == sm[3], (i, sa[3], sm[3])
+        for x, y in zip(sa[:3], sm[:3]):
+            assert torch.equal(x, y), f"stream {i} {MIX[i]} differs alone vs batched"
+        assert torch.equal(loss_alone[i], m.loss[i]), i
+    assert m.frames_left() == max(0, max(N - steps * b for (_, _, b, _, N) in MIX))
+    m.close()
+
+
+def test_graph_replays_match_eager_every_step():
+    data = inputs(seed0=400)
+    say("graph replay vs eager")
+    ge, gg = handles(data), handles(data)
+    me = bd.MultiISNMF(ge, [d[1] for d in data], [d[2] for d in data])
+    mg = bd.MultiISNMF(gg, [d[1] for d in data], [d[2] for d in data])
+    for step in range(6):
+        mg.run(1, graph=True)
+        torch.cuda.synchronize()
+        me.run(1, graph=False)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(ge, gg)):
+            sa, sb = state(a), state(b)
+            assert sa[3] == sb[3]
+            for x, y in zip(sa[:3], sb[:3]):
+                assert torch.equal(x, y), f"replay {step} stream {i}"
+        assert torch.equal(me.loss, mg.loss)
+    me.close()
+    mg.close()
+
+
+def test_batched_streams_match_oracle():
+    """Two streams of the mix against the FP64 oracle: FP32 at 1e-5, BF16 at
+    the precision-form bound (2e-2 on W, A, B; 1e-3 on the loss)."""
+    data = inputs(seed0=500)
+    steps = 3
+    say("batched vs oracle")
+    hs = handles(data)
+    m = bd.MultiISNMF(hs, [d[1] for d in data], [d[2] for d in data])
+    m.run(steps, graph=True)
+    torch.cuda.synchronize()
+    for i, tol in ((5, 1e-5), (1, 2e-2), (3, 2e-2)):
+        F, K, b, prec, N = MIX[i]
+        W0 = data[i][0].cpu().double().numpy().T
+        V = data[i][1].cpu().double().numpy().T
+        st = oracle.OnlineState(W0)
+        for s in range(steps):
+            st.step(V[:, s * b:min((s + 1) * b, N)], iters=20)
+        W64, A, B, t = state(hs[i])
+        assert t == min(N, steps * b)
+        for x, y, nm in ((from_gpu_kf(W64), st.W, "W"), (from_gpu_kf(A), st.A, "A"),
+                         (from_gpu_kf(B), st.B, "B")):
+            e = rel_fro(x, y)
+            print(f"[batched] stream {i} {MIX[i]} {nm} rel {e:.2e}")
+            assert e <= tol
+        assert abs(m.loss[i].item() - st.loss_sum) <= 1e-3 * st.loss_sum
+    m.close()
+
+
+def test_autotune_picks_a_valid_variant_and_keeps_parity():
+    say("autotune")
+    bd.tune_clear()
+    for F, K, prec in ((513, 50, "bf16"), (1025, 40, "bf16")):
+        v, us = bd.autotune(F, K, 64, precision=prec, trials=3)
+        nw, cpw, wg = bd.tune_get(F, K, prec)
+        print(f"[autotune] F={F} K={K} {prec}: variant {v} nw={nw} cpw={cpw} wg={wg} {us:.1f} us")
+        assert us > 0 and nw * cpw * 64 >= (F // 64) * 64
+        V, W0 = synth.problem(F, K, 64, seed=7)
+        g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), 64, precision=prec)
+        g.step(torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV))
+        st = oracle.OnlineState(W0.astype(np.float64))
+        st.step(V.astype(np.float64), iters=20)
+        assert rel_fro(from_gpu_kf(g.get_w64()), st.W) < 2e-2
+    bd.tune_clear()

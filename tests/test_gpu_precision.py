@@ -31,7 +31,9 @@ def say(*a):
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
-@pytest.mark.parametrize("F,K,b", [(513, 50, 128), (129, 8, 16), (257, 64, 33), (70, 5, 6)])
+@pytest.mark.parametrize("F,K,b", [(513, 50, 128), (129, 8, 16), (257, 64, 33), (70, 5, 6),
+                                   (257, 96, 7), (513, 128, 12), (1025, 50, 16), (1025, 100, 9),
+                                   (1025, 16, 5), (700, 33, 4)])
 def test_one_step_error_is_small(precision, F, K, b):
     say(f"precision step {precision} F={F} K={K} b={b}")
     V, W0 = synth.problem(F, K, 3 * b, seed=5)
