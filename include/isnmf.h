@@ -234,6 +234,56 @@ int isnmf_multi_frames_left(const isnmf_multi *m, long long *host_max_left);
 
 int isnmf_multi_destroy(isnmf_multi *m);
 
+/* ------------------------------------------------------------- served form */
+
+/*
+ * Continuous-batching engine over many online sessions (fresh restarts).
+ * Sessions are registered handles whose W, A, B stay resident.  Clients
+ * submit chunks of frames already on the device; each engine step takes at
+ * most one pending chunk per session (oldest first, at most max_per_step
+ * chunks and max_frames frames), runs one minibatch step (b = chunk length)
+ * for all of them in shared launches, and keeps up to `inflight` steps
+ * enqueued while new arrivals join the next one.  Per session, chunks are
+ * applied in submission order, exactly as isnmf_online_step would.
+ *
+ * workspace: device memory of isnmf_server_workspace_size() bytes (descriptor
+ *   tables and work lists), 256-byte aligned, caller-owned.  The server also
+ *   allocates `inflight` small pinned host buffers and events.
+ * hbm_budget: admission by HBM footprint -- isnmf_server_open fails with
+ *   ISNMF_ENOMEM when the session's `footprint` (its workspace bytes, or any
+ *   figure the caller charges) would exceed it.
+ * Sessions must use the fused kernel with one 64-row chunk per wave and
+ * K <= 64 (F <= 516); chunks hold 1..min(b_max, 512, max_frames) frames.
+ * Calls are not thread-safe.
+ */
+typedef struct isnmf_server isnmf_server;
+
+size_t isnmf_server_workspace_size(int max_sessions, int max_per_step, int inflight);
+int isnmf_server_create(isnmf_server **out, int max_sessions, int max_per_step, int max_frames,
+                        int inflight, size_t hbm_budget, void *workspace, size_t ws_bytes,
+                        void *stream);
+/* Register a handle; *session receives its index. */
+int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *session);
+/* Queue a chunk (device F x n_frames FP32, ldv >= F).  arrival: the client's
+ * timestamp on isnmf_server_clock() (negative: now).  The frames must stay
+ * valid until the chunk completes. */
+int isnmf_server_submit(isnmf_server *s, int session, const float *V, int ldv, int n_frames,
+                        double arrival, long long *request);
+/* Retire finished steps and enqueue new ones (never blocks on the device). */
+int isnmf_server_pump(isnmf_server *s, int *launched_frames);
+int isnmf_server_pending(const isnmf_server *s, long long *queued, long long *inflight);
+/* Run until every submitted chunk has completed (synchronizes). */
+int isnmf_server_drain(isnmf_server *s);
+/* Completed chunks since the last call (host arrays of max_out entries, any
+ * may be NULL): request id, session, frames, arrival, launch and completion
+ * times in seconds on isnmf_server_clock(). */
+int isnmf_server_results(isnmf_server *s, int max_out, long long *req, int *session,
+                         int *n_frames, double *arrival, double *start, double *done, int *count);
+int isnmf_server_stats(const isnmf_server *s, long long *steps, long long *frames);
+/* Monotonic host clock in seconds used for arrival and completion times. */
+double isnmf_server_clock(void);
+int isnmf_server_destroy(isnmf_server *s);
+
 /* ------------------------------------------------------------- autotuner */
 
 /*

@@ -75,6 +75,19 @@ def _load():
         "isnmf_tune_get": (i, [i, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
         "isnmf_tune_set": (i, [i, i, i, i, i, i]),
         "isnmf_tune_clear": (None, []),
+        "isnmf_server_workspace_size": (sz, [i, i, i]),
+        "isnmf_server_create": (i, [ctypes.POINTER(vp), i, i, i, i, sz, vp, sz, vp]),
+        "isnmf_server_open": (i, [vp, vp, sz, ctypes.POINTER(i)]),
+        "isnmf_server_submit": (i, [vp, i, vp, i, i, d, ctypes.POINTER(ctypes.c_longlong)]),
+        "isnmf_server_pump": (i, [vp, ctypes.POINTER(i)]),
+        "isnmf_server_pending": (i, [vp, ctypes.POINTER(ctypes.c_longlong),
+                                     ctypes.POINTER(ctypes.c_longlong)]),
+        "isnmf_server_drain": (i, [vp]),
+        "isnmf_server_results": (i, [vp, i, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i)]),
+        "isnmf_server_stats": (i, [vp, ctypes.POINTER(ctypes.c_longlong),
+                                   ctypes.POINTER(ctypes.c_longlong)]),
+        "isnmf_server_clock": (d, []),
+        "isnmf_server_destroy": (i, [vp]),
         "isnmf_batch_workspace_size": (sz, [i, i, i, P]),
         "isnmf_batch_mu": (i, [vp, i, i, i, vp, i, vp, i, i, i, P, vp, vp, sz, vp]),
         "isnmf_objective_workspace_size": (sz, [i, i, i]),
@@ -96,6 +109,10 @@ EXPORTED = ("isnmf_params_default", "isnmf_strerror", "isnmf_online_workspace_si
             "isnmf_multi_workspace_size", "isnmf_multi_create", "isnmf_multi_step",
             "isnmf_multi_run", "isnmf_multi_frames_left", "isnmf_multi_destroy",
             "isnmf_autotune", "isnmf_tune_get", "isnmf_tune_set", "isnmf_tune_clear",
+            "isnmf_server_workspace_size", "isnmf_server_create", "isnmf_server_open",
+            "isnmf_server_submit", "isnmf_server_pump", "isnmf_server_pending",
+            "isnmf_server_drain", "isnmf_server_results", "isnmf_server_stats",
+            "isnmf_server_clock", "isnmf_server_destroy",
             "isnmf_batch_workspace_size", "isnmf_batch_mu",
             "isnmf_objective_workspace_size", "isnmf_objective")
 
@@ -326,6 +343,91 @@ class MultiISNMF:
         if getattr(self, "_m", None):
             _lib.isnmf_multi_destroy(self._m)
             self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching engine over many sessions (see include/isnmf.h)."""
+
+    def __init__(self, max_sessions=1024, max_per_step=1024, max_frames=65536, inflight=2,
+                 hbm_budget=1 << 40, device="cuda", stream=None):
+        nbytes = _lib.isnmf_server_workspace_size(max_sessions, max_per_step, inflight)
+        if nbytes == 0:
+            raise IsnmfError(EINVAL, "isnmf_server_workspace_size")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        s = ctypes.c_void_p()
+        _check(_lib.isnmf_server_create(ctypes.byref(s), max_sessions, max_per_step, max_frames,
+                                        inflight, int(hbm_budget), _ptr(self.workspace), nbytes,
+                                        _stream(stream)), "isnmf_server_create")
+        self._s = s
+        self.sessions = []
+        self._keep = {}
+
+    def open(self, g: "OnlineISNMF", footprint=None) -> int:
+        fp = g.workspace.numel() if footprint is None else int(footprint)
+        idx = ctypes.c_int()
+        _check(_lib.isnmf_server_open(self._s, g._h, fp, ctypes.byref(idx)), "isnmf_server_open")
+        self.sessions.append(g)
+        return idx.value
+
+    def submit(self, session: int, V: torch.Tensor, arrival: float = -1.0) -> int:
+        """V: (n, F) float32 frames on the device (kept alive until done)."""
+        _req(V, torch.float32, name="V")
+        r = ctypes.c_longlong()
+        _check(_lib.isnmf_server_submit(self._s, int(session), _ptr(V), _ld(V), V.shape[0],
+                                        float(arrival), ctypes.byref(r)), "isnmf_server_submit")
+        self._keep[r.value] = V
+        return r.value
+
+    def pump(self) -> int:
+        f = ctypes.c_int()
+        _check(_lib.isnmf_server_pump(self._s, ctypes.byref(f)), "isnmf_server_pump")
+        return f.value
+
+    def pending(self):
+        q, f = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(_lib.isnmf_server_pending(self._s, ctypes.byref(q), ctypes.byref(f)), "pending")
+        return q.value, f.value
+
+    def drain(self):
+        _check(_lib.isnmf_server_drain(self._s), "isnmf_server_drain")
+
+    def results(self, max_out=1 << 16):
+        import numpy as np
+        req = np.zeros(max_out, np.int64)
+        ses = np.zeros(max_out, np.int32)
+        nfr = np.zeros(max_out, np.int32)
+        arr = np.zeros(max_out)
+        sta = np.zeros(max_out)
+        don = np.zeros(max_out)
+        c = ctypes.c_int()
+        P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        _check(_lib.isnmf_server_results(self._s, max_out, P(req), P(ses), P(nfr), P(arr), P(sta),
+                                         P(don), ctypes.byref(c)), "isnmf_server_results")
+        n = c.value
+        for r in req[:n]:
+            self._keep.pop(int(r), None)
+        return {"req": req[:n], "session": ses[:n], "frames": nfr[:n], "arrival": arr[:n],
+                "start": sta[:n], "done": don[:n]}
+
+    def stats(self):
+        st, fr = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(_lib.isnmf_server_stats(self._s, ctypes.byref(st), ctypes.byref(fr)), "stats")
+        return st.value, fr.value
+
+    @staticmethod
+    def clock() -> float:
+        return _lib.isnmf_server_clock()
+
+    def close(self):
+        if getattr(self, "_s", None):
+            _lib.isnmf_server_destroy(self._s)
+            self._s = None
 
     def __del__(self):
         try:

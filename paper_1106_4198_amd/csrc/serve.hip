@@ -1,0 +1,468 @@
+// Served form: a continuous-batching engine over many online sessions.
+//
+// Sessions (isnmf_online handles, W/A/B resident on the device) register
+// with the server; their kernel descriptors are written once into device
+// tables.  Clients submit chunks (frames already on the device).  Each engine
+// step takes at most one pending chunk per session (per-session order is
+// kept, and consecutive steps of one session are ordered on the stream, so
+// each session still follows Algorithm 1 minibatch by minibatch),
+// up to max_frames frames in total, and runs one minibatch step for all of
+// them: one fit launch per kernel variant in use, then one fold and one
+// rescale launch per variant, reading a small work list (session, frames,
+// count) that reaches the device through a pinned ring buffer.  Up to
+// `inflight` steps are enqueued at once; chunks that arrive meanwhile join
+// the next step.  A chunk's latency is arrival to the end of its step.
+//
+// Each chunk's arithmetic is that of isnmf_online_step on its session with
+// b = chunk length (same kernel bodies and variant, fixed-order sums), so a
+// session's result does not depend on what else shares the step.
+#include <math.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "common.h"
+#include "fit_body.h"
+#include "fold_body.h"
+#include "state_body.h"
+
+using namespace isnmf;
+
+const OnlineDev *isnmf_handle_dev(const isnmf_online *h);
+const FitClass *isnmf_handle_class(const isnmf_online *h);
+const isnmf_params *isnmf_handle_params(const isnmf_online *h);
+int isnmf_handle_kernel(const isnmf_online *h);
+void isnmf_handle_advance(isnmf_online *h, long long frames, hipStream_t s);
+
+namespace {
+
+struct Work {
+    int sess;          // index in the device tables
+    int b;             // frames of the chunk
+    const float *V;    // the chunk's frames (ld = the session's ldv)
+    int ldv, pad;
+};
+
+// ---- kernels (grids: x = work item of the class range, y = tile / column)
+
+template <int NW, int CPW, int KMAX, int PREC, bool WG>
+__global__ __launch_bounds__(NW * 64) void serve_fit_kernel(const FitDesc *__restrict__ tab,
+                                                            const Work *__restrict__ work) {
+    const Work wk = work[blockIdx.x];
+    if ((int)blockIdx.y * NF >= wk.b) return;
+    FitDesc a = tab[wk.sess];
+    a.b = wk.b;
+    a.V = wk.V;
+    a.ldv = wk.ldv;
+    fit_body<NW, CPW, KMAX, PREC, WG>(a, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void serve_fold_kernel(const FoldArgs *__restrict__ tab,
+                                                         const Work *__restrict__ work) {
+    const Work wk = work[blockIdx.x];
+    FoldArgs a = tab[wk.sess];
+    a.b = wk.b;
+    fold_tile_body(a, blockIdx.y, 0, 1);
+}
+
+__global__ __launch_bounds__(256) void serve_rescale_kernel(const RescaleArgs *__restrict__ tab,
+                                                            const int *__restrict__ upd,
+                                                            const Work *__restrict__ work) {
+    const Work wk = work[blockIdx.x];
+    if (!upd[wk.sess]) return;
+    rescale_body(tab[wk.sess], blockIdx.y, wk.b);
+}
+
+template <int NW, int CPW, int KMAX, int PREC, bool WG>
+struct ServeL {
+    static hipError_t run(const FitDesc *tab, const Work *work, int n, int tiles, hipStream_t s) {
+        serve_fit_kernel<NW, CPW, KMAX, PREC, WG><<<dim3(n, tiles), NW * 64, 0, s>>>(tab, work);
+        return hipGetLastError();
+    }
+};
+
+// The variant dispatch of fit_launch.h, restated for the serving wrapper.
+template <int PREC>
+hipError_t serve_fit(const FitClass &c, const FitDesc *tab, const Work *work, int n, int tiles,
+                     hipStream_t s) {
+#define ISNMF_SK(NW, CPW, WG)                                                           \
+    switch (c.kmax) {                                                                   \
+        case 8: return ServeL<NW, CPW, 8, PREC, WG>::run(tab, work, n, tiles, s);       \
+        case 16: return ServeL<NW, CPW, 16, PREC, WG>::run(tab, work, n, tiles, s);     \
+        case 24: return ServeL<NW, CPW, 24, PREC, WG>::run(tab, work, n, tiles, s);     \
+        case 32: return ServeL<NW, CPW, 32, PREC, WG>::run(tab, work, n, tiles, s);     \
+        case 40: return ServeL<NW, CPW, 40, PREC, WG>::run(tab, work, n, tiles, s);     \
+        case 52: return ServeL<NW, CPW, 52, PREC, WG>::run(tab, work, n, tiles, s);     \
+        case 64: return ServeL<NW, CPW, 64, PREC, WG>::run(tab, work, n, tiles, s);     \
+        default: break;                                                                 \
+    }
+    if (!c.wg && c.cpw == 1) {
+        switch (c.nw) {
+            case 4: { ISNMF_SK(4, 1, false) break; }
+            case 8: { ISNMF_SK(8, 1, false) break; }
+            default: break;
+        }
+    }
+#undef ISNMF_SK
+    return hipErrorNotSupported;
+}
+
+hipError_t serve_fit_any(int prec, const FitClass &c, const FitDesc *tab, const Work *work, int n,
+                         int tiles, hipStream_t s) {
+    if (prec == 1) return serve_fit<1>(c, tab, work, n, tiles, s);
+    if (prec == 2) return serve_fit<2>(c, tab, work, n, tiles, s);
+    return serve_fit<0>(c, tab, work, n, tiles, s);
+}
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct isnmf_server {
+    // configuration
+    size_t budget = 0, used = 0;
+    int max_frames = 0, max_sessions = 0, max_registered = 0, inflight = 2;
+    hipStream_t stream = nullptr;
+    // sessions
+    struct Sess {
+        isnmf_online *h;
+        int prec, ldv_unused;
+        FitClass cls;
+        int F, K;
+        size_t footprint;
+        std::deque<long long> queue;   // pending request ids, FIFO
+    };
+    std::vector<Sess> sess;
+    FitDesc *d_fit = nullptr;
+    FoldArgs *d_fold = nullptr;
+    RescaleArgs *d_rs = nullptr;
+    int *d_upd = nullptr;
+    // requests
+    struct Req {
+        int sess, n, ldv;
+        const float *V;
+        double arrival, start, done;
+        int state;   // 0 queued, 1 launched, 2 done
+    };
+    std::vector<Req> reqs;
+    std::vector<long long> done_list;
+    size_t done_read = 0;
+    // step ring (pinned host work lists, device work lists, events)
+    struct Slot {
+        Work *host = nullptr;
+        Work *dev = nullptr;
+        hipEvent_t ev = nullptr;
+        bool busy = false;
+        std::vector<long long> reqs;
+    };
+    std::vector<Slot> slots;
+    int next_slot = 0;
+    long long steps = 0, frames = 0;
+    double busy_since = 0.0;
+};
+
+namespace {
+
+int prec_of(const isnmf_params &p) {
+    return p.precision == ISNMF_BF16 ? 1 : p.precision == ISNMF_FP16 ? 2 : 0;
+}
+
+// Retire finished steps: stamp completion times, free their sessions.
+void retire(isnmf_server *s) {
+    for (auto &sl : s->slots) {
+        if (!sl.busy) continue;
+        if (hipEventQuery(sl.ev) != hipSuccess) continue;
+        const double t = now_s();
+        for (long long r : sl.reqs) {
+            auto &q = s->reqs[r];
+            q.state = 2;
+            q.done = t;
+            s->done_list.push_back(r);
+        }
+        sl.reqs.clear();
+        sl.busy = false;
+    }
+}
+
+// Form and enqueue one step from the pending chunks; returns frames launched.
+int launch_step(isnmf_server *s) {
+    isnmf_server::Slot *slot = nullptr;
+    for (int i = 0; i < (int)s->slots.size(); ++i) {
+        auto &c = s->slots[(s->next_slot + i) % s->slots.size()];
+        if (!c.busy) {
+            slot = &c;
+            s->next_slot = (s->next_slot + i + 1) % (int)s->slots.size();
+            break;
+        }
+    }
+    if (!slot) return 0;
+    // at most one chunk per session, oldest request first across sessions
+    std::vector<std::pair<double, int>> cand;
+    for (int i = 0; i < (int)s->sess.size(); ++i) {
+        const auto &ss = s->sess[i];
+        if (!ss.queue.empty()) cand.push_back({s->reqs[ss.queue.front()].arrival, i});
+    }
+    if (cand.empty()) return 0;
+    std::sort(cand.begin(), cand.end());
+    std::vector<int> pick;
+    int frames = 0;
+    for (auto &c : cand) {
+        const auto &q = s->reqs[s->sess[c.second].queue.front()];
+        if (frames + q.n > s->max_frames && !pick.empty()) continue;
+        pick.push_back(c.second);
+        frames += q.n;
+        if ((int)pick.size() >= s->max_sessions) break;
+    }
+    // group by (kernel variant, precision, shape) so each launch has one shape
+    std::sort(pick.begin(), pick.end(), [&](int a, int b) {
+        const auto &A = s->sess[a], &B = s->sess[b];
+        return std::make_tuple(A.prec, A.cls.nw, A.cls.kmax, A.F, A.K) <
+               std::make_tuple(B.prec, B.cls.nw, B.cls.kmax, B.F, B.K);
+    });
+    const double t = now_s();
+    for (int i = 0; i < (int)pick.size(); ++i) {
+        auto &ss = s->sess[pick[i]];
+        const long long r = ss.queue.front();
+        ss.queue.pop_front();
+        auto &q = s->reqs[r];
+        q.state = 1;
+        q.start = t;
+        slot->host[i] = Work{pick[i], q.n, q.V, q.ldv, 0};
+        slot->reqs.push_back(r);
+    }
+    const int n = (int)pick.size();
+    hipStream_t st = s->stream;
+    if (hipMemcpyAsync(slot->dev, slot->host, sizeof(Work) * n, hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+        return -1;
+    // launches per group of equal (variant, shape)
+    for (int lo = 0; lo < n;) {
+        const auto &A = s->sess[pick[lo]];
+        int hi = lo + 1, maxb = s->reqs[slot->reqs[lo]].n;
+        while (hi < n) {
+            const auto &B = s->sess[pick[hi]];
+            if (B.prec != A.prec || B.cls.nw != A.cls.nw || B.cls.kmax != A.cls.kmax || B.F != A.F ||
+                B.K != A.K)
+                break;
+            maxb = std::max(maxb, s->reqs[slot->reqs[hi]].n);
+            ++hi;
+        }
+        const int cnt = hi - lo;
+        const int tiles = (maxb + NF - 1) / NF;
+        if (serve_fit_any(A.prec, A.cls, s->d_fit, slot->dev + lo, cnt, tiles, st) != hipSuccess)
+            return -1;
+        const int ft = ((A.F + 15) / 16) * ((A.K + 15) / 16);
+        serve_fold_kernel<<<dim3(cnt, ft), 256, 0, st>>>(s->d_fold, slot->dev + lo);
+        serve_rescale_kernel<<<dim3(cnt, A.K), 256, 0, st>>>(s->d_rs, s->d_upd, slot->dev + lo);
+        lo = hi;
+    }
+    if (hipGetLastError() != hipSuccess) return -1;
+    for (int i = 0; i < n; ++i) {
+        auto &ss = s->sess[pick[i]];
+        isnmf_handle_advance(ss.h, s->reqs[slot->reqs[i]].n, st);
+    }
+    if (hipEventRecord(slot->ev, st) != hipSuccess) return -1;
+    slot->busy = true;
+    s->steps += 1;
+    s->frames += frames;
+    return frames;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t isnmf_server_workspace_size(int max_sessions, int max_per_step, int inflight) {
+    if (max_sessions < 1 || max_per_step < 1 || inflight < 1) return 0;
+    return align256(sizeof(FitDesc) * max_sessions) + align256(sizeof(FoldArgs) * max_sessions) +
+           align256(sizeof(RescaleArgs) * max_sessions) + align256(sizeof(int) * max_sessions) +
+           (size_t)inflight * align256(sizeof(Work) * max_per_step);
+}
+
+int isnmf_server_create(isnmf_server **out, int max_sessions, int max_per_step, int max_frames,
+                        int inflight, size_t hbm_budget, void *workspace, size_t ws_bytes,
+                        void *stream) {
+    if (!out) return ISNMF_EINVAL;
+    *out = nullptr;
+    if (max_sessions < 1 || max_per_step < 1 || max_frames < 1 || inflight < 1 || inflight > 8 ||
+        !workspace || ((uintptr_t)workspace & 255))
+        return ISNMF_EINVAL;
+    if (ws_bytes < isnmf_server_workspace_size(max_sessions, max_per_step, inflight))
+        return ISNMF_ENOMEM;
+    isnmf_server *s = new (std::nothrow) isnmf_server;
+    if (!s) return ISNMF_ENOMEM;
+    s->budget = hbm_budget;
+    s->max_frames = max_frames;
+    s->max_sessions = max_per_step;
+    s->inflight = inflight;
+    s->max_registered = max_sessions;
+    s->stream = (hipStream_t)stream;
+    char *p = (char *)workspace;
+    s->d_fit = (FitDesc *)p;
+    p += align256(sizeof(FitDesc) * max_sessions);
+    s->d_fold = (FoldArgs *)p;
+    p += align256(sizeof(FoldArgs) * max_sessions);
+    s->d_rs = (RescaleArgs *)p;
+    p += align256(sizeof(RescaleArgs) * max_sessions);
+    s->d_upd = (int *)p;
+    p += align256(sizeof(int) * max_sessions);
+    s->sess.reserve(max_sessions);
+    s->slots.resize(inflight);
+    for (auto &sl : s->slots) {
+        sl.dev = (Work *)p;
+        p += align256(sizeof(Work) * max_per_step);
+        if (hipHostMalloc((void **)&sl.host, sizeof(Work) * max_per_step, 0) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
+            for (auto &c : s->slots) {
+                if (c.host) hipHostFree(c.host);
+                if (c.ev) hipEventDestroy(c.ev);
+            }
+            delete s;
+            return ISNMF_ENOMEM;
+        }
+    }
+    *out = s;
+    return ISNMF_OK;
+}
+
+int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *session) {
+    if (!s || !h || !session) return ISNMF_EINVAL;
+    if ((int)s->sess.size() >= s->max_registered) return ISNMF_ENOMEM;
+    const isnmf_params &p = *isnmf_handle_params(h);
+    if (p.h_init == ISNMF_H_WARM) return ISNMF_EINVAL;
+    if (isnmf_handle_kernel(h) != ISNMF_KERNEL_FUSED) return ISNMF_EUNSUPPORTED;
+    const OnlineDev &d = *isnmf_handle_dev(h);
+    const FitClass &c = *isnmf_handle_class(h);
+    if (c.wg || c.cpw != 1 || (c.nw != 4 && c.nw != 8) || c.kmax > 64) return ISNMF_EUNSUPPORTED;
+    if (s->used + footprint > s->budget) return ISNMF_ENOMEM;   // admission by HBM footprint
+    const int idx = (int)s->sess.size();
+    FitDesc fd = make_fit_desc(d, nullptr, d.F, 1, p.inner_iters, p.eps, 0, nullptr, d.K);
+    FoldArgs fa = fold_args(d, 1, p.rho, p.update_w, nullptr, nullptr);
+    RescaleArgs ra = rescale_args(d, p.normalize, 0, nullptr, d.K);
+    const int upd = p.update_w;
+    hipStream_t st = s->stream;
+    if (hipMemcpyAsync(s->d_fit + idx, &fd, sizeof fd, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(s->d_fold + idx, &fa, sizeof fa, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(s->d_rs + idx, &ra, sizeof ra, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(s->d_upd + idx, &upd, sizeof upd, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return ISNMF_EDEVICE;
+    isnmf_server::Sess ss;
+    ss.h = h;
+    ss.prec = prec_of(p);
+    ss.ldv_unused = 0;
+    ss.cls = c;
+    ss.F = d.F;
+    ss.K = d.K;
+    ss.footprint = footprint;
+    s->sess.push_back(ss);
+    s->used += footprint;
+    *session = idx;
+    return ISNMF_OK;
+}
+
+int isnmf_server_submit(isnmf_server *s, int session, const float *V, int ldv, int n_frames,
+                        double arrival, long long *request) {
+    if (!s || session < 0 || session >= (int)s->sess.size() || !V || n_frames < 1) return ISNMF_EINVAL;
+    const auto &ss = s->sess[session];
+    const OnlineDev &d = *isnmf_handle_dev(ss.h);
+    if (ldv < d.F || n_frames > d.b_max || n_frames > 512 || n_frames > s->max_frames)
+        return ISNMF_EINVAL;
+    isnmf_server::Req q;
+    q.sess = session;
+    q.n = n_frames;
+    q.ldv = ldv;
+    q.V = V;
+    q.arrival = arrival < 0 ? now_s() : arrival;
+    q.start = q.done = 0.0;
+    q.state = 0;
+    s->reqs.push_back(q);
+    const long long id = (long long)s->reqs.size() - 1;
+    s->sess[session].queue.push_back(id);
+    if (request) *request = id;
+    return ISNMF_OK;
+}
+
+int isnmf_server_pump(isnmf_server *s, int *launched_frames) {
+    if (!s) return ISNMF_EINVAL;
+    retire(s);
+    int total = 0;
+    for (;;) {
+        const int f = launch_step(s);
+        if (f < 0) return ISNMF_EDEVICE;
+        if (f == 0) break;
+        total += f;
+    }
+    if (launched_frames) *launched_frames = total;
+    return ISNMF_OK;
+}
+
+int isnmf_server_pending(const isnmf_server *s, long long *queued, long long *inflight) {
+    if (!s) return ISNMF_EINVAL;
+    long long qn = 0, fl = 0;
+    for (const auto &ss : s->sess) qn += (long long)ss.queue.size();
+    for (const auto &sl : s->slots) fl += (long long)sl.reqs.size();
+    if (queued) *queued = qn;
+    if (inflight) *inflight = fl;
+    return ISNMF_OK;
+}
+
+int isnmf_server_drain(isnmf_server *s) {
+    if (!s) return ISNMF_EINVAL;
+    for (;;) {
+        if (isnmf_server_pump(s, nullptr) != ISNMF_OK) return ISNMF_EDEVICE;
+        long long q = 0, f = 0;
+        isnmf_server_pending(s, &q, &f);
+        if (q == 0 && f == 0) return ISNMF_OK;
+        if (hipStreamSynchronize(s->stream) != hipSuccess) return ISNMF_EDEVICE;
+    }
+}
+
+int isnmf_server_results(isnmf_server *s, int max_out, long long *req, int *session,
+                         int *n_frames, double *arrival, double *start, double *done, int *count) {
+    if (!s || !count || max_out < 0) return ISNMF_EINVAL;
+    int c = 0;
+    while (s->done_read < s->done_list.size() && c < max_out) {
+        const long long r = s->done_list[s->done_read++];
+        const auto &q = s->reqs[r];
+        if (req) req[c] = r;
+        if (session) session[c] = q.sess;
+        if (n_frames) n_frames[c] = q.n;
+        if (arrival) arrival[c] = q.arrival;
+        if (start) start[c] = q.start;
+        if (done) done[c] = q.done;
+        ++c;
+    }
+    *count = c;
+    return ISNMF_OK;
+}
+
+int isnmf_server_stats(const isnmf_server *s, long long *steps, long long *frames) {
+    if (!s) return ISNMF_EINVAL;
+    if (steps) *steps = s->steps;
+    if (frames) *frames = s->frames;
+    return ISNMF_OK;
+}
+
+double isnmf_server_clock(void) { return now_s(); }
+
+int isnmf_server_destroy(isnmf_server *s) {
+    if (!s) return ISNMF_EINVAL;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    for (auto &sl : s->slots) {
+        if (sl.host) hipHostFree(sl.host);
+        if (sl.ev) hipEventDestroy(sl.ev);
+    }
+    delete s;
+    return e == hipSuccess ? ISNMF_OK : ISNMF_EDEVICE;
+}
+
+}  // extern "C"
