@@ -83,6 +83,134 @@ def cpu_baseline(V, W0, target_s: float):
                       f"F={F} K={K} b={B} I={ITERS}, FP64, {dt:.1f} s"}
 
 
+PEAK_BF16_MFMA = 2500e12        # MI355X dense BF16 matrix peak, FLOP/s
+
+
+def gen_streams(synth, shapes, seed0, threads):
+    """Per-stream seeded frames: shapes = [(F, K, frames)] -> [(V F x N, W0)]."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(i):
+        F, K, N = shapes[i]
+        return synth.frames(F, K, N, seed0 + i), synth.initial_dictionary(F, K, seed0 + i)
+
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(one, range(len(shapes))))
+
+
+def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0):
+    """S streams advanced together, BF16 products, one replayed hipGraph per step."""
+    rng = np.random.default_rng(seed0)
+    if mixed:
+        Fs = rng.choice([257, 513, 1025], size=S)
+        Ks = rng.integers(16, 129, size=S)
+        bs = rng.choice([32, 64, 128, 256], size=S)
+    else:
+        Fs, Ks, bs = np.full(S, F), np.full(S, K), np.full(S, B)
+    warm = 1
+    shapes = [(int(Fs[i]), int(Ks[i]), int(bs[i]) * (steps + warm)) for i in range(S)]
+    t0 = time.perf_counter()
+    data = gen_streams(synth, shapes, seed0, threads)
+    gen_s = time.perf_counter() - t0
+    tuned = 0
+    if mixed:   # autotuned kernel variant per distinct shape
+        for (Fi, Ki) in sorted(set((int(a), int(b)) for a, b in zip(Fs, Ks))):
+            bd.autotune(Fi, Ki, 64, precision="bf16", trials=2)
+            tuned += 1
+    hs, Vs = [], []
+    for (V, W0), b in zip(data, bs):
+        Vs.append(torch.from_numpy(np.ascontiguousarray(V.T)).to(dev))
+        hs.append(bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(dev), int(b),
+                                 precision="bf16"))
+    m = bd.MultiISNMF(hs, Vs, [int(x) for x in bs], loss=False)
+    m.run(warm, graph=True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    m.run(steps, graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    frames = int(sum(int(b) * steps for b in bs))
+    flops = float(sum(flops_per_frame(int(Fi), int(Ki), ITERS) * int(b) * steps
+                      for Fi, Ki, b in zip(Fs, Ks, bs)))
+    m.close()
+    for h in hs:
+        h.close()
+    out = {"value": frames / (ms / 1e3), "unit": "frames/s", "streams": S, "steps": steps,
+           "ms_per_step": ms / steps, "precision": "bf16", "graph": True,
+           "achieved_tflops": flops / (ms / 1e3) / 1e12,
+           "frac_bf16_peak": flops / (ms / 1e3) / PEAK_BF16_MFMA,
+           "gen_s": round(gen_s, 1)}
+    if mixed:
+        out["workload"] = ("F in {257,513,1025}, K ~ U[16,128], b in {32,64,128,256}, "
+                           f"{steps} timed minibatches per stream; {tuned} shapes autotuned")
+    else:
+        out["workload"] = f"{S} streams of F={F} K={K} b={B}, {steps} timed minibatches each"
+    return out
+
+
+def bench_served(bd, synth, torch, np, dev, S, n_chunks, duration_s, threads, seed0):
+    """Continuous batching: S sessions (F in {257,513}, K in {32,64}, BF16
+    products), chunks of U[1,512] frames.  Capacity with every chunk queued at
+    once, then Poisson arrivals at 50% and 90% of it: p50/p99 chunk latency."""
+    rng = np.random.default_rng(seed0)
+    Fs = rng.choice([257, 513], size=S)
+    Ks = rng.choice([32, 64], size=S)
+    pool_n = 16384
+    pools = {}
+    for Fi in (257, 513):
+        V = synth.frames(Fi, 50, pool_n, seed0 + Fi, threads=threads)
+        pools[Fi] = torch.from_numpy(np.ascontiguousarray(V.T)).to(dev)
+    hs = [bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(
+        synth.initial_dictionary(int(Fs[i]), int(Ks[i]), seed0 + i).T)).to(dev), 512,
+        precision="bf16") for i in range(S)]
+
+    def chunk(i, L):
+        o = int(rng.integers(0, pool_n - L))
+        return pools[int(Fs[i])][o:o + L]
+
+    def run(arrivals, sess, lens):
+        srv = bd.Server(max_sessions=S, max_per_step=S, max_frames=1 << 16, inflight=2)
+        ids = [srv.open(h) for h in hs]
+        chunks = [chunk(int(sx), int(L)) for sx, L in zip(sess, lens)]
+        t0 = bd.Server.clock()
+        k = 0
+        n = len(arrivals)
+        while k < n:
+            now = bd.Server.clock() - t0
+            while k < n and arrivals[k] <= now:
+                srv.submit(ids[int(sess[k])], chunks[k], t0 + arrivals[k])
+                k += 1
+            srv.pump()
+        srv.drain()
+        r = srv.results(1 << 20)
+        lat = (r["done"] - r["arrival"]) * 1e3
+        span = r["done"].max() - (t0 + arrivals[0])
+        steps, frames = srv.stats()
+        srv.close()
+        return {"frames_per_s": frames / span, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "chunks": int(n), "steps": steps}
+
+    lens = rng.integers(1, 513, size=n_chunks)
+    sess = rng.integers(0, S, size=n_chunks)
+    cap = run(np.zeros(n_chunks), sess, lens)
+    out = {"sessions": S, "precision": "bf16", "chunk_frames": "U[1,512]",
+           "capacity": cap}
+    for load in (0.5, 0.9):
+        rate = load * cap["frames_per_s"] / lens.mean()          # chunks per second
+        n = max(64, int(rate * duration_s))
+        l2 = rng.integers(1, 513, size=n)
+        s2 = rng.integers(0, S, size=n)
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        arr -= arr[0]
+        out[f"load_{int(load * 100)}"] = run(arr, s2, l2)
+    for h in hs:
+        h.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +223,12 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=2011)
+    ap.add_argument("--batch-streams", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=8)
+    ap.add_argument("--serve-sessions", type=int, default=1024)
+    ap.add_argument("--serve-chunks", type=int, default=4096)
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and served forms")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic, to scale rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
@@ -210,6 +344,20 @@ def main() -> int:
     torch.cuda.synchronize()
     plain_fps = p_steps * B / (e0.elapsed_time(e1) / 1e3)
     gp.close()
+
+    if not args.no_forms:
+        thr = cpu_threads()
+        forms["batched_uniform"] = bench_batched(bd, synth, torch, np, dev, args.batch_streams,
+                                                 args.batch_steps, thr, False, 70000)
+        print(f"[bench] batched uniform: {forms['batched_uniform']['value']:.4g} frames/s",
+              file=sys.stderr, flush=True)
+        forms["batched_mixed"] = bench_batched(bd, synth, torch, np, dev, args.batch_streams,
+                                               max(2, args.batch_steps // 2), thr, True, 80000)
+        print(f"[bench] batched mixed: {forms['batched_mixed']['value']:.4g} frames/s",
+              file=sys.stderr, flush=True)
+        forms["served"] = bench_served(bd, synth, torch, np, dev, args.serve_sessions,
+                                       args.serve_chunks, args.serve_seconds, thr, 90000)
+        print(f"[bench] served: {forms['served']}", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
