@@ -4,7 +4,8 @@
 Workload: one pass of online IS-NMF (Algorithm 1 with mini-batches, fresh
 restarts) over N = 1,000,000 synthetic Gamma/Exponential power-spectrogram
 frames, F = 513, K = 50, minibatch b = 128, I = 20 multiplicative updates of
-h per frame, FP32 fused MFMA path.  A "step" is one isnmf_online_step: the
+h per frame, FP32 fused path (the fit variant, MFMA tile or VALU, chosen by
+the library's autotuner before timing).  A "step" is one isnmf_online_step: the
 inner fit of the minibatch, the fold into A and B, W = sqrt(A/B) and the
 column rescaling.  V is resident in HBM before the timed region starts.
 
@@ -28,27 +29,49 @@ if ROOT not in sys.path:
 METRIC = "online IS-NMF frames/s at F=513,K=50 vs plain FP32; p99 chunk latency"
 F, K, B, ITERS = 513, 50, 128, 20
 PEAK_FP32_MFMA = 157.3e12        # MI355X dense FP32 matrix peak, FLOP/s
+PEAK_FP32_VECTOR = 157.3e12      # MI355X FP32 vector peak (packed FMA), FLOP/s
+# FP32 FMA without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+PEAK_FP32_VALU_UNPACKED = 256 * 4 * 16 * 2 * 2.4e9
 
 
 def flops_per_frame(F: int, K: int, iters: int) -> float:
-    """Algorithmic flops of one frame: I+1 model products W h, I pairs
-    W^T r2, W^T r1, and the rank-1 increments of A and B: (3I + 3) F K MACs."""
+    """Algorithmic flops of one frame's whole step: I+1 model products W h,
+    I pairs W^T r2, W^T r1, and the rank-1 increments of A and B:
+    (3I + 3) F K multiply-adds."""
     return 2.0 * (3 * iters + 3) * F * K
 
 
+def fit_flops_per_frame(F: int, K: int, iters: int) -> float:
+    """Flops of one frame inside the fit kernel alone: I+1 model products and
+    I pairs of transposed products, (3I + 1) F K multiply-adds."""
+    return 2.0 * (3 * iters + 1) * F * K
+
+
 # HBM traffic of the fit kernel measured with rocprofv3 --pmc (FETCH_SIZE,
-# WRITE_SIZE), keyed by the sha1 of the kernel source it was measured on.
-# A changed kernel has no entry, and its traffic is reported as null.
-TRAFFIC = {
-    # FETCH_SIZE 707.9 KiB x 2.0 + WRITE_SIZE 547.0 KiB x 1.0 per b=128 launch
-    # (profiles/fused_fit_F513_K50_b128_pmc.md)
-    "69c549109c00391bd413404f3696582ba3f5306d": 1962.8 * 1024,
+# WRITE_SIZE), keyed by (kernel, sha1 of the sources it was built from).  A
+# changed kernel has no entry and its traffic is reported as null.
+FIT_SOURCES = {
+    "valu": ("fit_valu.hip",),
+    "mfma": ("fit_body.h", "fit_launch.h", "fit_f32.hip"),
 }
+TRAFFIC = {}
 
 
-def _src_hash() -> str:
-    p = os.path.join(ROOT, "paper_1106_4198_amd", "csrc", "fused.hip")
-    return hashlib.sha1(open(p, "rb").read()).hexdigest()
+def _src_hash(kind: str) -> str:
+    h = hashlib.sha1()
+    for name in FIT_SOURCES[kind]:
+        with open(os.path.join(ROOT, "paper_1106_4198_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def fit_kernel_name(nw: int, cpw: int, kmax: int, wg: int) -> tuple:
+    """(kind, kernel symbol) of the tuned FP32 fit variant for (F, K)."""
+    if cpw == 0:
+        ck = {1: 1, 2: 2, 3: 3, 4: 4, 5: 5, 6: 7, 7: 7, 8: 8}[(K + 7) // 8]
+        rf = next(r for r in (1, 2, 3, 5, 9, 17) if (F + 63) // 64 <= r)
+        return "valu", f"fit_valu_kernel<{ck},{rf}>"
+    return "mfma", f"fit_single_kernel<{nw},{cpw},{kmax},0,{bool(wg)}>"
 
 
 def cpu_threads() -> int:
@@ -271,7 +294,12 @@ def main() -> int:
     print(f"[bench] data ready: N={N} F={F} ({Vt.numel() * 4 / 2**30:.2f} GiB) in {gen_s:.1f} s",
           file=sys.stderr, flush=True)
 
-    # warm-up on a scratch stream state
+    # pick the FP32 fit variant for this shape (MFMA tile or VALU), then warm up
+    tuned_v, tuned_us = bd.autotune(F, K, B, precision="fp32", inner_iters=ITERS, trials=20)
+    nw, cpw, wg = bd.tune_get(F, K, "fp32")
+    kind, kname = fit_kernel_name(nw, cpw, 52, wg)
+    print(f"[bench] autotuned FP32 fit: {kname} ({tuned_us:.1f} us per launch)", file=sys.stderr,
+          flush=True)
     g = bd.OnlineISNMF(Wt, B, inner_iters=ITERS)
     assert g.kernel_used == "fused"
     if args.warmup > 0:
@@ -303,14 +331,19 @@ def main() -> int:
     g.run_pass(Vt[:nframes], B)
     launches, fit_ms = g.timing()
     g.close()
-    fit_flops = flops_per_frame(F, K, ITERS) * nframes
+    fit_flops = fit_flops_per_frame(F, K, ITERS) * nframes
     achieved = fit_flops / (fit_ms / 1e3)
-    traffic = TRAFFIC.get(_src_hash())
-    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": traffic,
-                "kernel": "fused_fit_kernel<8,1,52>", "launches": launches,
+    traffic = TRAFFIC.get((kname, _src_hash(kind)))
+    peak = PEAK_FP32_VECTOR if kind == "valu" else PEAK_FP32_MFMA
+    roofline = {"bound": "alu" if kind == "valu" else "mfma", "achieved": achieved / 1e12,
+                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": traffic, "kernel": kname, "launches": launches,
                 "avg_launch_us": fit_ms * 1e3 / max(launches, 1),
-                "flops_per_launch": flops_per_frame(F, K, ITERS) * B}
+                "flops_per_launch": fit_flops_per_frame(F, K, ITERS) * B}
+    if kind == "valu":
+        # one frame per workgroup: b = 128 workgroups on 128 of the 256 CUs
+        roofline["peak_unpacked_fp32"] = PEAK_FP32_VALU_UNPACKED / 1e12
+        roofline["cus_used"] = min(B, 256)
 
     # precision forms: BF16 / FP16 products, same stream prefix
     def time_form(precision, nsteps):
@@ -373,8 +406,9 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"online IS-NMF one pass, fresh restarts: F={F} K={K} "
-                               f"N={nframes} frames b={B} I={ITERS}, fused FP32 MFMA",
+                               f"N={nframes} frames b={B} I={ITERS}, fused FP32 ({kname})",
                    "F": F, "K": K, "b": B, "inner_iters": ITERS, "frames": nframes,
+                   "fit_variant": kname,
                    "generator": "V=(W_true H_true)*E, W_true~Gamma(0.5), H_true~Gamma(0.3), "
                                 "E~Exp(1), seeded PCG64"},
         "roofline": roofline,

@@ -78,6 +78,10 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
     t.W16c = (uint16_t *)take((size_t)K * FR * 2);
     t.w16_kind = prec_code(p);
     t.wexp = (int)lrint(log2((double)F));
+    // register-order copy for the VALU fit variant (FP32 shapes it covers)
+    const bool wv = p.precision == ISNMF_FP32 && valu_class(F, K).ok;
+    t.Wv = wv ? (float *)take(wv_floats(F, K) * 4) : nullptr;
+    t.wv_ck = (K + 7) / 8;
     t.A = (double *)take(fk * 8);
     t.B = (double *)take(fk * 8);
     t.Wn = (double *)take(fk * 8);
@@ -100,7 +104,7 @@ int use_fused(const isnmf_params &p, int F, int K) {
     return fused_supported(F, K, prec_code(p)) ? 1 : 0;
 }
 
-// Zero the 16-bit copies once (their padding rows/columns are never written),
+// Zero the 16-bit and register-order copies once (their padding is never written),
 // then write W into every copy.
 hipError_t init_w(const OnlineDev &d, const float *W, int ldw, hipStream_t s) {
     hipError_t e = hipSuccess;
@@ -108,6 +112,7 @@ hipError_t init_w(const OnlineDev &d, const float *W, int ldw, hipStream_t s) {
         e = hipMemsetAsync(d.W16r, 0, (size_t)d.F * d.KP * 2, s);
         if (e == hipSuccess) e = hipMemsetAsync(d.W16c, 0, (size_t)d.K * d.FR * 2, s);
     }
+    if (d.Wv && e == hipSuccess) e = hipMemsetAsync(d.Wv, 0, wv_floats(d.F, d.K) * 4, s);
     if (e == hipSuccess) e = launch_set_w(d, W, ldw, nullptr, s);
     return e;
 }

@@ -29,6 +29,21 @@ constexpr int TAIL_MAX = 2;
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// Register order of W for the VALU fit (512 threads, thread t = 8p + q holds
+// W[p + 64r][q + 8c], r < ceil(F/64), c < ck): element e = r ck + c of thread t
+// sits at float index 4 (512 (e / 4) + t) + e mod 4, so each thread reads its
+// elements as float4 and a wave's read is one contiguous 1 KiB block.
+// Entries of rows >= F or columns >= K are zero.
+__host__ __device__ inline size_t wv_index(int f, int k, int ck) {
+    const int e = (f >> 6) * ck + (k >> 3);
+    const int t = ((f & 63) << 3) | (k & 7);
+    return ((size_t)((e >> 2) * 512 + t) << 2) | (size_t)(e & 3);
+}
+inline size_t wv_floats(int F, int K) {
+    const int e = ((F + 63) / 64) * ((K + 7) / 8);
+    return (size_t)512 * 4 * ((e + 3) / 4);
+}
+
 // Device-side state of one online stream (views into the caller's workspace).
 struct OnlineDev {
     int F, K, b_max;
@@ -40,6 +55,8 @@ struct OnlineDev {
     uint16_t *W16c;      // K x FR (column k at k*FR): the same values, column-major
     int w16_kind;        // 0 none, 1 BF16, 2 FP16
     int wexp;            // s = round(log2 F): 16-bit copies hold W * 2^s
+    float *Wv;           // W in the register order of the VALU fit (see wv_index) or null
+    int wv_ck;           // ceil(K / 8): components per thread of that order
     double *A, *B;       // F x K, ld F
     double *Wn;          // F x K: sqrt(A/B) before rescaling
     double *dwpart;      // K: per-column sum of squared change of W
@@ -66,6 +83,7 @@ struct FitDesc {
     const float *W;            // F x K, ld F (FP32 working copy)
     const uint16_t *W16r;      // F x KP, 16-bit W * wscale
     const uint16_t *W16c;      // K x FR, 16-bit W * wscale
+    const float *Wv;           // W in the VALU fit's register order (or null)
     float *Hb;                 // caller's K x b (warm start in / fitted h out) or null
     float *Hi;                 // b x KP internal copy of the fitted h
     float *R1, *R2;            // b x FR
@@ -73,13 +91,19 @@ struct FitDesc {
     int *flags;
 };
 
-// Kernel variant of the fused fit for a shape (see fit_body.h).
+// Kernel variant of the fused fit for a shape: an MFMA tile variant of
+// fit_body.h (cpw >= 1: NW waves x CPW chunks of 64 rows, NF frames per
+// workgroup), or the VALU variant of fit_valu.hip (cpw = 0: one frame per
+// workgroup of nw = 8 waves, rf rows and kmax / 8 components per thread).
 struct FitClass {
     int ok;
     int nw, cpw, kmax, wg;
     int main_chunks, tail;
+    int rf;
 };
 FitClass fit_class(int F, int K, int prec);
+// The VALU variant for (F, K) with FP32 products, or ok = 0.
+FitClass valu_class(int F, int K);
 FitDesc make_fit_desc(const OnlineDev &d, const float *V, int ldv, int b, int iters, double eps,
                       int warm, float *Hb, int ldh);
 
@@ -104,6 +128,11 @@ hipError_t launch_fused_fit(const OnlineDev &d, const FitClass &c, const float *
                             int iters, double eps, int warm, float *Hb, int ldh, int prec,
                             hipStream_t s);
 bool fused_supported(int F, int K, int prec);
+// VALU variant launches (class from valu_class): b frames, or the frames of
+// n batched items of NF frames each.
+hipError_t launch_fit_valu(const FitDesc &a, const FitClass &c, int b, hipStream_t s);
+hipError_t launch_fit_valu_multi(const FitClass &c, const FitDesc *d, const int2 *items, int n,
+                                 const long long *cur, const int *beff, hipStream_t s);
 // Every fit variant valid for the shape (the default first); returns the count.
 int fit_candidates(int F, int K, int prec, FitClass *out, int max_out);
 // The variant the autotuner chose for (F, K, prec, b), or the default.

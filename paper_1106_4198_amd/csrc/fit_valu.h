@@ -1,0 +1,333 @@
+// Latency variant of the fused fit (FP32 products on the VALU): one frame per
+// workgroup.
+//
+// It computes what fit_body.h computes for a frame (the inner problem of
+// Algorithm 1, i.e. the argmin over h of eq. (4), by I multiplicative updates
+// of Section 2.1, then the final model, the ratios 1/x and (eps+v)/x^2 the
+// fold consumes, the frame loss and the fitted h), in the same output layouts.
+// A minibatch of b frames occupies b CUs instead of b/4, which shortens the
+// dependent chain of 2I+1 matrix-vector products when one stream runs alone.
+//
+// Mapping: 512 threads = 64 row groups p x 8 component groups q (q = t & 7,
+// p = t >> 3).  Thread (p, q) keeps W[p + 64r][q + 8c] (r < RF, c < CK) in
+// registers; RF = ceil(F / 64), CK = ceil(K / 8), so only the last row set
+// can be partial and no thread holds a row set that is entirely past F.
+//   x_f          : partial over the thread's components, summed over the 8
+//                  q-lanes of the row with DPP (the same value in all 8);
+//   num_k, den_k : partial over the thread's rows, summed over the wave with
+//                  DPP row_ror 8 and the gfx950 permlane16/permlane32 swaps
+//                  (four values per register afterwards), then over the 8
+//                  waves by the lane owning k (8 + 8 values from LDS).
+// Two workgroup barriers per update.  Every sum has a fixed order, so results
+// are bitwise repeatable and independent of the other frames of a launch.
+#pragma once
+
+#include "common.h"
+#include "devmath.h"
+
+namespace isnmf {
+namespace valu {
+
+constexpr int VT = 512;   // threads per workgroup
+constexpr int KS = 20;    // LDS floats per component: 8 N + 8 D partials, padded
+
+template <int CTRL>
+__device__ inline float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// Sum over the 8 lanes with the same lane >> 3 (identical result in all 8).
+__device__ inline float sum8(float v) {
+    v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);   // row_half_mirror: the other quad of the 8
+    return v;
+}
+
+template <int CTRL>
+__device__ inline double dppd(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)u, CTRL, 0xf, 0xf, false);
+    const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, (uint64_t)hi << 32 | lo);
+}
+
+__device__ inline double join(unsigned lo, unsigned hi) {
+    return __builtin_bit_cast(double, (uint64_t)hi << 32 | lo);
+}
+
+// Sum over the 64 lanes of the wave in a fixed order (every lane gets it):
+// 8-lane groups with DPP, lanes 8 apart, then 16-lane rows and halves with
+// the permlane swaps.
+__device__ inline double wave_sum(double v) {
+    v += dppd<0xB1>(v);
+    v += dppd<0x4E>(v);
+    v += dppd<0x141>(v);
+    v += dppd<0x128>(v);
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    auto l16 = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+    auto h16 = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+    v = join(l16[0], h16[0]) + join(l16[1], h16[1]);
+    u = __builtin_bit_cast(uint64_t, v);
+    auto l32 = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+    auto h32 = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+    return join(l32[0], h32[0]) + join(l32[1], h32[1]);
+}
+
+// a, b -> rows (a0+a1, b0+b1, a2+a3, b2+b3) of 16 lanes each
+__device__ inline float swap16_add(float a, float b) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// a, b -> rows (a0+a2, a1+a3, b0+b2, b1+b3)
+__device__ inline float swap32_add(float a, float b) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+template <int CK, int RF>
+__device__ inline void body(const FitDesc &a, int fr) {
+    constexpr int NV = 2 * CK;              // num/den values per thread
+    constexpr int NG = (CK + 1) / 2;        // registers after the in-wave reduction
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int w = t >> 6;
+    const int q = t & 7;
+    const int p = t >> 3;
+    const int F = a.F, K = a.K;
+    const float eps = a.eps;
+
+    __shared__ float4 red4[8 * CK * KS / 4];   // [k][N 0..7 | D 0..7 | pad] per wave w
+    __shared__ float hsh[8 * CK];
+    __shared__ double lred[8];
+    float *red = reinterpret_cast<float *>(red4);
+
+    // the last row set holds rows p + 64 (RF-1); it has rows below F in wave w
+    // iff 8w + 64 (RF-1) < F (uniform per wave)
+    constexpr int RL = RF - 1;
+    const bool last_live = 8 * w + 64 * RL < F;
+    const bool last_ok = p + 64 * RL < F;
+
+    // W from its register-order copy: one float4 per thread per 4 elements,
+    // contiguous over the workgroup (zero past F and K)
+    constexpr int NE = RF * CK;
+    float wr[RF][CK];
+    {
+        const float4 *wv = reinterpret_cast<const float4 *>(a.Wv);
+#pragma unroll
+        for (int g = 0; g < (NE + 3) / 4; ++g) {
+            const float4 v = wv[g * VT + t];
+            const float e4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (4 * g + j < NE) wr[(4 * g + j) / CK][(4 * g + j) % CK] = e4[j];
+        }
+    }
+    float ve[RF];   // eps + v (0 past F)
+    float vr[RF];
+    int bad = 0;
+#pragma unroll
+    for (int r = 0; r < RF; ++r) {
+        const int f = p + 64 * r;
+        const bool ok = r < RL || last_ok;
+        const float v = ok ? a.V[(size_t)fr * a.ldv + f] : 0.f;
+        bad |= !isfinite(v);
+        vr[r] = v;
+        ve[r] = ok ? eps + v : 0.f;
+    }
+    if (bad) atomicOr(a.flags, FLAG_NONFINITE_V);
+
+    if (t < 8 * CK)   // thread t owns component k = t
+        hsh[t] = t < K ? (a.warm ? a.Hb[(size_t)fr * a.ldh + t] : 1.f) : 0.f;
+    __syncthreads();
+    float hk[CK];
+#pragma unroll
+    for (int c = 0; c < CK; ++c) hk[c] = hsh[q + 8 * c];
+
+    // eps enters the sum once, in the q = 0 lane of each row
+    const float s0 = q == 0 ? eps : 0.f;
+    float x[RF];
+    auto model = [&]() {
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            float s = s0;
+#pragma unroll
+            for (int c = 0; c < CK; ++c) s = fmaf(wr[r][c], hk[c], s);
+            x[r] = sum8(s);
+        }
+        x[RL] = 1.f;
+        if (last_live) {
+            float s = s0;
+#pragma unroll
+            for (int c = 0; c < CK; ++c) s = fmaf(wr[RL][c], hk[c], s);
+            s = sum8(s);
+            x[RL] = last_ok ? s : 1.f;   // rows past F: W = 0 and v' = 0, any x > 0
+        }
+    };
+
+    int guard = 0;
+    for (int it = 0; it < a.iters; ++it) {
+        model();
+        float nd[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) nd[i] = 0.f;
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const float r1 = __builtin_amdgcn_rcpf(x[r]);
+            const float r2 = ve[r] * r1 * r1;
+#pragma unroll
+            for (int c = 0; c < CK; ++c) {
+                nd[2 * c] = fmaf(wr[r][c], r2, nd[2 * c]);
+                nd[2 * c + 1] = fmaf(wr[r][c], r1, nd[2 * c + 1]);
+            }
+        }
+        if (last_live) {
+            const float r1 = __builtin_amdgcn_rcpf(x[RL]);
+            const float r2 = ve[RL] * r1 * r1;
+#pragma unroll
+            for (int c = 0; c < CK; ++c) {
+                nd[2 * c] = fmaf(wr[RL][c], r2, nd[2 * c]);
+                nd[2 * c + 1] = fmaf(wr[RL][c], r1, nd[2 * c + 1]);
+            }
+        }
+        // over the wave: lanes 8 apart, then rows 0+1 / 2+3, then halves
+#pragma unroll
+        for (int i = 0; i < NV; ++i) nd[i] += dpp<0x128>(nd[i]);   // row_ror 8
+        float u[CK];
+#pragma unroll
+        for (int c = 0; c < CK; ++c) u[c] = swap16_add(nd[2 * c], nd[2 * c + 1]);
+        float g4[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) g4[g] = swap32_add(u[2 * g], 2 * g + 1 < CK ? u[2 * g + 1] : 0.f);
+        // register g, row j = lane >> 4 now holds value 4g + j: component
+        // c = 2g + (j >> 1) (k = q + 8c), N for even j and D for odd j
+        if ((lane & 8) == 0) {
+            const int j = lane >> 4;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const int c = 2 * g + (j >> 1);
+                if (c < CK) red[(q + 8 * c) * KS + (j & 1) * 8 + w] = g4[g];
+            }
+        }
+        __syncthreads();
+        if (t < K) {
+            const float4 *pk = red4 + t * (KS / 4);
+            const float4 n0 = pk[0], n1 = pk[1], d0 = pk[2], d1 = pk[3];
+            const float N = ((n0.x + n0.y) + (n0.z + n0.w)) + ((n1.x + n1.y) + (n1.z + n1.w));
+            const float D = ((d0.x + d0.y) + (d0.z + d0.w)) + ((d1.x + d1.y) + (d1.z + d1.w));
+            float h = hsh[t];
+            if (D > 0.f && N >= 0.f)
+                h *= __builtin_amdgcn_sqrtf(N * __builtin_amdgcn_rcpf(D));
+            else
+                guard = 1;
+            hsh[t] = h;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CK; ++c) hk[c] = hsh[q + 8 * c];
+    }
+    if (guard) atomicOr(a.flags, FLAG_GUARD_H);
+
+    // final model; ratios for the fold and the frame loss.  Lane q takes row
+    // set q (and q + 8), so each lane evaluates the loss term of at most two
+    // rows and the 8 lanes of a row group cover its row sets without overlap.
+    model();
+    double lsum = 0.0;
+    auto finish_row = [&](int base) {
+        float xs = 1.f, vs = 0.f, es = 0.f;
+#pragma unroll
+        for (int r = base; r < RF && r < base + 8; ++r)
+            if ((r & 7) == q) {
+                xs = x[r];
+                vs = vr[r];
+                es = ve[r];
+            }
+        const int r = base + q;
+        const int f = p + 64 * r;
+        if (r < RL || (r == RL && last_ok)) {
+            const float ir = __builtin_amdgcn_rcpf(xs);
+            a.R1[(size_t)fr * a.FR + f] = ir;
+            a.R2[(size_t)fr * a.FR + f] = es * ir * ir;
+            lsum += dis_term(a.epsd + double(vs), double(xs));
+        }
+    };
+    finish_row(0);
+    if (RF > 8 && (RF > 9 || last_live)) finish_row(8);
+    if (RF > 16 && last_live) finish_row(16);
+    lsum = wave_sum(lsum);
+    if (lane == 0) lred[w] = lsum;
+    __syncthreads();
+    if (t == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) s += lred[v];
+        a.lossf[fr] = s;
+    }
+    if (t < K) {
+        a.Hi[(size_t)fr * a.KP + t] = hsh[t];
+        if (a.Hb) a.Hb[(size_t)fr * a.ldh + t] = hsh[t];
+    }
+}
+
+template <int CK, int RF>
+__global__ __launch_bounds__(VT) void fit_valu_kernel(FitDesc a) {
+    body<CK, RF>(a, blockIdx.x);
+}
+
+// Batched form: item = (stream, tile of NF frames); workgroup NF*i + j fits
+// frame j of item i; frames past the stream's minibatch of this step exit.
+template <int CK, int RF>
+__global__ __launch_bounds__(VT) void fit_valu_multi_kernel(const FitDesc *__restrict__ descs,
+                                                            const int2 *__restrict__ items,
+                                                            const long long *__restrict__ cursor,
+                                                            const int *__restrict__ beff) {
+    const int2 it = items[blockIdx.x / NF];
+    const int fr = it.y * NF + (int)(blockIdx.x % NF);
+    const int b = beff[it.x];
+    if (fr >= b) return;   // uniform per workgroup
+    FitDesc a = descs[it.x];
+    const long long c = cursor[it.x];
+    a.b = b;
+    a.V += c * a.ldv;
+    if (a.Hb) a.Hb += c * a.ldh;
+    body<CK, RF>(a, fr);
+}
+
+// Launch of the (CK, rf) instance, rf = 1..17: b frames of *a (d = nullptr),
+// or the frames of n batched items of d.  Explicitly instantiated per CK in
+// fit_valu_ck*.hip, so the instances build in parallel.
+template <int CK>
+hipError_t launch_any(const FitDesc *a, int rf, int b, const FitDesc *d, const int2 *items, int n,
+                      const long long *cur, const int *beff, hipStream_t s) {
+    switch (rf) {
+#define ISNMF_VALU_RF(RF)                                                             \
+    case RF:                                                                          \
+        if (d)                                                                        \
+            fit_valu_multi_kernel<CK, RF><<<n * NF, VT, 0, s>>>(d, items, cur, beff); \
+        else                                                                          \
+            fit_valu_kernel<CK, RF><<<b, VT, 0, s>>>(*a);                             \
+        break;
+        ISNMF_VALU_RF(1) ISNMF_VALU_RF(2) ISNMF_VALU_RF(3) ISNMF_VALU_RF(4)
+        ISNMF_VALU_RF(5) ISNMF_VALU_RF(6) ISNMF_VALU_RF(7) ISNMF_VALU_RF(8)
+        ISNMF_VALU_RF(9) ISNMF_VALU_RF(10) ISNMF_VALU_RF(11) ISNMF_VALU_RF(12)
+        ISNMF_VALU_RF(13) ISNMF_VALU_RF(14) ISNMF_VALU_RF(15) ISNMF_VALU_RF(16)
+        ISNMF_VALU_RF(17)
+#undef ISNMF_VALU_RF
+        default:
+            return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+#define ISNMF_VALU_EXTERN(CKV)                                                                  \
+    extern template hipError_t launch_any<CKV>(const FitDesc *, int, int, const FitDesc *,     \
+                                               const int2 *, int, const long long *, const int *, \
+                                               hipStream_t);
+#define ISNMF_VALU_INSTANTIATE(CKV)                                                      \
+    template hipError_t launch_any<CKV>(const FitDesc *, int, int, const FitDesc *,     \
+                                        const int2 *, int, const long long *, const int *, \
+                                        hipStream_t);
+
+}  // namespace valu
+}  // namespace isnmf

@@ -8,6 +8,9 @@
 //   chunks 9..16, 16-bit:     K <= 64: 8 waves x 2 chunks, W in registers;
 //                             K > 64:  16 waves x 1 chunk, W read from its
 //                             16-bit copies in L2 (too large for registers)
+//   FP32, F <= 1088, K <= 64: the VALU variant (one frame per workgroup) where
+//                             no MFMA tile fits, and as a tuning candidate
+//                             elsewhere
 #include <math.h>
 
 #include "common.h"
@@ -26,7 +29,7 @@ int kclass(int K, int prec) {
 }  // namespace
 
 FitClass fit_class(int F, int K, int prec) {
-    FitClass c = {0, 0, 0, 0, 0, 0, 0};
+    FitClass c = {};
     if (F < 1 || K < 1) return c;
     c.main_chunks = F / CHUNK;
     c.tail = F % CHUNK;
@@ -54,6 +57,8 @@ FitClass fit_class(int F, int K, int prec) {
         }
         c.ok = 1;
     }
+    // FP32 beyond the register-resident MFMA tiles: one frame per workgroup
+    if (!c.ok && prec == 0) return valu_class(F, K);
     return c;
 }
 
@@ -67,6 +72,10 @@ int fit_candidates(int F, int K, int prec, FitClass *out, int max_out) {
         if (n < max_out) out[n++] = c;
     };
     add(d);
+    if (prec == 0 && d.cpw != 0) {   // the VALU variant, when the default is an MFMA tile
+        const FitClass v = valu_class(F, K);
+        if (v.ok) add(v);
+    }
     if (prec != 0 && d.kmax <= 64) {
         const int nch = d.main_chunks < 1 ? 1 : d.main_chunks;
         if (nch > 4 && nch <= 8) {   // 4 waves x 2 chunks instead of 8 x 1
@@ -109,6 +118,7 @@ FitDesc make_fit_desc(const OnlineDev &d, const float *V, int ldv, int b, int it
     a.W = d.W32;
     a.W16r = d.W16r;
     a.W16c = d.W16c;
+    a.Wv = d.Wv;
     a.Hb = Hb;
     a.Hi = (float *)d.Hi;
     a.R1 = (float *)d.R1;
@@ -123,6 +133,7 @@ hipError_t launch_fused_fit(const OnlineDev &d, const FitClass &c, const float *
                             hipStream_t s) {
     if (!c.ok) return hipErrorNotSupported;
     const FitDesc a = make_fit_desc(d, V, ldv, b, iters, eps, warm, Hb, ldh);
+    if (c.cpw == 0) return prec == 0 ? launch_fit_valu(a, c, b, s) : hipErrorNotSupported;
     const int grid = (b + NF - 1) / NF;
     if (prec == 1) return launch_fit_single_p<1>(a, c, grid, s);
     if (prec == 2) return launch_fit_single_p<2>(a, c, grid, s);

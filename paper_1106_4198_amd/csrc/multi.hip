@@ -166,7 +166,9 @@ hipError_t enqueue_step(isnmf_multi *m, hipStream_t s) {
     prepare_kernel<<<blocks, 256, 0, s>>>(m->S, m->d_b, m->d_nf, m->d_cursor, m->d_beff);
     for (const auto &g : m->groups) {
         hipError_t e;
-        if (g.prec == 1)
+        if (g.c.cpw == 0)
+            e = launch_fit_valu_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
+        else if (g.prec == 1)
             e = launch_fit_multi_p<1>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
         else if (g.prec == 2)
             e = launch_fit_multi_p<2>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
@@ -217,6 +219,7 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         if (p.h_init == ISNMF_H_WARM) return ISNMF_EINVAL;            // fresh restarts only
         if (isnmf_handle_kernel(handles[s]) != ISNMF_KERNEL_FUSED) return ISNMF_EUNSUPPORTED;
         if (b[s] > 512) return ISNMF_EUNSUPPORTED;                   // single fold slice
+        if (isnmf_handle_class(handles[s])->cpw == 0 && !d.Wv) return ISNMF_EUNSUPPORTED;
         for (int r = 0; r < s; ++r)
             if (handles[r] == handles[s]) return ISNMF_EINVAL;        // one entry per stream
     }
@@ -251,7 +254,7 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
     std::vector<int2> items;
     items.reserve(nitems);
     // fit items grouped by (variant, precision)
-    std::vector<std::pair<std::tuple<int, int, int, int, int>, std::vector<int2>>> groups;
+    std::vector<std::pair<std::tuple<int, int, int, int, int, int>, std::vector<int2>>> groups;
     for (int s = 0; s < S; ++s) {
         const OnlineDev &d = *isnmf_handle_dev(handles[s]);
         const isnmf_params &p = *isnmf_handle_params(handles[s]);
@@ -260,7 +263,7 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         fold[s] = fold_args(d, b[s], p.rho, p.update_w, nullptr, d_loss ? d_loss + s : nullptr);
         rs[s] = rescale_args(d, p.normalize, 0, nullptr, d.K);
         upd[s] = p.update_w;
-        const auto key = std::make_tuple(c.nw, c.cpw, c.kmax, c.wg, prec_of(p));
+        const auto key = std::make_tuple(c.nw, c.cpw, c.kmax, c.wg, c.rf, prec_of(p));
         size_t gi = 0;
         while (gi < groups.size() && groups[gi].first != key) ++gi;
         if (gi == groups.size()) groups.push_back({key, {}});
@@ -269,7 +272,7 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
     for (auto &g : groups) {
         isnmf_multi::Group G;
         G.c = *isnmf_handle_class(handles[g.second.front().x]);
-        G.prec = std::get<4>(g.first);
+        G.prec = std::get<5>(g.first);
         G.off = (int)items.size();
         G.n = (int)g.second.size();
         items.insert(items.end(), g.second.begin(), g.second.end());

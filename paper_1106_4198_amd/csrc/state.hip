@@ -62,7 +62,7 @@ __global__ void dw_total_kernel(int K, const double *__restrict__ dwpart, int up
 
 __global__ void set_w_kernel(int F, int K, const float *__restrict__ W, int ldw,
                              const double *__restrict__ Wd, double *__restrict__ W64,
-                             float *__restrict__ W32, W16Out w16) {
+                             float *__restrict__ W32, W16Out w16, WvOut wv) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)F * K) return;
     const int f = (int)(e % F);
@@ -71,6 +71,7 @@ __global__ void set_w_kernel(int F, int K, const float *__restrict__ W, int ldw,
     W64[e] = v;
     W32[e] = float(v);
     store_w16(w16, f, k, v);
+    store_wv(wv, f, k, v);
 }
 
 __global__ void loss_total_kernel(const double *__restrict__ lossf, int b,
@@ -116,7 +117,7 @@ hipError_t launch_set_w(const OnlineDev &d, const float *W, int ldw, const doubl
                         hipStream_t s) {
     const long n = (long)d.F * d.K;
     set_w_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(d.F, d.K, W, ldw, W64, d.W64, d.W32,
-                                                        w16_out(d));
+                                                        w16_out(d), wv_out(d));
     return hipGetLastError();
 }
 

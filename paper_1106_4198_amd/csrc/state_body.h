@@ -30,6 +30,16 @@ __device__ inline void store_w16(const W16Out &o, int f, int k, double w) {
     o.c[(size_t)k * o.FR + f] = b;
 }
 
+// The VALU fit's register-order copy of W (null when the handle has none).
+struct WvOut {
+    float *p;
+    int ck;
+};
+
+__device__ inline void store_wv(const WvOut &o, int f, int k, double w) {
+    if (o.p) o.p[wv_index(f, k, o.ck)] = float(w);
+}
+
 // Sum over a 256-thread block in a fixed order: per-wave xor butterfly (the
 // same value in every lane), then the four wave sums in index order.
 __device__ inline double block_sum256(double v, double *red4) {
@@ -47,6 +57,7 @@ struct RescaleArgs {
     double *W64;
     float *W32;
     W16Out w16;
+    WvOut wv;
     double *A, *B;
     int normalize, warm;
     float *Hb;      // warm-start activations to compensate (or null)
@@ -97,6 +108,7 @@ __device__ __forceinline__ void rescale_body(const RescaleArgs &a, int k, int b)
             a.W64[col + f] = w;
             a.W32[col + f] = float(w);
             store_w16(a.w16, f, k, w);
+            store_wv(a.wv, f, k, w);
             if (a.normalize) {
                 a.A[col + f] = av[r] / scale;
                 a.B[col + f] = bv[r] * scale;
@@ -110,6 +122,7 @@ __device__ __forceinline__ void rescale_body(const RescaleArgs &a, int k, int b)
         a.W64[col + f] = w;
         a.W32[col + f] = float(w);
         store_w16(a.w16, f, k, w);
+        store_wv(a.wv, f, k, w);
         if (a.normalize) {
             a.A[col + f] /= scale;
             a.B[col + f] *= scale;
@@ -132,6 +145,8 @@ inline W16Out w16_out(const OnlineDev &d) {
     return o;
 }
 
+inline WvOut wv_out(const OnlineDev &d) { return WvOut{d.Wv, d.wv_ck}; }
+
 inline RescaleArgs rescale_args(const OnlineDev &d, int normalize, int warm, float *Hb, int ldh) {
     RescaleArgs a;
     a.F = d.F;
@@ -140,6 +155,7 @@ inline RescaleArgs rescale_args(const OnlineDev &d, int normalize, int warm, flo
     a.W64 = d.W64;
     a.W32 = d.W32;
     a.w16 = w16_out(d);
+    a.wv = wv_out(d);
     a.A = d.A;
     a.B = d.B;
     a.normalize = normalize;

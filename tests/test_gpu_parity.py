@@ -6,6 +6,7 @@ Tolerances (norm-wise and elementwise, see helpers.assert_close):
   FP32 path, one step from identical state:           1e-5  (W, A, B, H)
   full pass, running loss and final objective:        1e-3
 """
+import contextlib
 import sys
 
 import numpy as np
@@ -128,6 +129,69 @@ def test_step_fp32_variants(kernel):
     compare_step(130, 10, 11, 6, "fp32", kernel, seed=24, tol=1e-5, normalize=False)
     compare_step(130, 10, 11, 6, "fp32", kernel, seed=25, tol=1e-5, update_w=False)
     compare_step(130, 10, 5, 6, "fp32", kernel, seed=26, tol=1e-5, b_max=16)   # ragged batch
+
+
+# ---------------------------------------------------------------- one step, FP32 VALU variant
+
+@contextlib.contextmanager
+def valu_variant(F, K):
+    """Handles of shape (F, K) created inside use the VALU fit variant (the
+    default for FP32 where no MFMA tile fits, a tuning entry elsewhere)."""
+    bd.tune_clear()
+    if bd.tune_get(F, K, "fp32")[1] != 0:
+        bd.tune_set(F, K, "fp32", 8, 0, 0)
+    assert bd.tune_get(F, K, "fp32") == (8, 0, 0)
+    try:
+        yield
+    finally:
+        bd.tune_clear()
+
+
+@pytest.mark.parametrize("F,K,b", [(129, 8, 1), (513, 50, 128), (257, 64, 7), (65, 16, 9),
+                                   (64, 3, 4), (68, 33, 6), (3, 2, 5), (200, 52, 13),
+                                   (1025, 40, 33), (1088, 64, 5), (700, 57, 10), (1025, 1, 3),
+                                   (577, 24, 4)])
+def test_step_fp32_valu(F, K, b):
+    with valu_variant(F, K):
+        compare_step(F, K, b, 20, "fp32", "fused", seed=27, tol=1e-5)
+
+
+def test_step_fp32_valu_variants():
+    with valu_variant(130, 10):
+        compare_step(130, 10, 11, 6, "fp32", "fused", seed=22, tol=1e-5, warm=True)
+        compare_step(130, 10, 11, 6, "fp32", "fused", seed=23, tol=1e-5, rho=0.7)
+        compare_step(130, 10, 11, 6, "fp32", "fused", seed=24, tol=1e-5, normalize=False)
+        compare_step(130, 10, 11, 6, "fp32", "fused", seed=25, tol=1e-5, update_w=False)
+        compare_step(130, 10, 5, 6, "fp32", "fused", seed=26, tol=1e-5, b_max=16)
+        compare_step(130, 10, 5, 0, "fp32", "fused", seed=28, tol=1e-5)
+
+
+def test_valu_large_config_and_repeatability():
+    """The benchmark shape with the VALU variant (full and ragged minibatch),
+    and two identical runs giving identical bits."""
+    with valu_variant(513, 50):
+        compare_step(513, 50, 128, 20, "fp32", "fused", seed=51, tol=1e-5, steps_before=3)
+        compare_step(513, 50, 64, 20, "fp32", "fused", seed=52, tol=1e-5, steps_before=3, b_max=128)
+        V, W0 = synth.problem(513, 50, 256, seed=53)
+        Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+        outs = []
+        for _ in range(2):
+            g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), 128)
+            H = torch.zeros((128, 50), dtype=torch.float32, device=DEV)
+            for s in range(2):
+                g.step(Vt[128 * s:128 * (s + 1)], H)
+            outs.append((g.get_w64(), H.clone()))
+            g.close()
+        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_fp32_wide_F_uses_the_valu_variant():
+    W0 = torch.rand((40, 1025), dtype=torch.float32, device=DEV) + 0.5
+    g = bd.OnlineISNMF(W0, 4, kernel="auto")
+    assert g.kernel_used == "fused"
+    assert bd.tune_get(1025, 40, "fp32") == (8, 0, 0)
+    W0 = torch.rand((40, 1089), dtype=torch.float32, device=DEV) + 0.5
+    assert bd.OnlineISNMF(W0, 4, kernel="auto").kernel_used == "plain"
 
 
 def test_auto_falls_back_to_plain_for_wide_K():

@@ -102,3 +102,16 @@ def test_admission_by_hbm_footprint():
     with pytest.raises(bd.IsnmfError):
         srv.submit(0, torch.rand((300, 257), device=DEV))   # above max_frames
     srv.close()
+
+
+def test_served_form_rejects_the_valu_variant():
+    """The served form runs MFMA tile variants only; a handle whose fit is the
+    one-frame-per-workgroup VALU variant is refused, not silently rerouted."""
+    say("serve rejects VALU")
+    W0 = torch.rand((40, 1025), device=DEV) + 0.5
+    g = bd.OnlineISNMF(W0, 16)   # FP32, F = 1025: the VALU variant
+    srv = bd.Server(max_sessions=2, max_per_step=2, max_frames=64)
+    with pytest.raises(bd.IsnmfError) as ei:
+        srv.open(g)
+    assert ei.value.code == bd.EUNSUPPORTED
+    srv.close()
