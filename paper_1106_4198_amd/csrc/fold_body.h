@@ -26,11 +26,13 @@ __device__ inline floatx4 mfma16(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-__device__ inline void epilogue(const FoldArgs &a, int f, int k, double sa, double sb) {
+// A = rho A + sum_n r2 h W^2, B = rho B + sum_n r1 h (Algorithm 1), W = sqrt(A/B);
+// w, a0, b0: the element's current W, A, B.
+__device__ inline void epilogue(const FoldArgs &a, int f, int k, double sa, double sb, double w,
+                                double a0, double b0) {
     const size_t e = (size_t)f + (size_t)k * a.F;
-    const double w = a.W64[e];
-    const double av = a.rho * a.A[e] + sa * (w * w);
-    const double bv = a.rho * a.B[e] + sb;
+    const double av = a.rho * a0 + sa * (w * w);
+    const double bv = a.rho * b0 + sb;
     a.A[e] = av;
     a.B[e] = bv;
     if (a.update_w) {
@@ -61,10 +63,29 @@ __device__ __forceinline__ void fold_tile_body(const FoldArgs &a, int tile, int 
     const int sub = lane >> 4;             // frame within the group of 4
     const bool fok = fa < a.F, kok = kb < a.K;
 
-    if (a.d_loss_sum && tile == 0 && slice == 0 && threadIdx.x == 0) {
+    // epilogue operands (wave 0 only), loaded before the frame rounds
+    const int kc = k0 + (lane & 15);
+    double wq[4], aq[4], bq[4];
+    if (w == 0 && nslices == 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = f0 + 4 * sub + r;
+            const bool ok = f < a.F && kc < a.K;
+            const size_t e = ok ? (size_t)f + (size_t)kc * a.F : 0;
+            wq[r] = ok ? a.W64[e] : 0.0;
+            aq[r] = ok ? a.A[e] : 0.0;
+            bq[r] = ok ? a.B[e] : 0.0;
+        }
+    }
+
+    // minibatch loss: wave 1 of tile 0, lane l sums frames l, l + 64, ... in
+    // order, then a fixed xor butterfly over the lanes
+    if (a.d_loss_sum && tile == 0 && slice == 0 && w == 1) {
         double s = 0.0;
-        for (int n = 0; n < a.b; ++n) s += a.lossf[n];
-        *a.d_loss_sum += s;
+        for (int n = lane; n < a.b; n += 64) s += a.lossf[n];
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) s += __shfl_xor(s, m, 64);
+        if (lane == 0) *a.d_loss_sum += s;
     }
 
     floatx4 ca = {0.f, 0.f, 0.f, 0.f}, cb = {0.f, 0.f, 0.f, 0.f};
@@ -91,12 +112,12 @@ __device__ __forceinline__ void fold_tile_body(const FoldArgs &a, int tile, int 
     if (w != 0) return;
     ca = ((red[0][0][lane] + red[1][0][lane]) + red[2][0][lane]) + red[3][0][lane];
     cb = ((red[0][1][lane] + red[1][1][lane]) + red[2][1][lane]) + red[3][1][lane];
-    const int kc = k0 + (lane & 15);
     if (nslices == 1) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int f = f0 + 4 * sub + r;
-            if (f < a.F && kc < a.K) epilogue(a, f, kc, double(ca[r]), double(cb[r]));
+            if (f < a.F && kc < a.K)
+                epilogue(a, f, kc, double(ca[r]), double(cb[r]), wq[r], aq[r], bq[r]);
         }
     } else {
         const size_t fk = (size_t)a.F * a.K;

@@ -74,13 +74,16 @@ __global__ void set_w_kernel(int F, int K, const float *__restrict__ W, int ldw,
     store_wv(wv, f, k, v);
 }
 
+// Same order as the MFMA fold's loss sum: lane l adds frames l, l + 64, ...,
+// then a fixed xor butterfly (one wave).
 __global__ void loss_total_kernel(const double *__restrict__ lossf, int b,
                                   double *__restrict__ out) {
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int n = 0; n < b; ++n) s += lossf[n];
-        *out += s;
-    }
+    const int lane = threadIdx.x;
+    double s = 0.0;
+    for (int n = lane; n < b; n += 64) s += lossf[n];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) s += __shfl_xor(s, m, 64);
+    if (lane == 0) *out += s;
 }
 
 }  // namespace
