@@ -51,10 +51,14 @@ def fit_flops_per_frame(F: int, K: int, iters: int) -> float:
 # WRITE_SIZE), keyed by (kernel, sha1 of the sources it was built from).  A
 # changed kernel has no entry and its traffic is reported as null.
 FIT_SOURCES = {
-    "valu": ("fit_valu.hip",),
+    "valu": ("fit_valu.h", "fit_valu.hip"),
     "mfma": ("fit_body.h", "fit_launch.h", "fit_f32.hip"),
 }
-TRAFFIC = {}
+TRAFFIC = {
+    # FETCH_SIZE 709.5 KiB x 2.0 + WRITE_SIZE 552.0 KiB x 1.0 per b=128 launch
+    # (profiles/fit_valu_F513_K50_b128_pmc.md)
+    ("fit_valu_kernel<7,9>", "3a52d33403d73f6b503be659431b0dd019a540e2"): (709.5 * 2.0 + 552.0) * 1024,
+}
 
 
 def _src_hash(kind: str) -> str:
@@ -68,9 +72,7 @@ def _src_hash(kind: str) -> str:
 def fit_kernel_name(nw: int, cpw: int, kmax: int, wg: int) -> tuple:
     """(kind, kernel symbol) of the tuned FP32 fit variant for (F, K)."""
     if cpw == 0:
-        ck = {1: 1, 2: 2, 3: 3, 4: 4, 5: 5, 6: 7, 7: 7, 8: 8}[(K + 7) // 8]
-        rf = next(r for r in (1, 2, 3, 5, 9, 17) if (F + 63) // 64 <= r)
-        return "valu", f"fit_valu_kernel<{ck},{rf}>"
+        return "valu", f"fit_valu_kernel<{(K + 7) // 8},{(F + 63) // 64}>"
     return "mfma", f"fit_single_kernel<{nw},{cpw},{kmax},0,{bool(wg)}>"
 
 
@@ -93,7 +95,7 @@ def cpu_baseline(V, W0, target_s: float):
     t0 = time.perf_counter()
     st.step(V[:, :B].astype(np.float64), iters=ITERS)
     one = time.perf_counter() - t0
-    steps = max(2, min(256, int(target_s / max(one, 1e-3))))
+    steps = max(2, min(2048, int(target_s / max(one, 1e-3))))
     Vs = V[:, :steps * B].astype(np.float64)
     st = oracle.OnlineState(W0.astype(np.float64))
     t0 = time.perf_counter()
