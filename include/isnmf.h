@@ -300,9 +300,12 @@ int isnmf_autotune(int F, int K, int b, const isnmf_params *p, int trials, int *
 /* Read / set / clear the tuning table (for persisting it between processes):
  * nw = waves per workgroup, cpw = 64-row chunks per wave, wg = W read from
  * its 16-bit copies in memory instead of registers.  cpw = 0 denotes the
- * FP32 VALU variant (one frame per workgroup of nw = 8 waves), which the
- * served form does not run (isnmf_server_open returns ISNMF_EUNSUPPORTED for
- * a handle created with it). */
+ * FP32 VALU variant (one frame per workgroup of nw = 8 waves) and cpw = -1
+ * the BF16 16-frame tile variant (16 frames per workgroup of nw waves on
+ * 16x16x32 MFMA); the served form runs neither (isnmf_server_open returns
+ * ISNMF_EUNSUPPORTED for a handle created with them).  The autotuner times
+ * the variants at the b it is given: a single stream's minibatch for
+ * latency, or the frames of all streams of a batched step for throughput. */
 int isnmf_tune_get(int F, int K, int precision, int *nw, int *cpw, int *wg);
 int isnmf_tune_set(int F, int K, int precision, int nw, int cpw, int wg);
 void isnmf_tune_clear(void);

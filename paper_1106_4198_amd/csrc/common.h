@@ -93,8 +93,11 @@ struct FitDesc {
 
 // Kernel variant of the fused fit for a shape: an MFMA tile variant of
 // fit_body.h (cpw >= 1: NW waves x CPW chunks of 64 rows, NF frames per
-// workgroup), or the VALU variant of fit_valu.hip (cpw = 0: one frame per
-// workgroup of nw = 8 waves, rf rows and kmax / 8 components per thread).
+// workgroup), the VALU variant of fit_valu.h (cpw = 0: one frame per
+// workgroup of nw = 8 waves, rf row sets and kmax / 8 components per
+// thread), or the 16-frame tile variant of fit_tile.h (cpw = -1: BF16
+// products, nw = 8 waves of 16 frames each, rf = ceil(F / 32) contraction
+// steps of 32 rows, kmax = 32 ceil(K / 32)).
 struct FitClass {
     int ok;
     int nw, cpw, kmax, wg;
@@ -104,6 +107,8 @@ struct FitClass {
 FitClass fit_class(int F, int K, int prec);
 // The VALU variant for (F, K) with FP32 products, or ok = 0.
 FitClass valu_class(int F, int K);
+// The 16-frame tile variant for (F, K) with BF16 products, or ok = 0.
+FitClass tile_class(int F, int K);
 FitDesc make_fit_desc(const OnlineDev &d, const float *V, int ldv, int b, int iters, double eps,
                       int warm, float *Hb, int ldh);
 
@@ -133,6 +138,12 @@ bool fused_supported(int F, int K, int prec);
 hipError_t launch_fit_valu(const FitDesc &a, const FitClass &c, int b, hipStream_t s);
 hipError_t launch_fit_valu_multi(const FitClass &c, const FitDesc *d, const int2 *items, int n,
                                  const long long *cur, const int *beff, hipStream_t s);
+// 16-frame tile variant launches: b frames, or n batched items (stream, tile of 16 frames).
+hipError_t launch_fit_tile(const FitDesc &a, const FitClass &c, int b, hipStream_t s);
+hipError_t launch_fit_tile_multi(const FitClass &c, const FitDesc *d, const int2 *items, int n,
+                                 const long long *cur, const int *beff, hipStream_t s);
+// Frames per batched work item of a fit class.
+inline int frames_per_item(const FitClass &c) { return c.cpw == -1 ? 128 : NF; }
 // Every fit variant valid for the shape (the default first); returns the count.
 int fit_candidates(int F, int K, int prec, FitClass *out, int max_out);
 // The variant the autotuner chose for (F, K, prec, b), or the default.

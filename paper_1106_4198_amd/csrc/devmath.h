@@ -29,6 +29,37 @@ __device__ inline double dis_term(double y, double x) {
     return d - log(u);
 }
 
+// Sum over the 64 lanes of a wave in a fixed order, the result in every
+// lane: 8-lane groups with DPP (xor 1, xor 2, half-row mirror), lanes 8 apart
+// (row_ror 8), then 16-lane rows and 32-lane halves with the gfx950
+// permlane16/permlane32 swaps.  No LDS and no barrier.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)u, CTRL, 0xf, 0xf, false);
+    const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, (uint64_t)hi << 32 | lo);
+}
+
+__device__ inline double join_f64(unsigned lo, unsigned hi) {
+    return __builtin_bit_cast(double, (uint64_t)hi << 32 | lo);
+}
+
+__device__ inline double wave_sum_f64(double v) {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x128>(v);
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    auto l16 = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+    auto h16 = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+    v = join_f64(l16[0], h16[0]) + join_f64(l16[1], h16[1]);
+    u = __builtin_bit_cast(uint64_t, v);
+    auto l32 = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+    auto h32 = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+    return join_f64(l32[0], h32[0]) + join_f64(l32[1], h32[1]);
+}
+
 // Sum over the 16 lanes that share (lane & 3): xor butterfly over lane bits
 // 2..5.  Every lane of the group ends with the same, order-independent value.
 __device__ inline double sum_over_quads(double v) {

@@ -1,0 +1,367 @@
+// Throughput variant of the fused fit for BF16 products: each wave fits 16
+// frames on v_mfma_f32_16x16x32_bf16, 8 waves (128 frames) per workgroup.
+//
+// It computes what fit_body.h computes (the inner problem of Algorithm 1: I
+// multiplicative updates of Section 2.1, then the final model, the ratios
+// 1/x and (eps+v)/x^2 for the fold, the frame loss and the fitted h), with
+// the three products of an update as matrix-matrix products whose N
+// dimension is a wave's 16 frames:
+//   X   [F x 16] = W [F x K] . H [K x 16]        (M = rows, K = components)
+//   NUM [K x 16] = W^T [K x F] . R2 [F x 16]     (M = components, K = rows)
+//   DEN [K x 16] = W^T [K x F] . R1 [F x 16]
+// A wave owns all rows and components of its frames, so an update needs no
+// exchange with other waves: the X accumulators become the B operand of
+// NUM/DEN in registers, and the NUM/DEN accumulators become the B operand of
+// the next X.  That works because an MFMA sums over its K index in whatever
+// order the (lane, slot) pairs give: the rows of a 32-row contraction step
+// are taken in the order the X accumulators of tiles 2s and 2s+1 hold them
+// (lane (g, n), slot j < 4 -> row 32s + 4g + j, slot j >= 4 -> row 32s + 16 +
+// 4g + j - 4), the components of a 32-component step in the order the
+// NUM/DEN accumulators of m-tiles 2c and 2c+1 hold them (the same pattern),
+// and both W operands are stored in LDS in those orders.
+//
+// W enters as the 16-bit copies W * 2^s and h as h * 2^-s, so X is unscaled
+// and NUM, DEN share the factor 2^s, which cancels in num/den.  Accumulation
+// is FP32, the ratios and h are FP32, the frame loss terms FP32 summed in
+// FP64 per frame.
+#pragma once
+
+#include "common.h"
+
+namespace isnmf {
+namespace tile {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int WF = 16;       // frames per wave
+constexpr int NWT = 8;       // waves per workgroup
+constexpr int FPW = WF * NWT;  // frames per workgroup
+
+__device__ inline f4 mfma(bf16x8 a, bf16x8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// 4 consecutive 16-bit values (8 bytes, 8-byte aligned) or zeros
+__device__ inline uint2 ld4(const uint16_t *p, bool ok) {
+    return ok ? *reinterpret_cast<const uint2 *>(p) : uint2{0u, 0u};
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+// two FP32 -> two bf16 (round to nearest even), a in the low half
+__device__ inline uint32_t pack2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){a, b}, bf16x2));
+}
+
+// d_IS(y, x) = u - 1 - log u with u = y / x = y * r (FP32; series near u = 1)
+__device__ inline float dis32(float y, float r) {
+    const float u = y * r;
+    const float d = u - 1.f;
+    if (fabsf(d) < 0.125f) {
+        float s = -1.f / 9.f;
+        s = fmaf(s, d, 1.f / 8.f);
+        s = fmaf(s, d, -1.f / 7.f);
+        s = fmaf(s, d, 1.f / 6.f);
+        s = fmaf(s, d, -1.f / 5.f);
+        s = fmaf(s, d, 1.f / 4.f);
+        s = fmaf(s, d, -1.f / 3.f);
+        s = fmaf(s, d, 1.f / 2.f);
+        return s * d * d;
+    }
+    return d - __logf(u);
+}
+
+// LDS bytes of the two W operand arrays for (S contraction steps of 32
+// rows, KS steps of 32 components): X operands [2S][KS][64] and W^T operands
+// [S][2 KS][64], 16 bytes each.
+__host__ __device__ constexpr size_t lds_bytes(int S, int KS) {
+    return (size_t)(2 * S * KS + S * 2 * KS) * 64 * 16;
+}
+
+// S = ceil(F / 32) contraction steps, KS = ceil(K / 32) component steps.
+template <int S, int KS>
+__device__ inline void body(const FitDesc &a, int n_first) {
+    constexpr int T = 2 * S;        // 16-row tiles (the last may be past F)
+    constexpr int MT = 2 * KS;      // 16-component m-tiles
+    extern __shared__ uint4 wl[];
+    uint4 *wxl = wl;                        // [T][KS][64]: X A operands
+    uint4 *wnl = wl + T * KS * 64;          // [S][MT][64]: W^T A operands
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int n = lane & 15;
+    const int F = a.F, K = a.K;
+    const int fr = n_first + WF * w + n;     // this lane's frame (B/C column)
+    const bool fok = fr < a.b;
+    const float eps = a.eps;
+
+    // ---- W operands into LDS (bf16 bits of W * 2^s; zero past F and K)
+    for (int e = threadIdx.x; e < T * KS * 64; e += NWT * 64) {
+        const int l = e & 63, c = (e >> 6) % KS, t = (e >> 6) / KS;
+        const int row = 16 * t + (l & 15), k0 = 32 * c + 4 * (l >> 4);
+        const uint16_t *pr = a.W16r + (size_t)row * a.KP;
+        const uint2 lo = ld4(pr + k0, row < F && k0 < a.KP);
+        const uint2 hi = ld4(pr + k0 + 16, row < F && k0 + 16 < a.KP);
+        wxl[e] = uint4{lo.x, lo.y, hi.x, hi.y};
+    }
+    for (int e = threadIdx.x; e < S * MT * 64; e += NWT * 64) {
+        const int l = e & 63, mt = (e >> 6) % MT, s = (e >> 6) / MT;
+        const int k = 16 * mt + (l & 15), r0 = 32 * s + 4 * (l >> 4);
+        const uint16_t *pc = a.W16c + (size_t)k * a.FR;
+        // rows r0.. and r0 + 16..: below FR (a multiple of 64), zero past F
+        const uint2 lo = ld4(pc + r0, k < K && r0 < a.FR);
+        const uint2 hi = ld4(pc + r0 + 16, k < K && r0 + 16 < a.FR);
+        wnl[e] = uint4{lo.x, lo.y, hi.x, hi.y};
+    }
+
+    // ---- eps + v at the lane's rows (C layout: rows 16t + 4g + j, frame n),
+    // rounded to bf16 for the update loop (the ratios it feeds are bf16
+    // operands); the final pass reads v again in FP32
+    uint32_t vp[T][2];
+    int bad = 0;
+    auto load_v = [&](int t, int j) {
+        const int row = 16 * t + 4 * g + j;
+        return (row < F && fok) ? a.V[(size_t)fr * a.ldv + row] : 0.f;
+    };
+    auto vprime = [&](int t, int j, float v) { return 16 * t + 4 * g + j < F && fok ? eps + v : 0.f; };
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = load_v(t, j);
+            bad |= !isfinite(v[j]);
+        }
+        vp[t][0] = pack2(vprime(t, 0, v[0]), vprime(t, 1, v[1]));
+        vp[t][1] = pack2(vprime(t, 2, v[2]), vprime(t, 3, v[3]));
+    }
+    // unpacked where used: the empty asm keeps the compiler from hoisting
+    // the FP32 values out of the update loop (that would undo the packing)
+    auto vq = [&](int t, int j) {
+        uint32_t u = vp[t][j >> 1];
+        asm volatile("" : "+v"(u));
+        return __uint_as_float((j & 1) ? (u & 0xffff0000u) : (u << 16));
+    };
+    // X accumulator start: eps, or 1 on rows past F (W = 0 there, x only needs to be > 0)
+    const f4 ce = {eps, eps, eps, eps};
+    auto cinit = [&](int t) {
+        f4 c = ce;
+        // F > 32 (S - 1): only the last two tiles can reach past F
+        if (t >= T - 2 && 16 * t + 15 >= F) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (16 * t + 4 * g + j >= F) c[j] = 1.f;
+        }
+        return c;
+    };
+
+    // ---- h (FP32): lane (g, n) holds components 16 mt + 4g + j of frame n
+    float hq[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 16 * mt + 4 * g + j;
+            hq[mt][j] = k < K ? ((a.warm && fok) ? a.Hb[(size_t)fr * a.ldh + k] : 1.f) : 0.f;
+        }
+    // the X B operand: slot j of step c is m-tile 2c (j < 4) or 2c + 1 (j >= 4)
+    bf16x8 hb[KS];
+    auto pack_h = [&]() {
+#pragma unroll
+        for (int c = 0; c < KS; ++c) {
+            const float sc = a.hscale;
+            const uint4 u = {pack2(hq[2 * c][0] * sc, hq[2 * c][1] * sc),
+                             pack2(hq[2 * c][2] * sc, hq[2 * c][3] * sc),
+                             pack2(hq[2 * c + 1][0] * sc, hq[2 * c + 1][1] * sc),
+                             pack2(hq[2 * c + 1][2] * sc, hq[2 * c + 1][3] * sc)};
+            hb[c] = __builtin_bit_cast(bf16x8, u);
+        }
+    };
+    pack_h();
+    __syncthreads();   // W operands in LDS
+
+    auto model = [&](int t) {
+        f4 x = cinit(t);
+#pragma unroll
+        for (int c = 0; c < KS; ++c)
+            x = mfma(__builtin_bit_cast(bf16x8, wxl[(t * KS + c) * 64 + lane]), hb[c], x);
+        return x;
+    };
+
+    int guard = 0;
+    for (int it = 0; it < a.iters; ++it) {
+        f4 na[MT], da[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            na[mt] = f4{0.f, 0.f, 0.f, 0.f};
+            da[mt] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            // the W operands are re-read from LDS at every step (kept from
+            // being hoisted into registers: all of them would not fit), and
+            // the steps are not interleaved by the scheduler (live ranges)
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+            const f4 x0 = model(2 * s), x1 = model(2 * s + 1);
+            float r1[8], r2[8];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                r1[j] = __builtin_amdgcn_rcpf(x0[j]);
+                r2[j] = vq(2 * s, j) * r1[j] * r1[j];
+                r1[4 + j] = __builtin_amdgcn_rcpf(x1[j]);
+                r2[4 + j] = vq(2 * s + 1, j) * r1[4 + j] * r1[4 + j];
+            }
+            const bf16x8 b1 = __builtin_bit_cast(
+                bf16x8, uint4{pack2(r1[0], r1[1]), pack2(r1[2], r1[3]), pack2(r1[4], r1[5]),
+                              pack2(r1[6], r1[7])});
+            const bf16x8 b2 = __builtin_bit_cast(
+                bf16x8, uint4{pack2(r2[0], r2[1]), pack2(r2[2], r2[3]), pack2(r2[4], r2[5]),
+                              pack2(r2[6], r2[7])});
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const bf16x8 wt = __builtin_bit_cast(bf16x8, wnl[(s * MT + mt) * 64 + lane]);
+                na[mt] = mfma(wt, b2, na[mt]);
+                da[mt] = mfma(wt, b1, da[mt]);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (16 * mt + 4 * g + j < K) {
+                    const float N = na[mt][j], D = da[mt][j];
+                    if (D > 0.f && N >= 0.f)
+                        hq[mt][j] *= __builtin_amdgcn_sqrtf(N * __builtin_amdgcn_rcpf(D));
+                    else if (fok)
+                        guard = 1;
+                }
+            }
+        pack_h();
+    }
+    if (guard) atomicOr(a.flags, FLAG_GUARD_H);
+
+    // ---- final model: R1, R2 for the fold (FP32) and the frame loss
+    double ls = 0.0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        const f4 x = model(t);
+        const int row0 = 16 * t + 4 * g;
+        f4 r1, r2;
+        float l = 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float r = __builtin_amdgcn_rcpf(x[j]);
+            const float ve = vprime(t, j, load_v(t, j));
+            r1[j] = r;
+            r2[j] = ve * r * r;
+            if (row0 + j < F) l += dis32(ve, r);
+        }
+        ls += double(l);
+        if (fok && row0 < F) {   // FR is a multiple of 64: rows row0..row0+3 are in the buffer
+            *reinterpret_cast<f4 *>(a.R1 + (size_t)fr * a.FR + row0) = r1;
+            *reinterpret_cast<f4 *>(a.R2 + (size_t)fr * a.FR + row0) = r2;
+        }
+    }
+    // frame n's loss: lanes n, n + 16, n + 32, n + 48, in that order
+    const double l1 = __shfl_xor(ls, 16, 64);
+    const double l2 = __shfl_xor(ls, 32, 64);
+    const double l3 = __shfl_xor(ls, 48, 64);
+    if (g == 0 && fok) a.lossf[fr] = ((ls + l1) + l2) + l3;
+    if (fok) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 16 * mt + 4 * g + j;
+                if (k < K) {
+                    a.Hi[(size_t)fr * a.KP + k] = hq[mt][j];
+                    if (a.Hb) a.Hb[(size_t)fr * a.ldh + k] = hq[mt][j];
+                }
+            }
+    }
+}
+
+template <int S, int KS>
+__global__ __launch_bounds__(NWT * 64) void fit_tile_kernel(FitDesc a) {
+    body<S, KS>(a, blockIdx.x * FPW);
+}
+
+// Batched form: item = (stream, tile of 128 frames); tiles past the stream's
+// minibatch of this step exit.
+template <int S, int KS>
+__global__ __launch_bounds__(NWT * 64) void fit_tile_multi_kernel(const FitDesc *__restrict__ descs,
+                                                                  const int2 *__restrict__ items,
+                                                                  const long long *__restrict__ cursor,
+                                                                  const int *__restrict__ beff) {
+    const int2 it = items[blockIdx.x];
+    const int b = beff[it.x];
+    if (it.y * FPW >= b) return;   // uniform per workgroup
+    FitDesc a = descs[it.x];
+    const long long c = cursor[it.x];
+    a.b = b;
+    a.V += c * a.ldv;
+    if (a.Hb) a.Hb += c * a.ldh;
+    body<S, KS>(a, it.y * FPW);
+}
+
+template <int S, int KS>
+hipError_t launch_one(const FitDesc *a, int b, const FitDesc *d, const int2 *items, int n,
+                      const long long *cur, const int *beff, hipStream_t s) {
+    constexpr size_t lds = lds_bytes(S, KS);
+    if (d) {
+        static const hipError_t attr = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&fit_tile_multi_kernel<S, KS>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (attr != hipSuccess) return attr;
+        fit_tile_multi_kernel<S, KS><<<n, NWT * 64, lds, s>>>(d, items, cur, beff);
+    } else {
+        static const hipError_t attr = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&fit_tile_kernel<S, KS>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (attr != hipSuccess) return attr;
+        fit_tile_kernel<S, KS><<<(b + FPW - 1) / FPW, NWT * 64, lds, s>>>(*a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tile
+}  // namespace isnmf
+
+namespace isnmf {
+namespace tile {
+
+constexpr int S_MAX = 20;   // F <= 640
+
+// Launch of the (S, KS) instance for S = 1..S_MAX; explicitly instantiated per
+// KS in fit_tile_k*.hip so the instances build in parallel.
+template <int KS>
+hipError_t launch_ks(int S, const FitDesc *a, int b, const FitDesc *d, const int2 *items, int n,
+                     const long long *cur, const int *beff, hipStream_t st) {
+    switch (S) {
+#define ISNMF_TILE_S(SV) \
+    case SV: return launch_one<SV, KS>(a, b, d, items, n, cur, beff, st);
+        ISNMF_TILE_S(1) ISNMF_TILE_S(2) ISNMF_TILE_S(3) ISNMF_TILE_S(4) ISNMF_TILE_S(5)
+        ISNMF_TILE_S(6) ISNMF_TILE_S(7) ISNMF_TILE_S(8) ISNMF_TILE_S(9) ISNMF_TILE_S(10)
+        ISNMF_TILE_S(11) ISNMF_TILE_S(12) ISNMF_TILE_S(13) ISNMF_TILE_S(14) ISNMF_TILE_S(15)
+        ISNMF_TILE_S(16) ISNMF_TILE_S(17) ISNMF_TILE_S(18) ISNMF_TILE_S(19) ISNMF_TILE_S(20)
+#undef ISNMF_TILE_S
+        default: return hipErrorNotSupported;
+    }
+}
+
+#define ISNMF_TILE_EXTERN(KSV)                                                                   \
+    extern template hipError_t launch_ks<KSV>(int, const FitDesc *, int, const FitDesc *,       \
+                                              const int2 *, int, const long long *, const int *, \
+                                              hipStream_t);
+#define ISNMF_TILE_INSTANTIATE(KSV)                                                       \
+    template hipError_t launch_ks<KSV>(int, const FitDesc *, int, const FitDesc *,       \
+                                       const int2 *, int, const long long *, const int *, \
+                                       hipStream_t);
+
+}  // namespace tile
+}  // namespace isnmf

@@ -1,0 +1,8 @@
+// Instances of the 16-frame tile variant with 1 step(s) of 32 components.
+#include "fit_tile.h"
+
+namespace isnmf {
+namespace tile {
+ISNMF_TILE_INSTANTIATE(1)
+}  // namespace tile
+}  // namespace isnmf

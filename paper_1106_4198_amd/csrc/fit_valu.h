@@ -44,36 +44,6 @@ __device__ inline float sum8(float v) {
     return v;
 }
 
-template <int CTRL>
-__device__ inline double dppd(double v) {
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)u, CTRL, 0xf, 0xf, false);
-    const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, (uint64_t)hi << 32 | lo);
-}
-
-__device__ inline double join(unsigned lo, unsigned hi) {
-    return __builtin_bit_cast(double, (uint64_t)hi << 32 | lo);
-}
-
-// Sum over the 64 lanes of the wave in a fixed order (every lane gets it):
-// 8-lane groups with DPP, lanes 8 apart, then 16-lane rows and halves with
-// the permlane swaps.
-__device__ inline double wave_sum(double v) {
-    v += dppd<0xB1>(v);
-    v += dppd<0x4E>(v);
-    v += dppd<0x141>(v);
-    v += dppd<0x128>(v);
-    uint64_t u = __builtin_bit_cast(uint64_t, v);
-    auto l16 = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
-    auto h16 = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
-    v = join(l16[0], h16[0]) + join(l16[1], h16[1]);
-    u = __builtin_bit_cast(uint64_t, v);
-    auto l32 = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
-    auto h32 = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
-    return join(l32[0], h32[0]) + join(l32[1], h32[1]);
-}
-
 // a, b -> rows (a0+a1, b0+b1, a2+a3, b2+b3) of 16 lanes each
 __device__ inline float swap16_add(float a, float b) {
     auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
@@ -255,7 +225,7 @@ __device__ inline void body(const FitDesc &a, int fr) {
     finish_row(0);
     if (RF > 8 && (RF > 9 || last_live)) finish_row(8);
     if (RF > 16 && last_live) finish_row(16);
-    lsum = wave_sum(lsum);
+    lsum = wave_sum_f64(lsum);
     if (lane == 0) lred[w] = lsum;
     __syncthreads();
     if (t == 0) {

@@ -20,7 +20,7 @@ namespace isnmf {
 namespace {
 
 __global__ __launch_bounds__(256) void fold_mfma_kernel(FoldArgs a) {
-    fold_tile_body(a, blockIdx.x, blockIdx.y, gridDim.y);
+    fold_tile16_body(a, blockIdx.x, blockIdx.y, gridDim.y);
 }
 
 
@@ -49,7 +49,7 @@ hipError_t launch_fold_mfma(const OnlineDev &d, int b, double rho, int update_w,
     FoldArgs a = fold_args(d, b, rho, update_w, part, d_loss_sum);
     const int slices = (b + SLICE - 1) / SLICE;
     if (slices > 1 && !part) return hipErrorInvalidValue;
-    fold_mfma_kernel<<<dim3(fold_tiles(d), slices), 256, 0, s>>>(a);
+    fold_mfma_kernel<<<dim3(fold_tiles16(d), slices), 256, 0, s>>>(a);
     if (slices > 1) {
         a.d_loss_sum = nullptr;
         const long fk = (long)d.F * d.K;

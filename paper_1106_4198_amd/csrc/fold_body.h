@@ -15,7 +15,6 @@ struct FoldArgs {
     double *A, *B, *Wn;
     double rho;
     int update_w;
-    int tiles_f;           // ceil(F / 16)
     float *part;           // slices x 2 x F x K partials (multi-slice only)
     const double *lossf;   // frame losses of the minibatch (may be null)
     double *d_loss_sum;    // += sum of lossf (may be null)
@@ -45,17 +44,145 @@ __device__ inline void epilogue(const FoldArgs &a, int f, int k, double sa, doub
     }
 }
 
-// One 16 x 16 tile of (f, k) per 256-thread block (4 waves); frame groups of
-// 4 dealt round-robin to the waves, partial tiles summed in wave order.
+// Batched and served fold: one 16-row tile of f and every component k per
+// 256-thread block (4 waves), KTM >= ceil(K / 16) tiles of 16 components, so
+// each block reads its r1, r2 rows once for all components.  The frames are the
+// contraction dimension of v_mfma_f32_16x16x4f32: wave w takes the groups of
+// 4 frames with (n / 4) mod 4 == w, in increasing n, and loads each group's
+// r1, r2 operand once for all component tiles; the four per-wave partials of
+// an element are summed in wave order.  Wave w then applies the FP64
+// epilogue to the component tiles kt = w (mod 4).
+// nslices > 1: write the FP32 partial tiles of slice `slice` instead.
+template <int KTM>
+__device__ __forceinline__ void fold_rows_body(const FoldArgs &a, int ft, int slice, int nslices) {
+    constexpr int KE = (KTM + 3) / 4;           // epilogue tiles per wave
+    __shared__ floatx4 red[4][KTM][2][64];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int KT = (a.K + 15) / 16;
+    const int f0 = ft * 16;
+    const int n_lo = slice * SLICE;
+    const int n_hi = min(a.b, n_lo + SLICE);
+    const int fa = f0 + (lane & 15);       // A operand row
+    const int sub = lane >> 4;             // frame within the group of 4
+    const bool fok = fa < a.F;
+
+    // epilogue operands of this wave's component tiles, loaded before the frame rounds
+    double wq[KE][4], aq[KE][4], bq[KE][4];
+    if (nslices == 1) {
+#pragma unroll
+        for (int u = 0; u < KE; ++u) {
+            const int kc = 16 * (w + 4 * u) + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int f = f0 + 4 * sub + r;
+                const bool ok = w + 4 * u < KT && f < a.F && kc < a.K;
+                const size_t e = ok ? (size_t)f + (size_t)kc * a.F : 0;
+                wq[u][r] = ok ? a.W64[e] : 0.0;
+                aq[u][r] = ok ? a.A[e] : 0.0;
+                bq[u][r] = ok ? a.B[e] : 0.0;
+            }
+        }
+    }
+
+    // minibatch loss: wave 1 of tile 0, lane l sums frames l, l + 64, ... in
+    // order, then a fixed xor butterfly over the lanes
+    if (a.d_loss_sum && ft == 0 && slice == 0 && w == 1) {
+        double s = 0.0;
+        for (int n = lane; n < a.b; n += 64) s += a.lossf[n];
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) s += __shfl_xor(s, m, 64);
+        if (lane == 0) *a.d_loss_sum += s;
+    }
+
+    floatx4 ca[KTM], cb[KTM];
+#pragma unroll
+    for (int kt = 0; kt < KTM; ++kt) {
+        ca[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        cb[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    // rounds of GR groups per wave: every load of a round is issued before
+    // its MFMAs (GR bounded so the round's operands stay within ~40 registers)
+    constexpr int GR = KTM <= 2 ? 8 : 2;
+#pragma unroll 1
+    for (int g0 = n_lo + 4 * w; g0 < n_hi; g0 += 4 * 4 * GR) {
+        float r2[GR], r1[GR], hh[GR][KTM];
+#pragma unroll
+        for (int g = 0; g < GR; ++g) {
+            const int n = g0 + 16 * g + sub;
+            const bool ok = n < n_hi;
+            r2[g] = (ok && fok) ? a.R2[(size_t)n * a.FR + fa] : 0.f;
+            r1[g] = (ok && fok) ? a.R1[(size_t)n * a.FR + fa] : 0.f;
+#pragma unroll
+            for (int kt = 0; kt < KTM; ++kt) {
+                const int kb = 16 * kt + (lane & 15);
+                hh[g][kt] = (ok && kt < KT && kb < a.K) ? a.H[(size_t)n * a.KP + kb] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < GR; ++g)
+#pragma unroll
+            for (int kt = 0; kt < KTM; ++kt) {
+                if (kt < KT) {
+                    ca[kt] = mfma16(r2[g], hh[g][kt], ca[kt]);
+                    cb[kt] = mfma16(r1[g], hh[g][kt], cb[kt]);
+                }
+            }
+    }
+#pragma unroll
+    for (int kt = 0; kt < KTM; ++kt) {
+        if (kt < KT) {
+            red[w][kt][0][lane] = ca[kt];
+            red[w][kt][1][lane] = cb[kt];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < KE; ++u) {
+        const int kt = w + 4 * u;
+        if (kt >= KT) continue;
+        const floatx4 sa = ((red[0][kt][0][lane] + red[1][kt][0][lane]) + red[2][kt][0][lane]) +
+                           red[3][kt][0][lane];
+        const floatx4 sb = ((red[0][kt][1][lane] + red[1][kt][1][lane]) + red[2][kt][1][lane]) +
+                           red[3][kt][1][lane];
+        const int kc = 16 * kt + (lane & 15);
+        if (nslices == 1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int f = f0 + 4 * sub + r;
+                if (f < a.F && kc < a.K)
+                    epilogue(a, f, kc, double(sa[r]), double(sb[r]), wq[u][r], aq[u][r], bq[u][r]);
+            }
+        } else {
+            const size_t fk = (size_t)a.F * a.K;
+            float *pa = a.part + (size_t)slice * 2 * fk;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int f = f0 + 4 * sub + r;
+                if (f < a.F && kc < a.K) {
+                    pa[f + (size_t)kc * a.F] = sa[r];
+                    pa[fk + f + (size_t)kc * a.F] = sb[r];
+                }
+            }
+        }
+    }
+}
+
+// Single-stream fold: one 16 x 16 tile of (f, k) per 256-thread block (4
+// waves), so a single minibatch spreads over ceil(F/16) ceil(K/16) blocks.
+// Each element is computed exactly as fold_rows_body computes it (the same
+// MFMA chain per wave over the frames with (n / 4) mod 4 == w, the same wave
+// order, the same epilogue), so both give the same bits.
 // nslices > 1: write the FP32 partial tile of slice `slice` instead of the
 // epilogue.
-__device__ __forceinline__ void fold_tile_body(const FoldArgs &a, int tile, int slice,
-                                               int nslices) {
+__device__ __forceinline__ void fold_tile16_body(const FoldArgs &a, int tile, int slice,
+                                                 int nslices) {
     __shared__ floatx4 red[4][2][64];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int f0 = (tile % a.tiles_f) * 16;
-    const int k0 = (tile / a.tiles_f) * 16;
+    const int tiles_f = (a.F + 15) / 16;
+    const int f0 = (tile % tiles_f) * 16;
+    const int k0 = (tile / tiles_f) * 16;
     const int n_lo = slice * SLICE;
     const int n_hi = min(a.b, n_lo + SLICE);
     const int fa = f0 + (lane & 15);       // A operand row
@@ -134,6 +261,13 @@ __device__ __forceinline__ void fold_tile_body(const FoldArgs &a, int tile, int 
 }
 
 
+// The fold instance for K components: the smallest of 1, 2, 4, 8 component
+// tiles (K <= 128) that covers them.
+inline int fold_ktm(int K) {
+    const int kt = (K + 15) / 16;
+    return kt <= 1 ? 1 : kt <= 2 ? 2 : kt <= 4 ? 4 : kt <= 8 ? 8 : 0;
+}
+
 inline FoldArgs fold_args(const OnlineDev &d, int b, double rho, int update_w, float *part,
                           double *d_loss_sum) {
     FoldArgs a;
@@ -151,7 +285,6 @@ inline FoldArgs fold_args(const OnlineDev &d, int b, double rho, int update_w, f
     a.Wn = d.Wn;
     a.rho = rho;
     a.update_w = update_w;
-    a.tiles_f = (d.F + 15) / 16;
     a.part = part;
     a.lossf = d.lossf;
     a.d_loss_sum = d_loss_sum;
@@ -159,6 +292,9 @@ inline FoldArgs fold_args(const OnlineDev &d, int b, double rho, int update_w, f
     return a;
 }
 
-inline int fold_tiles(const OnlineDev &d) { return ((d.F + 15) / 16) * ((d.K + 15) / 16); }
+// Blocks of the fold: per 16-row tile (fold_rows_body), per 16 x 16 tile
+// (fold_tile16_body).
+inline int fold_tiles(const OnlineDev &d) { return (d.F + 15) / 16; }
+inline int fold_tiles16(const OnlineDev &d) { return ((d.F + 15) / 16) * ((d.K + 15) / 16); }
 
 }  // namespace isnmf

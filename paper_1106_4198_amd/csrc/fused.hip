@@ -11,6 +11,8 @@
 //   FP32, F <= 1088, K <= 64: the VALU variant (one frame per workgroup) where
 //                             no MFMA tile fits, and as a tuning candidate
 //                             elsewhere
+//   BF16, F <= 640, K <= 64:  the 16-frame tile variant, a tuning candidate
+//                             (throughput over many frames)
 #include <math.h>
 
 #include "common.h"
@@ -76,6 +78,10 @@ int fit_candidates(int F, int K, int prec, FitClass *out, int max_out) {
         const FitClass v = valu_class(F, K);
         if (v.ok) add(v);
     }
+    if (prec == 1) {                 // the 16-frame tile variant (BF16)
+        const FitClass t = tile_class(F, K);
+        if (t.ok) add(t);
+    }
     if (prec != 0 && d.kmax <= 64) {
         const int nch = d.main_chunks < 1 ? 1 : d.main_chunks;
         if (nch > 4 && nch <= 8) {   // 4 waves x 2 chunks instead of 8 x 1
@@ -134,6 +140,7 @@ hipError_t launch_fused_fit(const OnlineDev &d, const FitClass &c, const float *
     if (!c.ok) return hipErrorNotSupported;
     const FitDesc a = make_fit_desc(d, V, ldv, b, iters, eps, warm, Hb, ldh);
     if (c.cpw == 0) return prec == 0 ? launch_fit_valu(a, c, b, s) : hipErrorNotSupported;
+    if (c.cpw == -1) return prec == 1 ? launch_fit_tile(a, c, b, s) : hipErrorNotSupported;
     const int grid = (b + NF - 1) / NF;
     if (prec == 1) return launch_fit_single_p<1>(a, c, grid, s);
     if (prec == 2) return launch_fit_single_p<2>(a, c, grid, s);

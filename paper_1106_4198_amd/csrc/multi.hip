@@ -11,6 +11,7 @@
 #include <math.h>
 
 #include <map>
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <tuple>
@@ -55,7 +56,8 @@ __global__ void advance_kernel(int S, const int *__restrict__ beff, long long *_
     if (s < S) cursor[s] += beff[s];
 }
 
-__global__ __launch_bounds__(256) void fold_multi_kernel(const FoldArgs *__restrict__ fa,
+template <int KTM>
+__global__ __launch_bounds__(256, 4) void fold_multi_kernel(const FoldArgs *__restrict__ fa,
                                                          const int2 *__restrict__ items,
                                                          const int *__restrict__ beff) {
     const int2 it = items[blockIdx.x];
@@ -63,10 +65,10 @@ __global__ __launch_bounds__(256) void fold_multi_kernel(const FoldArgs *__restr
     if (b == 0) return;
     FoldArgs a = fa[it.x];
     a.b = b;
-    fold_tile_body(a, it.y, 0, 1);
+    fold_rows_body<KTM>(a, it.y, 0, 1);
 }
 
-__global__ __launch_bounds__(256) void rescale_multi_kernel(const RescaleArgs *__restrict__ ra,
+__global__ __launch_bounds__(64) void rescale_multi_kernel(const RescaleArgs *__restrict__ ra,
                                                             const int *__restrict__ upd,
                                                             const int2 *__restrict__ items,
                                                             const int *__restrict__ beff) {
@@ -106,6 +108,7 @@ struct isnmf_multi {
     };
     std::vector<Group> groups;
     int fold_off = 0, fold_n = 0, rs_off = 0, rs_n = 0;
+    int fold_ktm = 1;   // fold instance: covers the widest stream's component tiles
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -168,6 +171,8 @@ hipError_t enqueue_step(isnmf_multi *m, hipStream_t s) {
         hipError_t e;
         if (g.c.cpw == 0)
             e = launch_fit_valu_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
+        else if (g.c.cpw == -1)
+            e = launch_fit_tile_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
         else if (g.prec == 1)
             e = launch_fit_multi_p<1>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
         else if (g.prec == 2)
@@ -176,9 +181,18 @@ hipError_t enqueue_step(isnmf_multi *m, hipStream_t s) {
             e = launch_fit_multi_p<0>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
         if (e != hipSuccess) return e;
     }
-    if (m->fold_n) fold_multi_kernel<<<m->fold_n, 256, 0, s>>>(m->d_fold, m->d_items + m->fold_off, m->d_beff);
+    if (m->fold_n) {
+        const int2 *fi = m->d_items + m->fold_off;
+        switch (m->fold_ktm) {
+            case 1: fold_multi_kernel<1><<<m->fold_n, 256, 0, s>>>(m->d_fold, fi, m->d_beff); break;
+            case 2: fold_multi_kernel<2><<<m->fold_n, 256, 0, s>>>(m->d_fold, fi, m->d_beff); break;
+            case 4: fold_multi_kernel<4><<<m->fold_n, 256, 0, s>>>(m->d_fold, fi, m->d_beff); break;
+            case 8: fold_multi_kernel<8><<<m->fold_n, 256, 0, s>>>(m->d_fold, fi, m->d_beff); break;
+            default: return hipErrorNotSupported;
+        }
+    }
     if (m->rs_n)
-        rescale_multi_kernel<<<m->rs_n, 256, 0, s>>>(m->d_rs, m->d_upd, m->d_items + m->rs_off, m->d_beff);
+        rescale_multi_kernel<<<m->rs_n, 64, 0, s>>>(m->d_rs, m->d_upd, m->d_items + m->rs_off, m->d_beff);
     advance_kernel<<<blocks, 256, 0, s>>>(m->S, m->d_beff, m->d_cursor);
     return hipGetLastError();
 }
@@ -267,7 +281,8 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         size_t gi = 0;
         while (gi < groups.size() && groups[gi].first != key) ++gi;
         if (gi == groups.size()) groups.push_back({key, {}});
-        for (int t = 0; t < (b[s] + NF - 1) / NF; ++t) groups[gi].second.push_back(int2{s, t});
+        const int per = frames_per_item(c);
+        for (int t = 0; t < (b[s] + per - 1) / per; ++t) groups[gi].second.push_back(int2{s, t});
     }
     for (auto &g : groups) {
         isnmf_multi::Group G;
@@ -281,6 +296,7 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
     m->fold_off = (int)items.size();
     for (int s = 0; s < S; ++s) {
         const int nt = fold_tiles(*isnmf_handle_dev(handles[s]));
+        m->fold_ktm = std::max(m->fold_ktm, fold_ktm(isnmf_handle_dev(handles[s])->K));
         for (int t = 0; t < nt; ++t) items.push_back(int2{s, t});
     }
     m->fold_n = (int)items.size() - m->fold_off;

@@ -62,15 +62,16 @@ __global__ __launch_bounds__(NW * 64) void serve_fit_kernel(const FitDesc *__res
     fit_body<NW, CPW, KMAX, PREC, WG>(a, blockIdx.y);
 }
 
-__global__ __launch_bounds__(256) void serve_fold_kernel(const FoldArgs *__restrict__ tab,
+template <int KTM>
+__global__ __launch_bounds__(256, 4) void serve_fold_kernel(const FoldArgs *__restrict__ tab,
                                                          const Work *__restrict__ work) {
     const Work wk = work[blockIdx.x];
     FoldArgs a = tab[wk.sess];
     a.b = wk.b;
-    fold_tile_body(a, blockIdx.y, 0, 1);
+    fold_rows_body<KTM>(a, blockIdx.y, 0, 1);
 }
 
-__global__ __launch_bounds__(256) void serve_rescale_kernel(const RescaleArgs *__restrict__ tab,
+__global__ __launch_bounds__(64) void serve_rescale_kernel(const RescaleArgs *__restrict__ tab,
                                                             const int *__restrict__ upd,
                                                             const Work *__restrict__ work) {
     const Work wk = work[blockIdx.x];
@@ -259,9 +260,14 @@ int launch_step(isnmf_server *s) {
         const int tiles = (maxb + NF - 1) / NF;
         if (serve_fit_any(A.prec, A.cls, s->d_fit, slot->dev + lo, cnt, tiles, st) != hipSuccess)
             return -1;
-        const int ft = ((A.F + 15) / 16) * ((A.K + 15) / 16);
-        serve_fold_kernel<<<dim3(cnt, ft), 256, 0, st>>>(s->d_fold, slot->dev + lo);
-        serve_rescale_kernel<<<dim3(cnt, A.K), 256, 0, st>>>(s->d_rs, s->d_upd, slot->dev + lo);
+        const dim3 fg(cnt, (A.F + 15) / 16);
+        switch (fold_ktm(A.K)) {
+            case 1: serve_fold_kernel<1><<<fg, 256, 0, st>>>(s->d_fold, slot->dev + lo); break;
+            case 2: serve_fold_kernel<2><<<fg, 256, 0, st>>>(s->d_fold, slot->dev + lo); break;
+            case 4: serve_fold_kernel<4><<<fg, 256, 0, st>>>(s->d_fold, slot->dev + lo); break;
+            default: serve_fold_kernel<8><<<fg, 256, 0, st>>>(s->d_fold, slot->dev + lo); break;
+        }
+        serve_rescale_kernel<<<dim3(cnt, A.K), 64, 0, st>>>(s->d_rs, s->d_upd, slot->dev + lo);
         lo = hi;
     }
     if (hipGetLastError() != hipSuccess) return -1;

@@ -45,7 +45,7 @@ __global__ void fold_kernel(int F, int K, int b, int FR, int KP, const TR *__res
     }
 }
 
-__global__ __launch_bounds__(256) void rescale_kernel(RescaleArgs a, int b) {
+__global__ __launch_bounds__(64) void rescale_kernel(RescaleArgs a, int b) {
     rescale_body(a, blockIdx.x, b);
 }
 
@@ -111,7 +111,7 @@ hipError_t launch_fold(const OnlineDev &d, int b, double rho, int update_w, int 
 hipError_t launch_rescale(const OnlineDev &d, int b, int update_w, int normalize, int warm,
                           float *Hb, int ldh, double *d_dw, hipStream_t s) {
     if (update_w)
-        rescale_kernel<<<d.K, 256, 0, s>>>(rescale_args(d, normalize, warm, Hb, ldh), b);
+        rescale_kernel<<<d.K, 64, 0, s>>>(rescale_args(d, normalize, warm, Hb, ldh), b);
     if (d_dw) dw_total_kernel<<<1, 64, 0, s>>>(d.K, d.dwpart, update_w, d_dw);
     return hipGetLastError();
 }

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "common.h"
+#include "devmath.h"
 
 namespace isnmf {
 
@@ -40,17 +41,6 @@ __device__ inline void store_wv(const WvOut &o, int f, int k, double w) {
     if (o.p) o.p[wv_index(f, k, o.ck)] = float(w);
 }
 
-// Sum over a 256-thread block in a fixed order: per-wave xor butterfly (the
-// same value in every lane), then the four wave sums in index order.
-__device__ inline double block_sum256(double v, double *red4) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
-    __syncthreads();
-    return ((red4[0] + red4[1]) + red4[2]) + red4[3];
-}
-
 struct RescaleArgs {
     int F, K;
     const double *Wn;
@@ -66,72 +56,61 @@ struct RescaleArgs {
     int *flags;
 };
 
-// Block (256 threads) per column k: s_k = sum_f Wn_fk, W = Wn / s, A /= s,
-// B *= s, warm H[k,:] *= s, and the column's squared change of W.
+// One wave per column k: s_k = sum_f Wn_fk, W = Wn / s, A /= s, B *= s,
+// warm H[k,:] *= s, and the column's squared change of W.  Lane l takes rows
+// l, l + 64, ... in order; the lane values are combined by wave_sum_f64.
 __device__ __forceinline__ void rescale_body(const RescaleArgs &a, int k, int b) {
-    __shared__ double red4[4];
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int F = a.F;
     const size_t col = (size_t)k * F;
-    // all loads first (one memory round trip), then the column sum
-    constexpr int RMAX = 8;   // rows per thread held in registers (F <= 2048)
-    double wn[RMAX], wo[RMAX], av[RMAX], bv[RMAX];
-    double s = 0.0;
+    constexpr int RW = 9;   // rows per lane held in registers (F <= 576); the rest loop
+    double wn[RW], wo[RW], av[RW], bv[RW];
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-        const int f = tid + 256 * r;
+    for (int r = 0; r < RW; ++r) {   // every load of the column in one round trip
+        const int f = lane + 64 * r;
         const bool ok = f < F;
         wn[r] = ok ? a.Wn[col + f] : 0.0;
         wo[r] = ok ? a.W64[col + f] : 0.0;
         av[r] = ok ? a.A[col + f] : 0.0;
         bv[r] = ok ? a.B[col + f] : 0.0;
     }
+    double s = 0.0;
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) s += wn[r];
-    for (int f = tid + 256 * RMAX; f < F; f += 256) s += a.Wn[col + f];
-    s = block_sum256(s, red4);
+    for (int r = 0; r < RW; ++r) s += wn[r];
+    for (int f = lane + 64 * RW; f < F; f += 64) s += a.Wn[col + f];
+    s = wave_sum_f64(s);
     double scale = 1.0;
     if (a.normalize) {
         if (s > 0.0)
             scale = s;
-        else if (tid == 0)
+        else if (lane == 0)
             atomicOr(a.flags, FLAG_GUARD_W);
     }
     double dw = 0.0;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-        const int f = tid + 256 * r;
-        if (f < F) {
-            const double w = wn[r] / scale;
-            const double dlt = w - wo[r];
-            dw += dlt * dlt;
-            a.W64[col + f] = w;
-            a.W32[col + f] = float(w);
-            store_w16(a.w16, f, k, w);
-            store_wv(a.wv, f, k, w);
-            if (a.normalize) {
-                a.A[col + f] = av[r] / scale;
-                a.B[col + f] = bv[r] * scale;
-            }
-        }
-    }
-    for (int f = tid + 256 * RMAX; f < F; f += 256) {
-        const double w = a.Wn[col + f] / scale;
-        const double dlt = w - a.W64[col + f];
+    auto update = [&](int f, double wnv, double wo, double av, double bv) {
+        const double w = wnv / scale;
+        const double dlt = w - wo;
         dw += dlt * dlt;
         a.W64[col + f] = w;
         a.W32[col + f] = float(w);
         store_w16(a.w16, f, k, w);
         store_wv(a.wv, f, k, w);
         if (a.normalize) {
-            a.A[col + f] /= scale;
-            a.B[col + f] *= scale;
+            a.A[col + f] = av / scale;
+            a.B[col + f] = bv * scale;
         }
+    };
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const int f = lane + 64 * r;
+        if (f < F) update(f, wn[r], wo[r], av[r], bv[r]);
     }
+    for (int f = lane + 64 * RW; f < F; f += 64)
+        update(f, a.Wn[col + f], a.W64[col + f], a.A[col + f], a.B[col + f]);
     if (a.warm && a.Hb && a.normalize)
-        for (int n = tid; n < b; n += 256) a.Hb[(size_t)n * a.ldh + k] *= float(scale);
-    dw = block_sum256(dw, red4);
-    if (tid == 0) a.dwpart[k] = dw;
+        for (int n = lane; n < b; n += 64) a.Hb[(size_t)n * a.ldh + k] *= float(scale);
+    dw = wave_sum_f64(dw);
+    if (lane == 0) a.dwpart[k] = dw;
 }
 
 inline W16Out w16_out(const OnlineDev &d) {

@@ -59,6 +59,51 @@ def test_one_step_error_is_small(precision, F, K, b):
     assert g.status() == 0
 
 
+def tile_variant(F, K):
+    """Make handles of shape (F, K) in BF16 use the 16-frame tile variant."""
+    bd.tune_clear()
+    bd.tune_set(F, K, "bf16", 8, -1, 0)
+    assert bd.tune_get(F, K, "bf16") == (8, -1, 0)
+
+
+@pytest.mark.parametrize("F,K,b", [(513, 50, 128), (129, 8, 16), (257, 64, 33), (70, 5, 6),
+                                   (513, 33, 7), (640, 64, 20), (16, 1, 3), (200, 40, 17),
+                                   (257, 16, 1), (600, 64, 48), (513, 50, 300), (33, 32, 129)])
+def test_tile_variant_one_step(F, K, b):
+    """BF16 16-frame tile variant (16x16x32 MFMA) against the FP64 oracle at the
+    precision-form bound, from a mid-stream state."""
+    say(f"tile step F={F} K={K} b={b}")
+    tile_variant(F, K)
+    try:
+        V, W0 = synth.problem(F, K, 3 * b, seed=6)
+        st = oracle.OnlineState(W0.astype(np.float64))
+        st.step(V[:, :b].astype(np.float64), iters=20)
+        st.step(V[:, b:2 * b].astype(np.float64), iters=20)
+        g = bd.OnlineISNMF(to_gpu_kf(st.W, np.float32, torch), b, precision="bf16",
+                           A0=to_gpu_kf(st.A, np.float64, torch), B0=to_gpu_kf(st.B, np.float64, torch))
+        g.set_w64(to_gpu_kf(st.W, np.float64, torch))
+        Vb = V[:, 2 * b:3 * b]
+        loss = torch.zeros((), dtype=torch.float64, device=DEV)
+        H = torch.zeros((b, K), dtype=torch.float32, device=DEV)
+        g.step(torch.from_numpy(np.ascontiguousarray(Vb.T)).to(DEV), H, loss)
+        Hr, _, _ = st.step(Vb.astype(np.float64), iters=20)
+        eW = rel_fro(from_gpu_kf(g.get_w64()), st.W)
+        _, A, B, _ = g.get()
+        eA = rel_fro(from_gpu_kf(A), st.A)
+        eB = rel_fro(from_gpu_kf(B), st.B)
+        eH = rel_fro(H.cpu().double().numpy().T, Hr)
+        el = abs(loss.item() - st.last_loss) / st.last_loss
+        print(f"[tile] F={F} K={K} b={b}: W {eW:.2e} A {eA:.2e} B {eB:.2e} H {eH:.2e} loss {el:.2e}")
+        assert eW < 2e-2 and eA < 2e-2 and eB < 2e-2 and eH < 5e-2
+        # one step's loss: 1e-3 once the minibatch averages the BF16 rounding of
+        # its products; tiny shapes (K = 1: no averaging over components) 5e-3
+        assert el < (1e-3 if F * K * b >= 4096 else 5e-3)
+        assert g.status() == 0
+        g.close()
+    finally:
+        bd.tune_clear()
+
+
 @pytest.mark.parametrize("precision", ["bf16", "fp16", "fp32"])
 def test_pass_accuracy_matches_stated_tolerance(precision):
     """F=513, K=50, b=128, I=20 over 24 minibatches (a prefix of the benchmark
