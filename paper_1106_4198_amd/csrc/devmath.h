@@ -29,6 +29,27 @@ __device__ inline double dis_term(double y, double x) {
     return d - log(u);
 }
 
+// The same term in FP32 from y and r = 1/x (the reciprocal the fit already
+// has): u = y r, d = u - 1; |d| < 1/8 sums the series of d - log(1 + d) to
+// d^9 (truncation below 2^-24 of the term), else d - log u.  The fused FP32
+// and 16-bit fits evaluate the frame loss with it and sum it in FP64.
+__device__ inline float dis_term32(float y, float r) {
+    const float u = y * r;
+    const float d = u - 1.f;
+    if (fabsf(d) < 0.125f) {
+        float s = -1.f / 9.f;
+        s = fmaf(s, d, 1.f / 8.f);
+        s = fmaf(s, d, -1.f / 7.f);
+        s = fmaf(s, d, 1.f / 6.f);
+        s = fmaf(s, d, -1.f / 5.f);
+        s = fmaf(s, d, 1.f / 4.f);
+        s = fmaf(s, d, -1.f / 3.f);
+        s = fmaf(s, d, 1.f / 2.f);
+        return s * d * d;
+    }
+    return d - __logf(u);
+}
+
 // Sum over the 64 lanes of a wave in a fixed order, the result in every
 // lane: 8-lane groups with DPP (xor 1, xor 2, half-row mirror), lanes 8 apart
 // (row_ror 8), then 16-lane rows and 32-lane halves with the gfx950

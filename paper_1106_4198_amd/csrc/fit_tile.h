@@ -27,6 +27,7 @@
 #pragma once
 
 #include "common.h"
+#include "devmath.h"
 
 namespace isnmf {
 namespace tile {
@@ -53,24 +54,6 @@ typedef float float2v __attribute__((ext_vector_type(2)));
 // two FP32 -> two bf16 (round to nearest even), a in the low half
 __device__ inline uint32_t pack2(float a, float b) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){a, b}, bf16x2));
-}
-
-// d_IS(y, x) = u - 1 - log u with u = y / x = y * r (FP32; series near u = 1)
-__device__ inline float dis32(float y, float r) {
-    const float u = y * r;
-    const float d = u - 1.f;
-    if (fabsf(d) < 0.125f) {
-        float s = -1.f / 9.f;
-        s = fmaf(s, d, 1.f / 8.f);
-        s = fmaf(s, d, -1.f / 7.f);
-        s = fmaf(s, d, 1.f / 6.f);
-        s = fmaf(s, d, -1.f / 5.f);
-        s = fmaf(s, d, 1.f / 4.f);
-        s = fmaf(s, d, -1.f / 3.f);
-        s = fmaf(s, d, 1.f / 2.f);
-        return s * d * d;
-    }
-    return d - __logf(u);
 }
 
 // LDS bytes of the two W operand arrays for (S contraction steps of 32
@@ -137,6 +120,7 @@ __device__ inline void body(const FitDesc &a, int n_first) {
         vp[t][0] = pack2(vprime(t, 0, v[0]), vprime(t, 1, v[1]));
         vp[t][1] = pack2(vprime(t, 2, v[2]), vprime(t, 3, v[3]));
     }
+    if (bad) atomicOr(a.flags, FLAG_NONFINITE_V);
     // unpacked where used: the empty asm keeps the compiler from hoisting
     // the FP32 values out of the update loop (that would undo the packing)
     auto vq = [&](int t, int j) {
@@ -259,7 +243,7 @@ __device__ inline void body(const FitDesc &a, int n_first) {
             const float ve = vprime(t, j, load_v(t, j));
             r1[j] = r;
             r2[j] = ve * r * r;
-            if (row0 + j < F) l += dis32(ve, r);
+            if (row0 + j < F) l += dis_term32(ve, r);
         }
         ls += double(l);
         if (fok && row0 < F) {   // FR is a multiple of 64: rows row0..row0+3 are in the buffer

@@ -95,7 +95,6 @@ __device__ inline void body(const FitDesc &a, int fr) {
         }
     }
     float ve[RF];   // eps + v (0 past F)
-    float vr[RF];
     int bad = 0;
 #pragma unroll
     for (int r = 0; r < RF; ++r) {
@@ -103,7 +102,6 @@ __device__ inline void body(const FitDesc &a, int fr) {
         const bool ok = r < RL || last_ok;
         const float v = ok ? a.V[(size_t)fr * a.ldv + f] : 0.f;
         bad |= !isfinite(v);
-        vr[r] = v;
         ve[r] = ok ? eps + v : 0.f;
     }
     if (bad) atomicOr(a.flags, FLAG_NONFINITE_V);
@@ -205,12 +203,11 @@ __device__ inline void body(const FitDesc &a, int fr) {
     model();
     double lsum = 0.0;
     auto finish_row = [&](int base) {
-        float xs = 1.f, vs = 0.f, es = 0.f;
+        float xs = 1.f, es = 0.f;
 #pragma unroll
         for (int r = base; r < RF && r < base + 8; ++r)
             if ((r & 7) == q) {
                 xs = x[r];
-                vs = vr[r];
                 es = ve[r];
             }
         const int r = base + q;
@@ -219,7 +216,7 @@ __device__ inline void body(const FitDesc &a, int fr) {
             const float ir = __builtin_amdgcn_rcpf(xs);
             a.R1[(size_t)fr * a.FR + f] = ir;
             a.R2[(size_t)fr * a.FR + f] = es * ir * ir;
-            lsum += dis_term(a.epsd + double(vs), double(xs));
+            lsum += double(dis_term32(es, ir));
         }
     };
     finish_row(0);

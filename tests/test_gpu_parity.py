@@ -362,3 +362,93 @@ def test_repeatable_bitwise(kernel):
     torch.cuda.synchronize()
     for x, y in zip(*outs):
         assert torch.equal(x, y)
+
+
+# ---------------------------------------------------------------- edge cases
+
+@pytest.mark.parametrize("precision,variant", [("fp32", "valu"), ("fp32", "mfma"), ("bf16", "tile"),
+                                               ("bf16", "mfma"), ("fp16", "mfma")])
+def test_nonfinite_input_flag_every_fused_variant(precision, variant):
+    F, K, b = 257, 20, 40
+    say(f"nonfinite {precision}/{variant}")
+    bd.tune_clear()
+    if variant == "valu":
+        bd.tune_set(F, K, "fp32", 8, 0, 0)
+    if variant == "tile":
+        bd.tune_set(F, K, "bf16", 8, -1, 0)
+    try:
+        for bad in (np.nan, np.inf):
+            V, W0 = synth.problem(F, K, b, seed=83)
+            V[100, 17] = bad
+            g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b,
+                               precision=precision)
+            assert g.kernel_used == "fused"
+            g.step(torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV))
+            assert g.status() & 1, (precision, variant, bad)
+            g.close()
+    finally:
+        bd.tune_clear()
+
+
+@pytest.mark.parametrize("variant", ["mfma", "valu"])
+def test_minibatch_above_one_fold_slice(variant):
+    """b = 1300 frames: the fold sums three slices of 512 frames."""
+    F, K = 257, 20
+    with (valu_variant(F, K) if variant == "valu" else contextlib.nullcontext()):
+        compare_step(F, K, 1300, 10, "fp32", "fused", seed=61, tol=1e-5, steps_before=1)
+
+
+def test_tile_variant_above_one_fold_slice():
+    F, K, b = 257, 40, 1100
+    say("tile multi-slice")
+    bd.tune_clear()
+    bd.tune_set(F, K, "bf16", 8, -1, 0)
+    try:
+        V, W0 = synth.problem(F, K, b, seed=62)
+        st = oracle.OnlineState(W0.astype(np.float64))
+        g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b, precision="bf16")
+        loss = torch.zeros((), dtype=torch.float64, device=DEV)
+        g.step(torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV), None, loss)
+        st.step(V.astype(np.float64), iters=20)
+        assert rel_fro(from_gpu_kf(g.get_w64()), st.W) < 2e-2
+        assert abs(loss.item() - st.loss_sum) <= 1e-3 * st.loss_sum
+        assert g.status() == 0
+    finally:
+        bd.tune_clear()
+
+
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_silent_frames(kernel):
+    """Frames that are entirely zero (v' = eps): every fit handles them."""
+    F, K, b = 129, 8, 12
+    say(f"silent frames {kernel}")
+    st = make_state(F, K, 71, 2)
+    Vb = synth.frames(F, K, b, 71 + 1000)
+    Vb[:, [0, 5, 11]] = 0.0
+    g = gpu_from_state(st, b, eps=1e-12, inner_iters=20, kernel=kernel)
+    Hg, lg, _ = run_step(g, Vb)
+    Hr, _, fl = st.step(Vb.astype(np.float64), iters=20)
+    assert fl == 0
+    assert_close(from_gpu_kf(g.get_w64()), st.W, 1e-5, "W")
+    assert_close(Hg, Hr, 2e-6 if kernel == "plain" else 2e-5, "H")
+    assert abs(lg - st.last_loss) <= 1e-5 * abs(st.last_loss)
+
+
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_eps_zero(kernel):
+    """eps = 0 (the plain IS divergence of eq. 1) on strictly positive data."""
+    F, K, b = 200, 12, 16
+    say(f"eps 0 {kernel}")
+    V, W0 = synth.problem(F, K, 2 * b, seed=73)
+    V = np.maximum(V, 1e-6).astype(np.float32)
+    st = oracle.OnlineState(W0.astype(np.float64))
+    st.step(V[:, :b].astype(np.float64), iters=10, eps=0.0)
+    g = bd.OnlineISNMF(to_gpu_kf(st.W, np.float32, torch), b, eps=0.0, inner_iters=10, kernel=kernel,
+                       A0=to_gpu_kf(st.A, np.float64, torch), B0=to_gpu_kf(st.B, np.float64, torch))
+    g.set_w64(to_gpu_kf(st.W, np.float64, torch))
+    loss = torch.zeros((), dtype=torch.float64, device=DEV)
+    g.step(torch.from_numpy(np.ascontiguousarray(V[:, b:].T)).to(DEV), None, loss)
+    st.step(V[:, b:].astype(np.float64), iters=10, eps=0.0)
+    assert_close(from_gpu_kf(g.get_w64()), st.W, 1e-5, "W")
+    assert abs(loss.item() - st.last_loss) <= 1e-5 * st.last_loss
+    assert g.status() == 0
