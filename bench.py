@@ -183,10 +183,13 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0):
     return out
 
 
-def bench_served(bd, synth, torch, np, dev, S, n_chunks, duration_s, threads, seed0):
+def bench_served(bd, synth, torch, np, dev, S, n_chunks, duration_s, threads, seed0,
+                 tune="latency"):
     """Continuous batching: S sessions (F in {257,513}, K in {32,64}, BF16
     products), chunks of U[1,512] frames.  Capacity with every chunk queued at
-    once, then Poisson arrivals at 50% and 90% of it: p50/p99 chunk latency."""
+    once, then Poisson arrivals at 50% and 90% of it: p50/p99 chunk latency.
+    tune: kernel variants timed at one mean chunk ("latency") or at a whole
+    served step ("throughput", capacity only)."""
     rng = np.random.default_rng(seed0)
     Fs = rng.choice([257, 513], size=S)
     Ks = rng.choice([32, 64], size=S)
@@ -195,6 +198,14 @@ def bench_served(bd, synth, torch, np, dev, S, n_chunks, duration_s, threads, se
     for Fi in (257, 513):
         V = synth.frames(Fi, 50, pool_n, seed0 + Fi, threads=threads)
         pools[Fi] = torch.from_numpy(np.ascontiguousarray(V.T)).to(dev)
+    # kernel variant per shape, timed at one mean chunk (latency) or at a
+    # served step's size: all sessions of a shape with a mean chunk each
+    variants = {}
+    for Fi in (257, 513):
+        for Ki in (32, 64):
+            nb = 256 if tune == "latency" else int(np.sum((Fs == Fi) & (Ks == Ki))) * 256
+            bd.autotune(Fi, Ki, max(nb, 256), precision="bf16", trials=2)
+            variants[f"{Fi}x{Ki}"] = list(bd.tune_get(Fi, Ki, "bf16"))
     hs = [bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(
         synth.initial_dictionary(int(Fs[i]), int(Ks[i]), seed0 + i).T)).to(dev), 512,
         precision="bf16") for i in range(S)]
@@ -228,9 +239,9 @@ def bench_served(bd, synth, torch, np, dev, S, n_chunks, duration_s, threads, se
     lens = rng.integers(1, 513, size=n_chunks)
     sess = rng.integers(0, S, size=n_chunks)
     cap = run(np.zeros(n_chunks), sess, lens)
-    out = {"sessions": S, "precision": "bf16", "chunk_frames": "U[1,512]",
-           "capacity": cap}
-    for load in (0.5, 0.9):
+    out = {"sessions": S, "precision": "bf16", "chunk_frames": "U[1,512]", "tuned_for": tune,
+           "variants": variants, "capacity": cap}
+    for load in ((0.5, 0.9) if tune == "latency" else ()):
         rate = load * cap["frames_per_s"] / lens.mean()          # chunks per second
         n = max(64, int(rate * duration_s))
         l2 = rng.integers(1, 513, size=n)
@@ -240,6 +251,7 @@ def bench_served(bd, synth, torch, np, dev, S, n_chunks, duration_s, threads, se
         out[f"load_{int(load * 100)}"] = run(arr, s2, l2)
     for h in hs:
         h.close()
+    bd.tune_clear()
     return out
 
 
@@ -400,6 +412,11 @@ def main() -> int:
         forms["served"] = bench_served(bd, synth, torch, np, dev, args.serve_sessions,
                                        args.serve_chunks, args.serve_seconds, thr, 90000)
         print(f"[bench] served: {forms['served']}", file=sys.stderr, flush=True)
+        forms["served_throughput"] = bench_served(bd, synth, torch, np, dev, args.serve_sessions,
+                                                  args.serve_chunks, args.serve_seconds, thr,
+                                                  90000, tune="throughput")
+        print(f"[bench] served (throughput variants): {forms['served_throughput']}",
+              file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,

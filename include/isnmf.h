@@ -252,8 +252,10 @@ int isnmf_multi_destroy(isnmf_multi *m);
  * hbm_budget: admission by HBM footprint -- isnmf_server_open fails with
  *   ISNMF_ENOMEM when the session's `footprint` (its workspace bytes, or any
  *   figure the caller charges) would exceed it.
- * Sessions must use the fused kernel with one 64-row chunk per wave and
- * K <= 64 (F <= 516); chunks hold 1..min(b_max, 512, max_frames) frames.
+ * Sessions must use the fused kernel: an MFMA tile variant with one 64-row
+ * chunk per wave and K <= 64 (F <= 516), or the BF16 16-frame tile variant
+ * (cpw = -1, F <= 640, K <= 64); chunks hold 1..min(b_max, 512, max_frames)
+ * frames.
  * Calls are not thread-safe.
  */
 typedef struct isnmf_server isnmf_server;
@@ -301,9 +303,9 @@ int isnmf_autotune(int F, int K, int b, const isnmf_params *p, int trials, int *
  * nw = waves per workgroup, cpw = 64-row chunks per wave, wg = W read from
  * its 16-bit copies in memory instead of registers.  cpw = 0 denotes the
  * FP32 VALU variant (one frame per workgroup of nw = 8 waves) and cpw = -1
- * the BF16 16-frame tile variant (16 frames per workgroup of nw waves on
- * 16x16x32 MFMA); the served form runs neither (isnmf_server_open returns
- * ISNMF_EUNSUPPORTED for a handle created with them).  The autotuner times
+ * the BF16 16-frame tile variant (16 frames per wave, nw = 8 waves per
+ * workgroup, on 16x16x32 MFMA); the served form runs the latter but not the
+ * VALU variant (isnmf_server_open returns ISNMF_EUNSUPPORTED for it).  The autotuner times
  * the variants at the b it is given: a single stream's minibatch for
  * latency, or the frames of all streams of a batched step for throughput. */
 int isnmf_tune_get(int F, int K, int precision, int *nw, int *cpw, int *wg);

@@ -91,6 +91,15 @@ struct FitDesc {
     int *flags;
 };
 
+// One chunk of a served step: session (index in the server's device tables),
+// frame count, frames (the session's frame stride ldv).
+struct ServeWork {
+    int sess;
+    int b;
+    const float *V;
+    int ldv, pad;
+};
+
 // Kernel variant of the fused fit for a shape: an MFMA tile variant of
 // fit_body.h (cpw >= 1: NW waves x CPW chunks of 64 rows, NF frames per
 // workgroup), the VALU variant of fit_valu.h (cpw = 0: one frame per
@@ -142,6 +151,9 @@ hipError_t launch_fit_valu_multi(const FitClass &c, const FitDesc *d, const int2
 hipError_t launch_fit_tile(const FitDesc &a, const FitClass &c, int b, hipStream_t s);
 hipError_t launch_fit_tile_multi(const FitClass &c, const FitDesc *d, const int2 *items, int n,
                                  const long long *cur, const int *beff, hipStream_t s);
+// ... and over a served step's work list: n chunks, `tiles` tiles of 128 frames each.
+hipError_t launch_fit_tile_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
+                                int tiles, hipStream_t s);
 // Frames per batched work item of a fit class.
 inline int frames_per_item(const FitClass &c) { return c.cpw == -1 ? 128 : NF; }
 // Every fit variant valid for the shape (the default first); returns the count.

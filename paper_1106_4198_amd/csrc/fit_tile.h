@@ -293,6 +293,31 @@ __global__ __launch_bounds__(NWT * 64) void fit_tile_multi_kernel(const FitDesc 
     body<S, KS>(a, it.y * FPW);
 }
 
+// Served form: grid (chunk i, 128-frame tile j) over a step's work list.
+template <int S, int KS>
+__global__ __launch_bounds__(NWT * 64) void fit_tile_work_kernel(const FitDesc *__restrict__ tab,
+                                                                 const ServeWork *__restrict__ work) {
+    const ServeWork wk = work[blockIdx.x];
+    if ((int)blockIdx.y * FPW >= wk.b) return;   // uniform per workgroup
+    FitDesc a = tab[wk.sess];
+    a.b = wk.b;
+    a.V = wk.V;
+    a.ldv = wk.ldv;
+    body<S, KS>(a, blockIdx.y * FPW);
+}
+
+template <int S, int KS>
+hipError_t launch_work_one(const FitDesc *tab, const ServeWork *work, int n, int tiles,
+                           hipStream_t s) {
+    constexpr size_t lds = lds_bytes(S, KS);
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&fit_tile_work_kernel<S, KS>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess) return attr;
+    fit_tile_work_kernel<S, KS><<<dim3(n, tiles), NWT * 64, lds, s>>>(tab, work);
+    return hipGetLastError();
+}
+
 template <int S, int KS>
 hipError_t launch_one(const FitDesc *a, int b, const FitDesc *d, const int2 *items, int n,
                       const long long *cur, const int *beff, hipStream_t s) {
@@ -338,14 +363,33 @@ hipError_t launch_ks(int S, const FitDesc *a, int b, const FitDesc *d, const int
     }
 }
 
+template <int KS>
+hipError_t launch_work_ks(int S, const FitDesc *tab, const ServeWork *work, int n, int tiles,
+                         hipStream_t st) {
+    switch (S) {
+#define ISNMF_TILE_S(SV) \
+    case SV: return launch_work_one<SV, KS>(tab, work, n, tiles, st);
+        ISNMF_TILE_S(1) ISNMF_TILE_S(2) ISNMF_TILE_S(3) ISNMF_TILE_S(4) ISNMF_TILE_S(5)
+        ISNMF_TILE_S(6) ISNMF_TILE_S(7) ISNMF_TILE_S(8) ISNMF_TILE_S(9) ISNMF_TILE_S(10)
+        ISNMF_TILE_S(11) ISNMF_TILE_S(12) ISNMF_TILE_S(13) ISNMF_TILE_S(14) ISNMF_TILE_S(15)
+        ISNMF_TILE_S(16) ISNMF_TILE_S(17) ISNMF_TILE_S(18) ISNMF_TILE_S(19) ISNMF_TILE_S(20)
+#undef ISNMF_TILE_S
+        default: return hipErrorNotSupported;
+    }
+}
+
 #define ISNMF_TILE_EXTERN(KSV)                                                                   \
     extern template hipError_t launch_ks<KSV>(int, const FitDesc *, int, const FitDesc *,       \
                                               const int2 *, int, const long long *, const int *, \
-                                              hipStream_t);
+                                              hipStream_t);                                      \
+    extern template hipError_t launch_work_ks<KSV>(int, const FitDesc *, const ServeWork *, int, \
+                                                   int, hipStream_t);
 #define ISNMF_TILE_INSTANTIATE(KSV)                                                       \
     template hipError_t launch_ks<KSV>(int, const FitDesc *, int, const FitDesc *,       \
                                        const int2 *, int, const long long *, const int *, \
-                                       hipStream_t);
+                                       hipStream_t);                                      \
+    template hipError_t launch_work_ks<KSV>(int, const FitDesc *, const ServeWork *, int, \
+                                            int, hipStream_t);
 
 }  // namespace tile
 }  // namespace isnmf

@@ -43,4 +43,12 @@ hipError_t launch_fit_tile_multi(const FitClass &c, const FitDesc *d, const int2
     return launch(c, nullptr, 0, d, items, n, cur, beff, s);
 }
 
+hipError_t launch_fit_tile_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
+                                int tiles, hipStream_t s) {
+    if (!c.ok || c.cpw != -1 || c.nw != tile::NWT) return hipErrorNotSupported;
+    if (c.kmax == 32) return tile::launch_work_ks<1>(c.rf, tab, work, n, tiles, s);
+    if (c.kmax == 64) return tile::launch_work_ks<2>(c.rf, tab, work, n, tiles, s);
+    return hipErrorNotSupported;
+}
+
 }  // namespace isnmf

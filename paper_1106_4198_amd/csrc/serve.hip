@@ -41,12 +41,7 @@ void isnmf_handle_advance(isnmf_online *h, long long frames, hipStream_t s);
 
 namespace {
 
-struct Work {
-    int sess;          // index in the device tables
-    int b;             // frames of the chunk
-    const float *V;    // the chunk's frames (ld = the session's ldv)
-    int ldv, pad;
-};
+typedef ServeWork Work;
 
 // ---- kernels (grids: x = work item of the class range, y = tile / column)
 
@@ -113,8 +108,13 @@ hipError_t serve_fit(const FitClass &c, const FitDesc *tab, const Work *work, in
     return hipErrorNotSupported;
 }
 
+// tiles: of NF frames for the MFMA tile variants, recomputed for the
+// 16-frame tile variant's 128-frame workgroups from max_b.
 hipError_t serve_fit_any(int prec, const FitClass &c, const FitDesc *tab, const Work *work, int n,
-                         int tiles, hipStream_t s) {
+                         int tiles, int max_b, hipStream_t s) {
+    if (c.cpw == -1)
+        return prec == 1 ? launch_fit_tile_work(c, tab, work, n, (max_b + 127) / 128, s)
+                         : hipErrorNotSupported;
     if (prec == 1) return serve_fit<1>(c, tab, work, n, tiles, s);
     if (prec == 2) return serve_fit<2>(c, tab, work, n, tiles, s);
     return serve_fit<0>(c, tab, work, n, tiles, s);
@@ -250,15 +250,15 @@ int launch_step(isnmf_server *s) {
         int hi = lo + 1, maxb = s->reqs[slot->reqs[lo]].n;
         while (hi < n) {
             const auto &B = s->sess[pick[hi]];
-            if (B.prec != A.prec || B.cls.nw != A.cls.nw || B.cls.kmax != A.cls.kmax || B.F != A.F ||
-                B.K != A.K)
+            if (B.prec != A.prec || B.cls.nw != A.cls.nw || B.cls.cpw != A.cls.cpw ||
+                B.cls.kmax != A.cls.kmax || B.F != A.F || B.K != A.K)
                 break;
             maxb = std::max(maxb, s->reqs[slot->reqs[hi]].n);
             ++hi;
         }
         const int cnt = hi - lo;
         const int tiles = (maxb + NF - 1) / NF;
-        if (serve_fit_any(A.prec, A.cls, s->d_fit, slot->dev + lo, cnt, tiles, st) != hipSuccess)
+        if (serve_fit_any(A.prec, A.cls, s->d_fit, slot->dev + lo, cnt, tiles, maxb, st) != hipSuccess)
             return -1;
         const dim3 fg(cnt, (A.F + 15) / 16);
         switch (fold_ktm(A.K)) {
@@ -347,7 +347,9 @@ int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *s
     if (isnmf_handle_kernel(h) != ISNMF_KERNEL_FUSED) return ISNMF_EUNSUPPORTED;
     const OnlineDev &d = *isnmf_handle_dev(h);
     const FitClass &c = *isnmf_handle_class(h);
-    if (c.wg || c.cpw != 1 || (c.nw != 4 && c.nw != 8) || c.kmax > 64) return ISNMF_EUNSUPPORTED;
+    const bool tile16 = c.cpw == -1 && prec_of(p) == 1;
+    if (!tile16 && (c.wg || c.cpw != 1 || (c.nw != 4 && c.nw != 8) || c.kmax > 64))
+        return ISNMF_EUNSUPPORTED;
     if (s->used + footprint > s->budget) return ISNMF_ENOMEM;   // admission by HBM footprint
     const int idx = (int)s->sess.size();
     FitDesc fd = make_fit_desc(d, nullptr, d.F, 1, p.inner_iters, p.eps, 0, nullptr, d.K);

@@ -115,3 +115,51 @@ def test_served_form_rejects_the_valu_variant():
         srv.open(g)
     assert ei.value.code == bd.EUNSUPPORTED
     srv.close()
+
+
+def test_served_tile_sessions_equal_alone_bitwise():
+    """BF16 sessions on the 16-frame tile variant (chunks of 1..300 frames,
+    several 128-frame tiles) are served bitwise as they run alone."""
+    say("served tile sessions vs alone")
+    bd.tune_clear()
+    for F, K in ((257, 32), (513, 64), (513, 32)):
+        bd.tune_set(F, K, "bf16", 8, -1, 0)
+    try:
+        rng = np.random.default_rng(11)
+        data = []
+        for i in range(9):
+            F, K = [(257, 32), (513, 64), (513, 32)][i % 3]
+            lens = rng.integers(1, 301, size=3)
+            V, W0 = synth.problem(F, K, int(lens.sum()), seed=1100 + i)
+            Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+            chunks, o = [], 0
+            for L in lens:
+                chunks.append(Vt[o:o + int(L)])
+                o += int(L)
+            data.append((torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), chunks))
+        alone = []
+        for W0, chunks in data:
+            g = bd.OnlineISNMF(W0, 300, precision="bf16")
+            for c in chunks:
+                g.step(c)
+            alone.append(g)
+        srv = bd.Server(max_sessions=9, max_per_step=9, max_frames=2700, inflight=2)
+        served = []
+        for W0, chunks in data:
+            g = bd.OnlineISNMF(W0, 300, precision="bf16")
+            served.append((g, srv.open(g)))
+        for k in range(3):
+            for i in range(len(data)):
+                srv.submit(served[i][1], data[i][1][k])
+            srv.pump()
+        srv.drain()
+        torch.cuda.synchronize()
+        for i, (ga, (gs, _)) in enumerate(zip(alone, served)):
+            Wa, Aa, Ba, ta = ga.get()
+            Ws, As, Bs, ts = gs.get()
+            assert ta == ts
+            assert torch.equal(ga.get_w64(), gs.get_w64()), i
+            assert torch.equal(Aa, As) and torch.equal(Ba, Bs), i
+        srv.close()
+    finally:
+        bd.tune_clear()
