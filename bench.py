@@ -183,6 +183,38 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0):
     return out
 
 
+def bench_multipass(bd, torch, np, Vt, Wt, N, passes, seed):
+    """Warm-restart passes over a finite set of N frames (section 2.3): H of
+    all N frames resident, each pass in its own seeded random order, FP32
+    fused path.  frames/s counts visits (passes x N)."""
+    rng = np.random.default_rng(seed)
+    perm = torch.from_numpy(np.stack([rng.permutation(N) for _ in range(passes)])
+                            .astype(np.int32)).to(Vt.device)
+    V = Vt[:N]
+    g = bd.OnlineISNMF(Wt, B, inner_iters=ITERS, warm=True)
+    H = torch.ones((N, K), dtype=torch.float32, device=Vt.device)
+    nw = min(N, 4 * B)                                  # warm-up: one pass over a prefix
+    pw = torch.arange(nw, dtype=torch.int32, device=Vt.device).view(1, nw)
+    g.run_passes(V[:nw], pw, B, H[:nw])
+    g.close()
+    g = bd.OnlineISNMF(Wt, B, inner_iters=ITERS, warm=True)
+    H = torch.ones((N, K), dtype=torch.float32, device=Vt.device)
+    loss = torch.zeros((), dtype=torch.float64, device=Vt.device)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    g.run_passes(V, perm, B, H, loss)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert g.status() == 0
+    g.close()
+    return {"value": passes * N / (ms / 1e3), "unit": "frames/s (visits)", "frames": N,
+            "passes": passes, "b": B, "ms": ms,
+            "loss_per_entry": loss.item() / (passes * N * F)}
+
+
 def bench_served(bd, synth, torch, np, dev, S, n_chunks, duration_s, threads, seed0,
                  tune="latency"):
     """Continuous batching: S sessions (F in {257,513}, K in {32,64}, BF16
@@ -398,6 +430,10 @@ def main() -> int:
     torch.cuda.synchronize()
     plain_fps = p_steps * B / (e0.elapsed_time(e1) / 1e3)
     gp.close()
+
+    forms["multipass"] = bench_multipass(bd, torch, np, Vt, Wt, min(N, 65536), 3, args.seed + 7)
+    print(f"[bench] multipass: {forms['multipass']['value']:.4g} frames/s", file=sys.stderr,
+          flush=True)
 
     if not args.no_forms:
         thr = cpu_threads()

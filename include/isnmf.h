@@ -144,6 +144,25 @@ int isnmf_online_pass(isnmf_online *h, const float *V, int ldv, long long n_fram
                       float *H, int ldh, double *d_loss_sum, void *stream);
 
 /*
+ * Several passes over a finite set of N frames with warm restarts (section
+ * 2.3, finite data sets): the activations of all N frames stay resident in H,
+ * and pass p visits the frames in the order perm[p N .. p N + N), in
+ * minibatches of b (the last one shorter when b does not divide N).  Each
+ * minibatch is one isnmf_online_step on the visited frames whose inner fit
+ * starts from their h of the previous visit (H as given on the first), and
+ * whose fitted, rescale-compensated h is written back to H.
+ * The handle must use ISNMF_H_WARM.  V: device F x N FP32 (ldv >= F).
+ * perm: device int, passes x N entries, each pass a permutation of 0..N-1;
+ *   an index outside [0, N) reads zero frames, writes nothing and sets the
+ *   status bit 8.  H: device K x N FP32 (ldh >= K), in/out.
+ * d_loss_sum as in isnmf_online_step (the total of every visit is added).
+ * 1 <= b <= b_max, passes >= 1.  The frames and activations of a minibatch
+ * are gathered into workspace buffers the handle reserves under H_WARM.
+ */
+int isnmf_online_passes(isnmf_online *h, const float *V, int ldv, long long N, const int *perm,
+                        int passes, int b, float *H, int ldh, double *d_loss_sum, void *stream);
+
+/*
  * Fit activations only (the inner argmin of Algorithm 1 at the current W, no
  * change to A, B or W): e.g. held-out evaluation, or timing of the fit.
  * Vb, b, Hb, ldh as in isnmf_online_step (Hb may be NULL); d_loss_sum

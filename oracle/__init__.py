@@ -221,3 +221,26 @@ def online_pass(V, W0, b: int, iters: int = 20, eps: float = 1e-12, rho: float =
     if keep_h:
         return st, np.asfortranarray(np.concatenate(Hs, axis=1)) if Hs else np.zeros((st.K, 0))
     return st
+
+
+def online_passes(V, W0, b: int, perms, iters: int = 20, eps: float = 1e-12, rho: float = 1.0,
+                  normalize: bool = True, H0=None, A0=None, B0=None):
+    """Several passes of online IS-NMF over a finite set with warm restarts
+    (section 2.3): the K x N activations stay resident, pass p visits the
+    frames in the order perms[p] in minibatches of b (a short final one), and
+    each frame's inner fit starts from its value of the previous visit (1 on
+    the first, or H0).  Returns (OnlineState, H)."""
+    V = _f64(V)
+    F, N = V.shape
+    st = OnlineState(W0, A0, B0)
+    H = np.ones((st.K, N), order="F") if H0 is None else _f64(H0, (st.K, N)).copy(order="F")
+    for order in perms:
+        order = np.asarray(order, dtype=np.int64)
+        if sorted(order.tolist()) != list(range(N)):
+            raise ValueError("each pass must visit every frame once")
+        for s in range(0, N, b):
+            idx = order[s:s + b]
+            Hb, _, _ = st.step(V[:, idx], iters=iters, eps=eps, rho=rho, normalize=normalize,
+                               H=H[:, idx])
+            H[:, idx] = Hb
+    return st, H

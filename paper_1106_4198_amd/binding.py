@@ -60,6 +60,7 @@ def _load():
                                   ctypes.POINTER(i)]),
         "isnmf_online_destroy": (i, [vp]),
         "isnmf_online_pass": (i, [vp, vp, i, ctypes.c_longlong, i, vp, i, vp, vp]),
+        "isnmf_online_passes": (i, [vp, vp, i, ctypes.c_longlong, vp, i, i, vp, i, vp, vp]),
         "isnmf_online_fit": (i, [vp, vp, i, i, vp, i, vp, vp]),
         "isnmf_online_set_timing": (i, [vp, i, i]),
         "isnmf_online_timing": (i, [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(d)]),
@@ -104,7 +105,7 @@ _lib = _load()
 EXPORTED = ("isnmf_params_default", "isnmf_strerror", "isnmf_online_workspace_size",
             "isnmf_online_init", "isnmf_online_step", "isnmf_online_get", "isnmf_online_get_w64",
             "isnmf_online_set", "isnmf_online_set_w64", "isnmf_online_status", "isnmf_online_info",
-            "isnmf_online_destroy", "isnmf_online_pass", "isnmf_online_fit",
+            "isnmf_online_destroy", "isnmf_online_pass", "isnmf_online_passes", "isnmf_online_fit",
             "isnmf_online_set_timing", "isnmf_online_timing",
             "isnmf_multi_workspace_size", "isnmf_multi_create", "isnmf_multi_step",
             "isnmf_multi_run", "isnmf_multi_frames_left", "isnmf_multi_destroy",
@@ -231,6 +232,21 @@ class OnlineISNMF:
         _check(_lib.isnmf_online_pass(self._h, _ptr(V), _ld(V), int(N), int(b), _ptr(H),
                                       _ld(H) if H is not None else self.K, _ptr(loss_sum),
                                       _stream(stream)), "isnmf_online_pass")
+
+    def run_passes(self, V: torch.Tensor, perm: torch.Tensor, b: int, H: torch.Tensor,
+                   loss_sum=None, stream=None):
+        """Warm-restart passes over the finite set V (N, F): pass p visits the
+        frames in the order perm[p] (perm: (passes, N) int32 on the device),
+        in minibatches of b; H (N, K) holds every frame's h across passes."""
+        _req(V, torch.float32, name="V")
+        N = V.shape[0]
+        _req(H, torch.float32, (N, self.K), "H")
+        if perm.dtype != torch.int32 or perm.dim() != 2 or perm.shape[1] != N or \
+                not perm.is_contiguous() or perm.device != V.device:
+            raise ValueError("perm must be a contiguous (passes, N) int32 tensor on V's device")
+        _check(_lib.isnmf_online_passes(self._h, _ptr(V), _ld(V), int(N), _ptr(perm),
+                                        int(perm.shape[0]), int(b), _ptr(H), _ld(H),
+                                        _ptr(loss_sum), _stream(stream)), "isnmf_online_passes")
 
     def fit(self, Vb: torch.Tensor, H: torch.Tensor | None = None, loss_sum=None, stream=None):
         """Inner fit only at the current W (A, B, W unchanged)."""

@@ -94,6 +94,9 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
     t.lossel = with_lossel ? (double *)take((size_t)b_max * FR * 8) : nullptr;
     const size_t pb = fold_partial_bytes(F, K, b_max);
     t.part = pb ? (float *)take(pb) : nullptr;
+    const bool warm = p.h_init == ISNMF_H_WARM;   // gather buffers of isnmf_online_passes
+    t.Vg = warm ? (float *)take((size_t)b_max * F * 4) : nullptr;
+    t.Hg = warm ? (float *)take((size_t)b_max * K * 4) : nullptr;
     if (d) *d = t;
     return off;
 }
@@ -280,6 +283,29 @@ int isnmf_online_pass(isnmf_online *h, const float *V, int ldv, long long n_fram
                                          H ? H + (size_t)s0 * ldh : nullptr, ldh, d_loss_sum,
                                          nullptr, stream);
         if (st != ISNMF_OK) return st;
+    }
+    return ISNMF_OK;
+}
+
+int isnmf_online_passes(isnmf_online *h, const float *V, int ldv, long long N, const int *perm,
+                        int passes, int b, float *H, int ldh, double *d_loss_sum, void *stream) {
+    if (!h || !V || !perm || !H || N < 1 || passes < 1 || b < 1 || b > h->d.b_max) return ISNMF_EINVAL;
+    if (ldv < h->d.F || ldh < h->d.K || h->p.h_init != ISNMF_H_WARM || !h->d.Vg || !h->d.Hg)
+        return ISNMF_EINVAL;
+    const OnlineDev &d = h->d;
+    hipStream_t s = (hipStream_t)stream;
+    for (int p = 0; p < passes; ++p) {
+        for (long long s0 = 0; s0 < N; s0 += b) {
+            const int bb = (int)(N - s0 < b ? N - s0 : b);
+            const int *idx = perm + (size_t)p * N + s0;
+            if (launch_gather_rows(d.Vg, d.F, V, ldv, N, idx, bb, d.F, d.flags, s) != hipSuccess ||
+                launch_gather_rows(d.Hg, d.K, H, ldh, N, idx, bb, d.K, d.flags, s) != hipSuccess)
+                return ISNMF_EDEVICE;
+            const int st = isnmf_online_step(h, d.Vg, d.F, bb, d.Hg, d.K, d_loss_sum, nullptr, stream);
+            if (st != ISNMF_OK) return st;
+            if (launch_scatter_rows(H, ldh, N, d.Hg, d.K, idx, bb, d.K, s) != hipSuccess)
+                return ISNMF_EDEVICE;
+        }
     }
     return ISNMF_OK;
 }

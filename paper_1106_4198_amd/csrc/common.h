@@ -16,6 +16,7 @@ enum : int {
     FLAG_NONFINITE_V = 1,
     FLAG_GUARD_H = 2,
     FLAG_GUARD_W = 4,
+    FLAG_BAD_INDEX = 8,
 };
 
 // Rows per MFMA chunk of the fused fit: 16 blocks x 4 rows of v_mfma_f32_4x4x1_16b.
@@ -66,6 +67,7 @@ struct OnlineDev {
     void *Xt;            // plain path scratch: b_max x FR model values / loss terms
     double *lossel;      // plain path: b_max x FR per-element loss terms
     float *part;         // fold slice partials (b_max > 512) or null
+    float *Vg, *Hg;      // warm multi-pass: gathered minibatch frames (b_max x F) and h (b_max x K)
     int *flags;          // sticky flags
     unsigned *counter;   // spare device word (zeroed at init)
 };
@@ -179,6 +181,14 @@ hipError_t launch_rescale(const OnlineDev &d, int b, int update_w, int normalize
 
 // *d_loss_sum += sum of lossf[0..b) in index order (one block).
 hipError_t launch_loss_total(const double *lossf, int b, double *d_loss_sum, hipStream_t s);
+
+// Rows idx[0..n) of src (row stride lds, rows < N) to dst rows 0..n (stride
+// ldd), w floats each; out-of-range indices give zero rows and FLAG_BAD_INDEX.
+hipError_t launch_gather_rows(float *dst, int ldd, const float *src, long long lds, long long N,
+                              const int *idx, int n, int w, int *flags, hipStream_t s);
+// dst rows idx[i] (stride ldd, rows < N) <- src row i (stride lds); out-of-range skipped.
+hipError_t launch_scatter_rows(float *dst, long long ldd, long long N, const float *src, int lds,
+                               const int *idx, int n, int w, hipStream_t s);
 
 // Copy helpers.
 hipError_t launch_set_w(const OnlineDev &d, const float *W, int ldw, const double *W64,

@@ -86,7 +86,44 @@ __global__ void loss_total_kernel(const double *__restrict__ lossf, int b,
     if (lane == 0) *out += s;
 }
 
+__global__ void gather_rows_kernel(float *__restrict__ dst, int ldd, const float *__restrict__ src,
+                                   long long lds, long long N, const int *__restrict__ idx, int w,
+                                   int *flags) {
+    const int i = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= w) return;
+    const long long r = idx[i];
+    float v = 0.f;
+    if (r >= 0 && r < N)
+        v = src[r * lds + j];
+    else if (j == 0)
+        atomicOr(flags, FLAG_BAD_INDEX);
+    dst[(size_t)i * ldd + j] = v;
+}
+
+__global__ void scatter_rows_kernel(float *__restrict__ dst, long long ldd, long long N,
+                                    const float *__restrict__ src, int lds,
+                                    const int *__restrict__ idx, int w) {
+    const int i = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= w) return;
+    const long long r = idx[i];
+    if (r >= 0 && r < N) dst[r * ldd + j] = src[(size_t)i * lds + j];
+}
+
 }  // namespace
+
+hipError_t launch_gather_rows(float *dst, int ldd, const float *src, long long lds, long long N,
+                              const int *idx, int n, int w, int *flags, hipStream_t s) {
+    gather_rows_kernel<<<dim3((w + 255) / 256, n), 256, 0, s>>>(dst, ldd, src, lds, N, idx, w, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(float *dst, long long ldd, long long N, const float *src, int lds,
+                               const int *idx, int n, int w, hipStream_t s) {
+    scatter_rows_kernel<<<dim3((w + 255) / 256, n), 256, 0, s>>>(dst, ldd, N, src, lds, idx, w);
+    return hipGetLastError();
+}
 
 hipError_t launch_loss_total(const double *lossf, int b, double *d_loss_sum, hipStream_t s) {
     loss_total_kernel<<<1, 64, 0, s>>>(lossf, b, d_loss_sum);

@@ -452,3 +452,62 @@ def test_eps_zero(kernel):
     assert_close(from_gpu_kf(g.get_w64()), st.W, 1e-5, "W")
     assert abs(loss.item() - st.last_loss) <= 1e-5 * st.last_loss
     assert g.status() == 0
+
+
+# ---------------------------------------------------------------- multi-pass over a finite set
+
+# FP64 mode: the resident H crosses the ABI in FP32, so every h is rounded to
+# FP32 between visits (6e-8 relative) and the FP64 state follows it to ~1e-8.
+@pytest.mark.parametrize("precision,kernel,variant,tol", [("fp64", "plain", "", 1e-7),
+                                                          ("fp32", "plain", "", 1e-4),
+                                                          ("fp32", "fused", "mfma", 1e-4),
+                                                          ("fp32", "fused", "valu", 1e-4)])
+def test_multipass_warm_restarts_match_oracle(precision, kernel, variant, tol):
+    """Three passes over N = 100 frames, each in its own random order, minibatches
+    of 16 (a short last one), warm restarts from the resident H (section 2.3)."""
+    F, K, N, b, I, P = 129, 8, 100, 16, 10, 3
+    say(f"multipass {precision}/{kernel}/{variant}")
+    V, W0 = synth.problem(F, K, N, seed=121)
+    rng = np.random.default_rng(122)
+    perms = [rng.permutation(N) for _ in range(P)]
+    st, Href = oracle.online_passes(V.astype(np.float64), W0.astype(np.float64), b, perms, iters=I)
+    bd.tune_clear()
+    if variant == "valu":
+        bd.tune_set(F, K, "fp32", 8, 0, 0)
+    try:
+        g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b, warm=True,
+                           inner_iters=I, precision=precision, kernel=kernel)
+        H = torch.ones((N, K), dtype=torch.float32, device=DEV)
+        perm = torch.from_numpy(np.stack(perms).astype(np.int32)).to(DEV)
+        loss = torch.zeros((), dtype=torch.float64, device=DEV)
+        g.run_passes(torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV), perm, b, H, loss)
+        torch.cuda.synchronize()
+        _, A, B, t = g.get()
+        assert t == P * N
+        assert rel_fro(from_gpu_kf(g.get_w64()), st.W) <= tol
+        assert rel_fro(from_gpu_kf(A), st.A) <= tol and rel_fro(from_gpu_kf(B), st.B) <= tol
+        assert rel_fro(H.cpu().double().numpy().T, Href) <= 10 * tol
+        assert abs(loss.item() - st.loss_sum) <= tol * st.loss_sum
+        assert g.status() == 0
+        g.close()
+    finally:
+        bd.tune_clear()
+
+
+def test_multipass_out_of_range_index_is_flagged_not_read():
+    F, K, N, b = 65, 4, 40, 8
+    say("multipass bad index")
+    V, W0 = synth.problem(F, K, N, seed=123)
+    g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b, warm=True)
+    H = torch.ones((N, K), dtype=torch.float32, device=DEV)
+    p = np.arange(N, dtype=np.int32)
+    p[5] = N + 1000           # outside [0, N): a zero frame, no write
+    p[6] = -3
+    perm = torch.from_numpy(p[None, :]).to(DEV)
+    g.run_passes(torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV), perm, b, H)
+    torch.cuda.synchronize()
+    assert g.status() & 8
+    g.close()
+    cold = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b, warm=False)
+    with pytest.raises(bd.IsnmfError):   # the passes entry point needs warm restarts
+        cold.run_passes(torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV), perm, b, H)

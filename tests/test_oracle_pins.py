@@ -330,6 +330,39 @@ def test_online_equals_batch_when_beta_is_N_and_r_is_0():
         assert _relerr(Hw, Hb) < 1e-13
 
 
+def test_multipass_with_beta_N_equals_batch_cycles():
+    """Several warm-restart passes over a finite set (section 2.3) with beta = N,
+    r = 0 and one h update per visit are as many batch MU cycles, whatever the
+    order each pass visits the frames in: the multi-pass driver (resident H,
+    permuted visits) against the separately written batch cycle."""
+    V, W0, _ = _rand_problem(16, 4, 30, seed=17)
+    rng = np.random.default_rng(5)
+    perms = [rng.permutation(30) for _ in range(4)]
+    st, H = oracle.online_passes(V, W0, 30, perms, iters=1, rho=0.0)
+    Wb, Hb = W0, np.ones((4, 30))
+    for _ in range(4):
+        Wb, Hb, _, _ = oracle.batch_cycle(V, Wb, Hb)
+    assert _relerr(st.W, Wb) < 1e-12
+    assert _relerr(H, Hb) < 1e-12
+
+
+def test_multipass_visits_keep_each_frames_own_h():
+    """With minibatches smaller than N, a frame's warm start is its own h from
+    the previous pass: swapping two frames in the data and in every pass's
+    order swaps their columns of H and changes nothing else."""
+    V, W0, _ = _rand_problem(12, 3, 20, seed=18)
+    rng = np.random.default_rng(6)
+    perms = [rng.permutation(20) for _ in range(3)]
+    st, H = oracle.online_passes(V, W0, 5, perms, iters=3)
+    swap = np.arange(20)
+    swap[[2, 7]] = [7, 2]
+    V2 = V[:, swap]
+    perms2 = [swap[p] for p in perms]   # visit the same data in the same order
+    st2, H2 = oracle.online_passes(V2, W0, 5, perms2, iters=3)
+    assert _relerr(st2.W, st.W) < 1e-14
+    assert _relerr(H2[:, swap], H) < 1e-14
+
+
 # ---------------------------------------------------------------- generator statistics
 
 def test_objective_at_true_factors_is_euler_gamma():
