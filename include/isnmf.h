@@ -154,10 +154,13 @@ int isnmf_online_pass(isnmf_online *h, const float *V, int ldv, long long n_fram
  * The handle must use ISNMF_H_WARM.  V: device F x N FP32 (ldv >= F).
  * perm: device int, passes x N entries, each pass a permutation of 0..N-1;
  *   an index outside [0, N) reads zero frames, writes nothing and sets the
- *   status bit 8.  H: device K x N FP32 (ldh >= K), in/out.
+ *   status bit 8.  A pass that repeats a frame in adjacent minibatches leaves
+ *   unspecified which of its h values the later visit starts from.
+ *   H: device K x N FP32 (ldh >= K), in/out.
  * d_loss_sum as in isnmf_online_step (the total of every visit is added).
  * 1 <= b <= b_max, passes >= 1.  The frames and activations of a minibatch
- * are gathered into workspace buffers the handle reserves under H_WARM.
+ * are gathered into workspace buffers the handle reserves under H_WARM; the
+ * gather of one minibatch and the write-back of the one before share a launch.
  */
 int isnmf_online_passes(isnmf_online *h, const float *V, int ldv, long long N, const int *perm,
                         int passes, int b, float *H, int ldh, double *d_loss_sum, void *stream);

@@ -96,7 +96,7 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
     t.part = pb ? (float *)take(pb) : nullptr;
     const bool warm = p.h_init == ISNMF_H_WARM;   // gather buffers of isnmf_online_passes
     t.Vg = warm ? (float *)take((size_t)b_max * F * 4) : nullptr;
-    t.Hg = warm ? (float *)take((size_t)b_max * K * 4) : nullptr;
+    t.Hg = warm ? (float *)take((size_t)b_max * K * 8) : nullptr;
     if (d) *d = t;
     return off;
 }
@@ -294,20 +294,45 @@ int isnmf_online_passes(isnmf_online *h, const float *V, int ldv, long long N, c
         return ISNMF_EINVAL;
     const OnlineDev &d = h->d;
     hipStream_t s = (hipStream_t)stream;
+    // Minibatch m runs on Hg buffer m % 2; the launch that gathers minibatch m
+    // also writes minibatch m-1 back when both lie in one pass (a permutation
+    // keeps their frames disjoint).  Across a pass boundary they may share
+    // frames, so the write-back goes first, on its own.
+    RowSwap a = {};
+    a.V = V;
+    a.H = H;
+    a.ldv = ldv;
+    a.ldh = ldh;
+    a.N = N;
+    a.F = d.F;
+    a.K = d.K;
+    a.Vg = d.Vg;
+    a.flags = d.flags;
+    const size_t hsz = (size_t)d.b_max * d.K;
+    int buf = 0;
     for (int p = 0; p < passes; ++p) {
         for (long long s0 = 0; s0 < N; s0 += b) {
             const int bb = (int)(N - s0 < b ? N - s0 : b);
-            const int *idx = perm + (size_t)p * N + s0;
-            if (launch_gather_rows(d.Vg, d.F, V, ldv, N, idx, bb, d.F, d.flags, s) != hipSuccess ||
-                launch_gather_rows(d.Hg, d.K, H, ldh, N, idx, bb, d.K, d.flags, s) != hipSuccess)
-                return ISNMF_EDEVICE;
-            const int st = isnmf_online_step(h, d.Vg, d.F, bb, d.Hg, d.K, d_loss_sum, nullptr, stream);
+            if (s0 == 0 && a.n_out > 0) {
+                RowSwap w = a;
+                w.n_in = 0;
+                if (launch_row_swap(w, s) != hipSuccess) return ISNMF_EDEVICE;
+                a.n_out = 0;
+            }
+            a.in_idx = perm + (size_t)p * N + s0;
+            a.n_in = bb;
+            a.Hg_in = d.Hg + buf * hsz;
+            if (launch_row_swap(a, s) != hipSuccess) return ISNMF_EDEVICE;
+            const int st = isnmf_online_step(h, d.Vg, d.F, bb, a.Hg_in, d.K, d_loss_sum, nullptr, stream);
             if (st != ISNMF_OK) return st;
-            if (launch_scatter_rows(H, ldh, N, d.Hg, d.K, idx, bb, d.K, s) != hipSuccess)
-                return ISNMF_EDEVICE;
+            a.out_idx = a.in_idx;
+            a.n_out = bb;
+            a.Hg_out = a.Hg_in;
+            buf ^= 1;
         }
     }
-    return ISNMF_OK;
+    a.n_in = 0;
+    return launch_row_swap(a, s) == hipSuccess ? ISNMF_OK : ISNMF_EDEVICE;
 }
 
 int isnmf_online_fit(isnmf_online *h, const float *Vb, int ldv, int b, float *Hb, int ldh,

@@ -67,7 +67,8 @@ struct OnlineDev {
     void *Xt;            // plain path scratch: b_max x FR model values / loss terms
     double *lossel;      // plain path: b_max x FR per-element loss terms
     float *part;         // fold slice partials (b_max > 512) or null
-    float *Vg, *Hg;      // warm multi-pass: gathered minibatch frames (b_max x F) and h (b_max x K)
+    float *Vg, *Hg;      // warm multi-pass: gathered minibatch frames (b_max x F) and h
+                         // (two buffers of b_max x K, alternating between minibatches)
     int *flags;          // sticky flags
     unsigned *counter;   // spare device word (zeroed at init)
 };
@@ -182,13 +183,27 @@ hipError_t launch_rescale(const OnlineDev &d, int b, int update_w, int normalize
 // *d_loss_sum += sum of lossf[0..b) in index order (one block).
 hipError_t launch_loss_total(const double *lossf, int b, double *d_loss_sum, hipStream_t s);
 
-// Rows idx[0..n) of src (row stride lds, rows < N) to dst rows 0..n (stride
-// ldd), w floats each; out-of-range indices give zero rows and FLAG_BAD_INDEX.
-hipError_t launch_gather_rows(float *dst, int ldd, const float *src, long long lds, long long N,
-                              const int *idx, int n, int w, int *flags, hipStream_t s);
-// dst rows idx[i] (stride ldd, rows < N) <- src row i (stride lds); out-of-range skipped.
-hipError_t launch_scatter_rows(float *dst, long long ldd, long long N, const float *src, int lds,
-                               const int *idx, int n, int w, hipStream_t s);
+// One launch that moves minibatches between a resident set of N frames (V: F
+// floats per frame, stride ldv; H: K floats, stride ldh) and the packed
+// buffers of one step: frames in_idx[0..n_in) are gathered into Vg and Hg_in
+// (rows of F and K floats), and rows 0..n_out of Hg_out are written back to H
+// at out_idx.  An index outside [0, N) gathers zeros and sets FLAG_BAD_INDEX,
+// and is skipped on write-back.  The two index sets must be disjoint: a frame
+// both read and written in one launch sees either value.
+struct RowSwap {
+    const float *V;
+    float *H;
+    long long ldv, ldh, N;
+    int F, K;
+    const int *in_idx;
+    int n_in;
+    float *Vg, *Hg_in;
+    const int *out_idx;
+    int n_out;
+    const float *Hg_out;
+    int *flags;
+};
+hipError_t launch_row_swap(const RowSwap &a, hipStream_t s);
 
 // Copy helpers.
 hipError_t launch_set_w(const OnlineDev &d, const float *W, int ldw, const double *W64,

@@ -86,42 +86,30 @@ __global__ void loss_total_kernel(const double *__restrict__ lossf, int b,
     if (lane == 0) *out += s;
 }
 
-__global__ void gather_rows_kernel(float *__restrict__ dst, int ldd, const float *__restrict__ src,
-                                   long long lds, long long N, const int *__restrict__ idx, int w,
-                                   int *flags) {
-    const int i = blockIdx.y;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= w) return;
-    const long long r = idx[i];
-    float v = 0.f;
-    if (r >= 0 && r < N)
-        v = src[r * lds + j];
-    else if (j == 0)
-        atomicOr(flags, FLAG_BAD_INDEX);
-    dst[(size_t)i * ldd + j] = v;
-}
-
-__global__ void scatter_rows_kernel(float *__restrict__ dst, long long ldd, long long N,
-                                    const float *__restrict__ src, int lds,
-                                    const int *__restrict__ idx, int w) {
-    const int i = blockIdx.y;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= w) return;
-    const long long r = idx[i];
-    if (r >= 0 && r < N) dst[r * ldd + j] = src[(size_t)i * lds + j];
+__global__ void row_swap_kernel(const RowSwap a) {
+    const int t = threadIdx.x;
+    if ((int)blockIdx.x < a.n_in) {
+        const int i = blockIdx.x;
+        const long long r = a.in_idx[i];
+        const bool ok = r >= 0 && r < a.N;
+        if (!ok && t == 0) atomicOr(a.flags, FLAG_BAD_INDEX);
+        const float *v = a.V + (ok ? r : 0) * a.ldv;
+        const float *h = a.H + (ok ? r : 0) * a.ldh;
+        for (int j = t; j < a.F; j += 256) a.Vg[(size_t)i * a.F + j] = ok ? v[j] : 0.f;
+        for (int j = t; j < a.K; j += 256) a.Hg_in[(size_t)i * a.K + j] = ok ? h[j] : 0.f;
+    } else {
+        const int i = blockIdx.x - a.n_in;
+        const long long r = a.out_idx[i];
+        if (r < 0 || r >= a.N) return;
+        for (int j = t; j < a.K; j += 256) a.H[r * a.ldh + j] = a.Hg_out[(size_t)i * a.K + j];
+    }
 }
 
 }  // namespace
 
-hipError_t launch_gather_rows(float *dst, int ldd, const float *src, long long lds, long long N,
-                              const int *idx, int n, int w, int *flags, hipStream_t s) {
-    gather_rows_kernel<<<dim3((w + 255) / 256, n), 256, 0, s>>>(dst, ldd, src, lds, N, idx, w, flags);
-    return hipGetLastError();
-}
-
-hipError_t launch_scatter_rows(float *dst, long long ldd, long long N, const float *src, int lds,
-                               const int *idx, int n, int w, hipStream_t s) {
-    scatter_rows_kernel<<<dim3((w + 255) / 256, n), 256, 0, s>>>(dst, ldd, N, src, lds, idx, w);
+hipError_t launch_row_swap(const RowSwap &a, hipStream_t s) {
+    if (a.n_in + a.n_out < 1) return hipSuccess;
+    row_swap_kernel<<<a.n_in + a.n_out, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

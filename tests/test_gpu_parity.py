@@ -494,6 +494,109 @@ def test_multipass_warm_restarts_match_oracle(precision, kernel, variant, tol):
         bd.tune_clear()
 
 
+@pytest.mark.parametrize("precision,kernel,variant,tol", [
+    ("fp64", "plain", "", 1e-9), ("fp32", "plain", "", 1e-5), ("fp32", "fused", "mfma", 1e-5),
+    ("fp32", "fused", "valu", 1e-5)])
+def test_heldout_fit_and_objective_match_oracle(precision, kernel, variant, tol):
+    """The held-out criterion of section 3: after a few training steps, fit the
+    activations of unseen frames at the frozen W (the inner argmin only), then
+    evaluate eq. (1) on them.  The fit leaves W, A, B and t untouched."""
+    F, K, b, I, Nt = 129, 8, 16, 10, 77
+    say(f"held-out fit {precision}/{kernel}/{variant}")
+    V, W0 = synth.problem(F, K, 4 * b + Nt, seed=128)
+    Vtr, Vte = V[:, :4 * b], V[:, 4 * b:]
+    bd.tune_clear()
+    if variant == "valu":
+        bd.tune_set(F, K, "fp32", 8, 0, 0)
+    try:
+        g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b,
+                           inner_iters=I, precision=precision, kernel=kernel)
+        Vtr_t = torch.from_numpy(np.ascontiguousarray(Vtr.T)).to(DEV)
+        for s0 in range(0, 4 * b, b):
+            g.step(Vtr_t[s0:s0 + b])
+        W, A, B, t = g.get()
+        W64 = g.get_w64()
+        torch.cuda.synchronize()
+        Wf = from_gpu_kf(W)                 # the W the fit runs on, as the oracle's input
+        if precision == "fp64":
+            Wf = from_gpu_kf(W64)
+        Vte_t = torch.from_numpy(np.ascontiguousarray(Vte.T)).to(DEV)
+        H = torch.zeros((Nt, K), dtype=torch.float32, device=DEV)
+        loss = torch.zeros((), dtype=torch.float64, device=DEV)
+        for s0 in range(0, Nt, b):          # minibatches of at most b_max, a short last one
+            g.fit(Vte_t[s0:s0 + b], H[s0:s0 + b], loss)
+        W2, A2, B2, t2 = g.get()
+        torch.cuda.synchronize()
+        assert t2 == t and torch.equal(W2, W) and torch.equal(A2, A) and torch.equal(B2, B)
+        Vd = Vte.astype(np.float64)
+        Href = np.stack([oracle.fit_h(Vd[:, n], Wf, iters=I)[0] for n in range(Nt)], axis=1)
+        lref = sum(oracle.dis(Vd[:, n], Wf @ Href[:, n], 1e-12) for n in range(Nt))
+        Hg = H.cpu().double().numpy().T
+        assert rel_fro(Hg, Href) <= max(10 * tol, 1e-7)   # H leaves the device in FP32
+        assert abs(loss.item() - lref) <= 10 * tol * lref
+        obj = bd.objective(Vte_t, W, H).item()
+        assert abs(obj - oracle.objective(Vd, from_gpu_kf(W), Hg)) <= 1e-9 * obj
+        assert abs(obj - lref / Nt) <= 10 * tol * obj
+        assert g.status() == 0
+        g.close()
+    finally:
+        bd.tune_clear()
+
+
+@pytest.mark.parametrize("precision,kernel,tol", [("fp64", "plain", 1e-6), ("fp32", "fused", 1e-4)])
+def test_multipass_with_beta_N_is_batch_mu_on_device(precision, kernel, tol):
+    """With beta = N (one minibatch of all N frames), r = 0 and one h update per
+    visit, each warm-restart pass is one batch MU cycle (section 2.3): the device
+    multi-pass entry point against the device batch MU and the oracle's cycles."""
+    F, K, N, C = 129, 8, 300, 4
+    say(f"multipass beta=N {precision}/{kernel}")
+    V, W0 = synth.problem(F, K, N, seed=126)
+    Wr, Hr = W0.astype(np.float64), np.ones((K, N))
+    for _ in range(C):
+        Wr, Hr, _, _ = oracle.batch_cycle(V.astype(np.float64), Wr, Hr)
+    Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+    W0t = torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV)
+    g = bd.OnlineISNMF(W0t, N, warm=True, inner_iters=1, rho=0.0, precision=precision,
+                       kernel=kernel)
+    H = torch.ones((N, K), dtype=torch.float32, device=DEV)
+    rng = np.random.default_rng(127)
+    perm = torch.from_numpy(np.stack([rng.permutation(N) for _ in range(C)]).astype(np.int32))
+    g.run_passes(Vt, perm.to(DEV), N, H)
+    Wb = W0t.clone()
+    Hb = torch.ones((N, K), dtype=torch.float32, device=DEV)
+    bd.batch_mu(Vt, Wb, Hb, C, precision=precision, kernel=kernel, trace=False)
+    torch.cuda.synchronize()
+    Wo = from_gpu_kf(g.get_w64())
+    assert g.status() == 0
+    g.close()
+    assert rel_fro(Wo, Wr) <= tol and rel_fro(Wo, from_gpu_kf(Wb)) <= tol
+    Ho = H.cpu().double().numpy().T
+    assert rel_fro(Ho, Hr) <= 10 * tol and rel_fro(Ho, Hb.cpu().double().numpy().T) <= 10 * tol
+
+
+@pytest.mark.parametrize("b", [16, 40])
+def test_multipass_frames_shared_across_a_pass_boundary(b):
+    """Pass 2 runs pass 1 backwards, so the first minibatch of a pass revisits
+    the frames the previous pass ended with (all of them when b = N): their h
+    must come back from the previous visit before the next one starts."""
+    F, K, N, I = 65, 8, 40, 10
+    say(f"multipass boundary b={b}")
+    V, W0 = synth.problem(F, K, N, seed=124)
+    p0 = np.random.default_rng(125).permutation(N)
+    perms = [p0, p0[::-1].copy(), p0]
+    st, Href = oracle.online_passes(V.astype(np.float64), W0.astype(np.float64), b, perms, iters=I)
+    g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b, warm=True,
+                       inner_iters=I)
+    H = torch.ones((N, K), dtype=torch.float32, device=DEV)
+    perm = torch.from_numpy(np.stack(perms).astype(np.int32)).to(DEV)
+    g.run_passes(torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV), perm, b, H)
+    torch.cuda.synchronize()
+    assert rel_fro(from_gpu_kf(g.get_w64()), st.W) <= 1e-4
+    assert rel_fro(H.cpu().double().numpy().T, Href) <= 1e-3
+    assert g.status() == 0
+    g.close()
+
+
 def test_multipass_out_of_range_index_is_flagged_not_read():
     F, K, N, b = 65, 4, 40, 8
     say("multipass bad index")
