@@ -86,6 +86,7 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
     t.B = (double *)take(fk * 8);
     t.Wn = (double *)take(fk * 8);
     t.dwpart = (double *)take((size_t)K * 8);
+    t.sc = (double *)take((size_t)K * 8);
     t.lossf = (double *)take((size_t)b_max * 8);
     t.R1 = take((size_t)b_max * FR * es);
     t.R2 = take((size_t)b_max * FR * es);
@@ -246,6 +247,7 @@ int isnmf_online_init(isnmf_online **out, int F, int K, int b_max, const isnmf_p
     if (e == hipSuccess)
         e = B0 ? hipMemcpyAsync(h->d.B, B0, fk8, hipMemcpyDeviceToDevice, s)
                : hipMemsetAsync(h->d.B, 0, fk8, s);
+    if (e == hipSuccess) e = launch_unit_scale(h->d, s);
     if (e != hipSuccess) {
         delete h;
         return ISNMF_EDEVICE;
@@ -400,11 +402,9 @@ int isnmf_online_get(const isnmf_online *h, float *W, double *A, double *B, long
                      void *stream) {
     if (!h) return ISNMF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const size_t fk = (size_t)h->d.F * h->d.K;
     hipError_t e = hipSuccess;
     if (W && e == hipSuccess) e = launch_get_w(h->d, W, s);
-    if (A && e == hipSuccess) e = hipMemcpyAsync(A, h->d.A, fk * 8, hipMemcpyDeviceToDevice, s);
-    if (B && e == hipSuccess) e = hipMemcpyAsync(B, h->d.B, fk * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_get_ab(h->d, A, B, s);
     if (host_t) *host_t = h->t;
     return e == hipSuccess ? ISNMF_OK : ISNMF_EDEVICE;
 }
@@ -425,6 +425,7 @@ int isnmf_online_set(isnmf_online *h, const float *W, const double *A, const dou
     const size_t fk = (size_t)h->d.F * h->d.K;
     hipError_t e = hipSuccess;
     if (W) e = launch_set_w(h->d, W, h->d.F, nullptr, s);
+    if ((A || B) && e == hipSuccess) e = launch_settle_ab(h->d, s);   // the one not given keeps its value
     if (A && e == hipSuccess) e = hipMemcpyAsync(h->d.A, A, fk * 8, hipMemcpyDeviceToDevice, s);
     if (B && e == hipSuccess) e = hipMemcpyAsync(h->d.B, B, fk * 8, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return ISNMF_EDEVICE;

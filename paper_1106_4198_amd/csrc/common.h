@@ -58,7 +58,9 @@ struct OnlineDev {
     int wexp;            // s = round(log2 F): 16-bit copies hold W * 2^s
     float *Wv;           // W in the register order of the VALU fit (see wv_index) or null
     int wv_ck;           // ceil(K / 8): components per thread of that order
-    double *A, *B;       // F x K, ld F
+    double *A, *B;       // F x K, ld F, stored before the last column rescale:
+                         // the statistics are A[:,k] / sc[k] and B[:,k] * sc[k]
+    double *sc;          // K: column scale of A and B not yet applied (1 = none)
     double *Wn;          // F x K: sqrt(A/B) before rescaling
     double *dwpart;      // K: per-column sum of squared change of W
     double *lossf;       // b_max: per-frame loss of the current minibatch
@@ -177,6 +179,11 @@ size_t fold_partial_bytes(int F, int K, int b);
 
 // Column rescale (when update_w), W copies, warm-H compensation; d_dw (if
 // not null) receives ||W_new - W_old||_F.
+// A, B with the pending column scale applied, into A and B (device F x K, or
+// null); settle applies it in place and clears it; unit_scale clears it.
+hipError_t launch_get_ab(const OnlineDev &d, double *A, double *B, hipStream_t s);
+hipError_t launch_settle_ab(const OnlineDev &d, hipStream_t s);
+hipError_t launch_unit_scale(const OnlineDev &d, hipStream_t s);
 hipError_t launch_rescale(const OnlineDev &d, int b, int update_w, int normalize, int warm,
                           float *Hb, int ldh, double *d_dw, hipStream_t s);
 

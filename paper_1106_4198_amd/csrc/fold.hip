@@ -34,7 +34,8 @@ __global__ void fold_reduce_kernel(FoldArgs a, int slices) {
         sa += double(a.part[(size_t)s * 2 * fk + e]);
         sb += double(a.part[(size_t)s * 2 * fk + fk + e]);
     }
-    epilogue(a, (int)(e % a.F), (int)(e / a.F), sa, sb, a.W64[e], a.A[e], a.B[e]);
+    const int k = (int)(e / a.F);
+    epilogue(a, (int)(e % a.F), k, sa, sb, a.W64[e], a.A[e] / a.sc[k], a.B[e] * a.sc[k]);
 }
 
 }  // namespace

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256, 4) void fold_multi_kernel(const FoldArgs *__re
     if (b == 0) return;
     FoldArgs a = fa[it.x];
     a.b = b;
-    fold_rows_body<KTM>(a, it.y, 0, 1);
+    fold_rows_body<KTM>(a, it.y);
 }
 
 __global__ __launch_bounds__(64) void rescale_multi_kernel(const RescaleArgs *__restrict__ ra,
@@ -74,7 +74,11 @@ __global__ __launch_bounds__(64) void rescale_multi_kernel(const RescaleArgs *__
                                                             const int *__restrict__ beff) {
     const int2 it = items[blockIdx.x];
     const int b = beff[it.x];
-    if (b == 0 || !upd[it.x]) return;
+    if (b == 0) return;   // no step: A, B and their pending scale are untouched
+    if (!upd[it.x]) {     // the fold stored A and B with no pending scale
+        if (threadIdx.x == 0) ra[it.x].sc[it.y] = 1.0;
+        return;
+    }
     rescale_body(ra[it.x], it.y, b);
 }
 
@@ -153,6 +157,43 @@ Layout layout(int S, size_t nitems) {
     L.items = take(sizeof(int2) * (nitems ? nitems : 1));
     L.total = off;
     return L;
+}
+
+// Workgroup i of a launch is dispatched to XCD i mod 8.  Ordering a launch's
+// items so that all items of a stream share an XCD lets that XCD's L2 merge
+// the partial cache lines that neighbouring tiles of the stream write (the
+// fold's 16-row column segments, the rescale's row-major 16-bit W) and serve
+// the lines they both read, instead of each XCD fetching and writing back its
+// own partial copy.  xcd[s] is the XCD of stream s; the queues are
+// interleaved, and once the shorter ones run out the rest keeps its order.
+constexpr int XCDS = 8;
+
+std::vector<int> xcd_assign(const std::vector<size_t> &load_per_stream) {
+    const int S = (int)load_per_stream.size();
+    std::vector<int> order(S), xcd(S, 0);
+    for (int s = 0; s < S; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return load_per_stream[a] > load_per_stream[b]; });
+    size_t load[XCDS] = {};
+    for (int s : order) {
+        int x = 0;
+        for (int y = 1; y < XCDS; ++y)
+            if (load[y] < load[x]) x = y;
+        xcd[s] = x;
+        load[x] += load_per_stream[s];
+    }
+    return xcd;
+}
+
+void push_xcd_ordered(std::vector<int2> &out, const std::vector<int2> &items,
+                      const std::vector<int> &xcd) {
+    std::vector<int2> q[XCDS];
+    for (const int2 &it : items) q[xcd[it.x]].push_back(it);
+    size_t longest = 0;
+    for (int x = 0; x < XCDS; ++x) longest = std::max(longest, q[x].size());
+    for (size_t j = 0; j < longest; ++j)
+        for (int x = 0; x < XCDS; ++x)
+            if (j < q[x].size()) out.push_back(q[x][j]);
 }
 
 size_t count_items(isnmf_online *const *h, const int *b, int S) {
@@ -276,6 +317,7 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         fit[s] = make_fit_desc(d, V[s], ldv[s], b[s], p.inner_iters, p.eps, 0, nullptr, d.K);
         fold[s] = fold_args(d, b[s], p.rho, p.update_w, nullptr, d_loss ? d_loss + s : nullptr);
         rs[s] = rescale_args(d, p.normalize, 0, nullptr, d.K);
+        rs[s].dwpart = nullptr;   // the batched step reports no dW
         upd[s] = p.update_w;
         const auto key = std::make_tuple(c.nw, c.cpw, c.kmax, c.wg, c.rf, prec_of(p));
         size_t gi = 0;
@@ -293,18 +335,29 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         items.insert(items.end(), g.second.begin(), g.second.end());
         m->groups.push_back(G);
     }
+    // streams to XCDs by their fold tiles x components (the state they move)
+    std::vector<size_t> state(S);
+    for (int s = 0; s < S; ++s) {
+        const OnlineDev &d = *isnmf_handle_dev(handles[s]);
+        state[s] = (size_t)d.F * d.K;
+    }
+    const std::vector<int> xcd = xcd_assign(state);
+    std::vector<int2> list;
     m->fold_off = (int)items.size();
     for (int s = 0; s < S; ++s) {
         const int nt = fold_tiles(*isnmf_handle_dev(handles[s]));
         m->fold_ktm = std::max(m->fold_ktm, fold_ktm(isnmf_handle_dev(handles[s])->K));
-        for (int t = 0; t < nt; ++t) items.push_back(int2{s, t});
+        for (int t = 0; t < nt; ++t) list.push_back(int2{s, t});
     }
+    push_xcd_ordered(items, list, xcd);
     m->fold_n = (int)items.size() - m->fold_off;
     m->rs_off = (int)items.size();
+    list.clear();
     for (int s = 0; s < S; ++s) {
         const int K = isnmf_handle_dev(handles[s])->K;
-        for (int k = 0; k < K; ++k) items.push_back(int2{s, k});
+        for (int k = 0; k < K; ++k) list.push_back(int2{s, k});
     }
+    push_xcd_ordered(items, list, xcd);
     m->rs_n = (int)items.size() - m->rs_off;
 
     hipStream_t st = (hipStream_t)stream;

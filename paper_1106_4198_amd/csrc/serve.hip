@@ -63,14 +63,17 @@ __global__ __launch_bounds__(256, 4) void serve_fold_kernel(const FoldArgs *__re
     const Work wk = work[blockIdx.x];
     FoldArgs a = tab[wk.sess];
     a.b = wk.b;
-    fold_rows_body<KTM>(a, blockIdx.y, 0, 1);
+    fold_rows_body<KTM>(a, blockIdx.y);
 }
 
 __global__ __launch_bounds__(64) void serve_rescale_kernel(const RescaleArgs *__restrict__ tab,
                                                             const int *__restrict__ upd,
                                                             const Work *__restrict__ work) {
     const Work wk = work[blockIdx.x];
-    if (!upd[wk.sess]) return;
+    if (!upd[wk.sess]) {   // the fold stored A and B with no pending scale
+        if (threadIdx.x == 0) tab[wk.sess].sc[blockIdx.y] = 1.0;
+        return;
+    }
     rescale_body(tab[wk.sess], blockIdx.y, wk.b);
 }
 
@@ -355,6 +358,7 @@ int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *s
     FitDesc fd = make_fit_desc(d, nullptr, d.F, 1, p.inner_iters, p.eps, 0, nullptr, d.K);
     FoldArgs fa = fold_args(d, 1, p.rho, p.update_w, nullptr, nullptr);
     RescaleArgs ra = rescale_args(d, p.normalize, 0, nullptr, d.K);
+    ra.dwpart = nullptr;   // served steps report no dW
     const int upd = p.update_w;
     hipStream_t st = s->stream;
     if (hipMemcpyAsync(s->d_fit + idx, &fd, sizeof fd, hipMemcpyHostToDevice, st) != hipSuccess ||

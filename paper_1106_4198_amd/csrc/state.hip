@@ -5,7 +5,10 @@
 //            Wn = sqrt(A / B)
 //   rescale: s_k = sum_f Wn_fk;  W = Wn / s,  A /= s,  B *= s,  warm H[k,:] *= s;
 //            dW = ||W_new - W_old||_F;  loss_sum += sum_n loss_n
-// A, B and the master W are FP64.  Every sum runs in a fixed order, so the
+// A, B and the master W are FP64.  A /= s and B *= s are deferred: the
+// rescale records s in sc, and whoever reads A and B next (the next fold,
+// isnmf_online_get) divides and multiplies by it, so they are read and written
+// once per step instead of twice.  Every sum runs in a fixed order, so the
 // results are bitwise repeatable.
 #include "common.h"
 #include "state_body.h"
@@ -18,8 +21,9 @@ template <typename TR>
 __global__ void fold_kernel(int F, int K, int b, int FR, int KP, const TR *__restrict__ R1,
                             const TR *__restrict__ R2, const TR *__restrict__ H,
                             const double *__restrict__ W64, double *__restrict__ A,
-                            double *__restrict__ B, double *__restrict__ Wn, double rho,
-                            int update_w, int *__restrict__ flags) {
+                            double *__restrict__ B, const double *__restrict__ sc,
+                            double *__restrict__ Wn, double rho, int update_w,
+                            int *__restrict__ flags) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)F * K) return;
     const int f = (int)(e % F);
@@ -31,8 +35,8 @@ __global__ void fold_kernel(int F, int K, int b, int FR, int KP, const TR *__res
         sb += double(R1[(size_t)n * FR + f]) * h;
     }
     const double w = W64[e];
-    const double a = rho * A[e] + sa * (w * w);
-    const double bb = rho * B[e] + sb;
+    const double a = rho * (A[e] / sc[k]) + sa * (w * w);
+    const double bb = rho * (B[e] * sc[k]) + sb;
     A[e] = a;
     B[e] = bb;
     if (update_w) {
@@ -47,6 +51,22 @@ __global__ void fold_kernel(int F, int K, int b, int FR, int KP, const TR *__res
 
 __global__ __launch_bounds__(64) void rescale_kernel(RescaleArgs a, int b) {
     rescale_body(a, blockIdx.x, b);
+}
+
+__global__ void unit_scale_kernel(double *__restrict__ sc, int K) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < K) sc[k] = 1.0;
+}
+
+// The statistics with the pending scale applied: A[:,k] / sc[k], B[:,k] * sc[k]
+// into Ao, Bo (either may be null); in place when they are A and B themselves.
+__global__ void apply_scale_kernel(int F, int K, const double *A, const double *B,
+                                   const double *__restrict__ sc, double *Ao, double *Bo) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)F * K) return;
+    const int k = (int)(e / F);
+    if (Ao) Ao[e] = A[e] / sc[k];
+    if (Bo) Bo[e] = B[e] * sc[k];
 }
 
 // ||W_new - W_old||_F from the per-column partials, in column order.
@@ -125,20 +145,46 @@ hipError_t launch_fold(const OnlineDev &d, int b, double rho, int update_w, int 
     if (is_double)
         fold_kernel<double><<<blocks, 256, 0, s>>>(d.F, d.K, b, d.FR, d.KP, (const double *)d.R1,
                                                    (const double *)d.R2, (const double *)d.Hi,
-                                                   d.W64, d.A, d.B, d.Wn, rho, update_w, d.flags);
+                                                   d.W64, d.A, d.B, d.sc, d.Wn, rho, update_w,
+                                                   d.flags);
     else
         fold_kernel<float><<<blocks, 256, 0, s>>>(d.F, d.K, b, d.FR, d.KP, (const float *)d.R1,
                                                   (const float *)d.R2, (const float *)d.Hi,
-                                                  d.W64, d.A, d.B, d.Wn, rho, update_w, d.flags);
+                                                  d.W64, d.A, d.B, d.sc, d.Wn, rho, update_w,
+                                                  d.flags);
     return hipGetLastError();
 }
 
 hipError_t launch_rescale(const OnlineDev &d, int b, int update_w, int normalize, int warm,
                           float *Hb, int ldh, double *d_dw, hipStream_t s) {
-    if (update_w)
-        rescale_kernel<<<d.K, 64, 0, s>>>(rescale_args(d, normalize, warm, Hb, ldh), b);
+    if (update_w) {
+        RescaleArgs a = rescale_args(d, normalize, warm, Hb, ldh);
+        if (!d_dw) a.dwpart = nullptr;
+        rescale_kernel<<<d.K, 64, 0, s>>>(a, b);
+    } else {
+        // the fold stored A and B with no pending scale
+        unit_scale_kernel<<<(d.K + 63) / 64, 64, 0, s>>>(d.sc, d.K);
+    }
     if (d_dw) dw_total_kernel<<<1, 64, 0, s>>>(d.K, d.dwpart, update_w, d_dw);
     return hipGetLastError();
+}
+
+hipError_t launch_unit_scale(const OnlineDev &d, hipStream_t s) {
+    unit_scale_kernel<<<(d.K + 63) / 64, 64, 0, s>>>(d.sc, d.K);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_ab(const OnlineDev &d, double *A, double *B, hipStream_t s) {
+    const long n = (long)d.F * d.K;
+    if (!A && !B) return hipSuccess;
+    apply_scale_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(d.F, d.K, d.A, d.B, d.sc, A, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_settle_ab(const OnlineDev &d, hipStream_t s) {
+    hipError_t e = launch_get_ab(d, d.A, d.B, s);
+    if (e == hipSuccess) e = launch_unit_scale(d, s);
+    return e;
 }
 
 hipError_t launch_set_w(const OnlineDev &d, const float *W, int ldw, const double *W64,

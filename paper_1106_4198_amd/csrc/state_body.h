@@ -48,31 +48,33 @@ struct RescaleArgs {
     float *W32;
     W16Out w16;
     WvOut wv;
-    double *A, *B;
+    double *sc;     // K: pending column scale of A and B, set to s_k (1 without normalize)
     int normalize, warm;
     float *Hb;      // warm-start activations to compensate (or null)
     int ldh;
-    double *dwpart;
+    double *dwpart; // per-column squared change of W, or null (not computed)
     int *flags;
 };
 
-// One wave per column k: s_k = sum_f Wn_fk, W = Wn / s, A /= s, B *= s,
-// warm H[k,:] *= s, and the column's squared change of W.  Lane l takes rows
-// l, l + 64, ... in order; the lane values are combined by wave_sum_f64.
+// One wave per column k: s_k = sum_f Wn_fk, W = Wn / s, warm H[k,:] *= s,
+// and the column's squared change of W when dwpart is set.  A /= s and B *= s
+// are not applied here: sc[k] = s records them for the next reader of A and B
+// (the fold applies them as it loads, with the same FP64 operations).  Lane l
+// takes rows l, l + 64, ... in order; the lane values are combined by
+// wave_sum_f64.
 __device__ __forceinline__ void rescale_body(const RescaleArgs &a, int k, int b) {
     const int lane = threadIdx.x & 63;
     const int F = a.F;
     const size_t col = (size_t)k * F;
+    const bool dw_on = a.dwpart != nullptr;
     constexpr int RW = 9;   // rows per lane held in registers (F <= 576); the rest loop
-    double wn[RW], wo[RW], av[RW], bv[RW];
+    double wn[RW], wo[RW];
 #pragma unroll
     for (int r = 0; r < RW; ++r) {   // every load of the column in one round trip
         const int f = lane + 64 * r;
         const bool ok = f < F;
         wn[r] = ok ? a.Wn[col + f] : 0.0;
-        wo[r] = ok ? a.W64[col + f] : 0.0;
-        av[r] = ok ? a.A[col + f] : 0.0;
-        bv[r] = ok ? a.B[col + f] : 0.0;
+        wo[r] = ok && dw_on ? a.W64[col + f] : 0.0;
     }
     double s = 0.0;
 #pragma unroll
@@ -87,7 +89,7 @@ __device__ __forceinline__ void rescale_body(const RescaleArgs &a, int k, int b)
             atomicOr(a.flags, FLAG_GUARD_W);
     }
     double dw = 0.0;
-    auto update = [&](int f, double wnv, double wo, double av, double bv) {
+    auto update = [&](int f, double wnv, double wo) {
         const double w = wnv / scale;
         const double dlt = w - wo;
         dw += dlt * dlt;
@@ -95,22 +97,21 @@ __device__ __forceinline__ void rescale_body(const RescaleArgs &a, int k, int b)
         a.W32[col + f] = float(w);
         store_w16(a.w16, f, k, w);
         store_wv(a.wv, f, k, w);
-        if (a.normalize) {
-            a.A[col + f] = av / scale;
-            a.B[col + f] = bv * scale;
-        }
     };
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
         const int f = lane + 64 * r;
-        if (f < F) update(f, wn[r], wo[r], av[r], bv[r]);
+        if (f < F) update(f, wn[r], wo[r]);
     }
     for (int f = lane + 64 * RW; f < F; f += 64)
-        update(f, a.Wn[col + f], a.W64[col + f], a.A[col + f], a.B[col + f]);
+        update(f, a.Wn[col + f], dw_on ? a.W64[col + f] : 0.0);
+    if (lane == 0) a.sc[k] = scale;
     if (a.warm && a.Hb && a.normalize)
         for (int n = lane; n < b; n += 64) a.Hb[(size_t)n * a.ldh + k] *= float(scale);
-    dw = wave_sum_f64(dw);
-    if (lane == 0) a.dwpart[k] = dw;
+    if (dw_on) {
+        dw = wave_sum_f64(dw);
+        if (lane == 0) a.dwpart[k] = dw;
+    }
 }
 
 inline W16Out w16_out(const OnlineDev &d) {
@@ -135,8 +136,7 @@ inline RescaleArgs rescale_args(const OnlineDev &d, int normalize, int warm, flo
     a.W32 = d.W32;
     a.w16 = w16_out(d);
     a.wv = wv_out(d);
-    a.A = d.A;
-    a.B = d.B;
+    a.sc = d.sc;
     a.normalize = normalize;
     a.warm = warm;
     a.Hb = Hb;
