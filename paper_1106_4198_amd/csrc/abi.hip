@@ -77,6 +77,7 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
     t.W16r = (uint16_t *)take((size_t)F * KP * 2);
     t.W16c = (uint16_t *)take((size_t)K * FR * 2);
     t.w16_kind = prec_code(p);
+    t.w16_rows = 1;
     t.wexp = (int)lrint(log2((double)F));
     // register-order copy for the VALU fit variant (FP32 shapes it covers)
     const bool wv = p.precision == ISNMF_FP32 && valu_class(F, K).ok;
@@ -235,6 +236,7 @@ int isnmf_online_init(isnmf_online **out, int F, int K, int b_max, const isnmf_p
     h->last = (hipStream_t)stream;
     h->kernel_used = use_fused(p, F, K) ? ISNMF_KERNEL_FUSED : ISNMF_KERNEL_PLAIN;
     h->cls = tuned_class(F, K, prec_code(p), b_max);
+    h->d.w16_rows = h->cls.cpw != -1;   // the 16-frame tile variant reads only W16c
     hipStream_t s = (hipStream_t)stream;
     const size_t fk8 = sizeof(double) * (size_t)F * K;
     hipError_t e = hipSuccess;
@@ -505,6 +507,12 @@ int isnmf_batch_mu(const float *V, int ldv, int F, int N, float *W, int ldw, flo
     if (hipMemsetAsync(h.d.flags, 0, sizeof(int), s) != hipSuccess) return ISNMF_EDEVICE;
     if (hipMemsetAsync(h.d.counter, 0, sizeof(unsigned), s) != hipSuccess) return ISNMF_EDEVICE;
     if (init_w(h.d, W, ldw, s) != hipSuccess) return ISNMF_EDEVICE;
+    // A(0) = B(0) = 0: rho = 0 multiplies them, and 0 times a non-finite
+    // leftover of the workspace would not be 0
+    const size_t fk8 = sizeof(double) * (size_t)F * K;
+    if (hipMemsetAsync(h.d.A, 0, fk8, s) != hipSuccess ||
+        hipMemsetAsync(h.d.B, 0, fk8, s) != hipSuccess || launch_unit_scale(h.d, s) != hipSuccess)
+        return ISNMF_EDEVICE;
     for (int c = 0; c < cycles; ++c) {
         int st = run_fit(&h, V, ldv, N, 1, 1, H, ldh, s);
         if (st != ISNMF_OK) return st;

@@ -55,6 +55,7 @@ struct OnlineDev {
     uint16_t *W16r;      // F x KP row-major: W * 2^wexp in BF16/FP16 (precision forms)
     uint16_t *W16c;      // K x FR (column k at k*FR): the same values, column-major
     int w16_kind;        // 0 none, 1 BF16, 2 FP16
+    int w16_rows;        // 1: W16r is kept current (0 when the fit variant reads only W16c)
     int wexp;            // s = round(log2 F): 16-bit copies hold W * 2^s
     float *Wv;           // W in the register order of the VALU fit (see wv_index) or null
     int wv_ck;           // ceil(K / 8): components per thread of that order

@@ -48,6 +48,16 @@ __device__ inline uint2 ld4(const uint16_t *p, bool ok) {
     return ok ? *reinterpret_cast<const uint2 *>(p) : uint2{0u, 0u};
 }
 
+// Components k0 .. k0 + 3 of row `row` from the column-major copy (K x FR),
+// zero past K: what the row-major copy holds there, whose padding is zero.
+__device__ inline uint2 ld4_cols(const uint16_t *W16c, int FR, int K, int row, int k0, bool rok) {
+    uint32_t h[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        h[j] = (rok && k0 + j < K) ? (uint32_t)W16c[(size_t)(k0 + j) * FR + row] : 0u;
+    return uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+}
+
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float float2v __attribute__((ext_vector_type(2)));
 
@@ -80,13 +90,13 @@ __device__ inline void body(const FitDesc &a, int n_first) {
     const bool fok = fr < a.b;
     const float eps = a.eps;
 
-    // ---- W operands into LDS (bf16 bits of W * 2^s; zero past F and K)
+    // ---- W operands into LDS (bf16 bits of W * 2^s; zero past F and K), both
+    // from the column-major copy: this variant needs no row-major copy
     for (int e = threadIdx.x; e < T * KS * 64; e += NWT * 64) {
         const int l = e & 63, c = (e >> 6) % KS, t = (e >> 6) / KS;
         const int row = 16 * t + (l & 15), k0 = 32 * c + 4 * (l >> 4);
-        const uint16_t *pr = a.W16r + (size_t)row * a.KP;
-        const uint2 lo = ld4(pr + k0, row < F && k0 < a.KP);
-        const uint2 hi = ld4(pr + k0 + 16, row < F && k0 + 16 < a.KP);
+        const uint2 lo = ld4_cols(a.W16c, a.FR, K, row, k0, row < F);
+        const uint2 hi = ld4_cols(a.W16c, a.FR, K, row, k0 + 16, row < F);
         wxl[e] = uint4{lo.x, lo.y, hi.x, hi.y};
     }
     for (int e = threadIdx.x; e < S * MT * 64; e += NWT * 64) {

@@ -26,6 +26,22 @@ __device__ inline floatx4 mfma16(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Wave partials of a 16 x 16 tile in LDS for the epilogue.  The MFMA result
+// of lane l, register r is element (row 4 (l / 16) + r, column l % 16); a
+// slab stores the 64 lanes' floatx4 with one floatx4 gap after every 16
+// lanes (RSLAB floats).  The epilogue reads element (row fl, column cl) with
+// lane fl + 16 q taking column cl = 4 q + j in its j-th pass, so a pass
+// covers 16 consecutive rows of 4 columns (four 128-byte runs of an F-major
+// FP64 array) and its LDS reads fall in 64 distinct banks.
+constexpr int RSLAB = 68 * 4;
+
+__device__ inline int red_pos(int l) { return l + (l >> 4); }   // floatx4 index in a slab
+
+__device__ inline float red_elem(const float *slab, int fl, int cl) {
+    const int sl = 16 * (fl >> 2) + cl;
+    return slab[4 * red_pos(sl) + (fl & 3)];
+}
+
 // A = rho A + sum_n r2 h W^2, B = rho B + sum_n r1 h (Algorithm 1), W = sqrt(A/B);
 // w, a0, b0: the element's current W, A, B (a0, b0 with the pending column
 // scale applied).  A and B are stored as computed here, with no pending scale.
@@ -49,25 +65,30 @@ __device__ inline void epilogue(const FoldArgs &a, int f, int k, double sa, doub
 // Batched and served fold: one 16-row tile of f and every component k per
 // 256-thread block (4 waves), KTM >= ceil(K / 16) tiles of 16 components, so
 // each block reads its r1, r2 rows once for all components.  The frames are the
-// contraction dimension of v_mfma_f32_16x16x4f32: wave w takes the groups of
-// 4 frames with (n / 4) mod 4 == w, in increasing n, and reads each group's
-// r1, r2 operand once for all component tiles; the four per-wave partials of
-// an element are summed in wave order.  Wave w then applies the FP64
-// epilogue to the component tiles kt = w (mod 4).
+// contraction dimension of v_mfma_f32_16x16x4f32.  Wave w owns the component
+// tiles kt = w (mod 4) and keeps four accumulators per tile, one per class of
+// groups of 4 frames with (n / 4) mod 4 == v, each fed in increasing n and
+// summed in class order at the end: the same chains and the same sums as the
+// single-stream fold's four waves, with no reduction across waves.
 // The operands of CH frames at a time are first staged in LDS by the whole
-// block with 16-byte loads, all issued before the first is waited for, so a
-// block keeps its whole chunk in flight; frames past the minibatch and
-// components past K are staged as zeros.  H rows sit HS floats apart in LDS,
-// so that the four frames of one MFMA operand fall in disjoint bank ranges.
+// block with 16-byte loads, all issued before the first is waited for;
+// frames past the minibatch and components past K are staged as zeros.  The
+// four frames of one MFMA operand fall in disjoint LDS bank ranges: with four
+// or more component tiles, component c of local frame n is stored at column
+// c ^ 16 (n mod 4) of its row; with fewer, rows are padded to HS floats.
+// The epilogue operands are loaded after the frames, which keeps the
+// registers, and so the resident blocks per CU, within the LDS bound.
 // One slice of at most SLICE frames (the batched forms' limit).
 template <int KTM>
 struct RowsFold {
     static constexpr int CH = KTM <= 2 ? 128 : 64;             // frames per staged chunk
-    static constexpr int HS = KTM == 1 ? 16 : 16 * KTM + 16;   // LDS floats per H row
+    static constexpr bool SWZ = KTM >= 4;                       // XOR-swizzled H rows
+    static constexpr int HS = SWZ ? 16 * KTM : KTM == 1 ? 16 : 48;   // LDS floats per H row
+    __device__ static int hcol(int n, int c) { return SWZ ? c ^ (16 * (n & 3)) : c; }
     static constexpr int HQ = 4 * KTM;                          // float4 of H data per row
     static constexpr int STAGE = CH * (32 + HS);                // floats: r2, r1, H
-    static constexpr int RED = 4 * KTM * 2 * 64 * 4;            // floats: wave partials
-    static constexpr int LDS = STAGE > RED ? STAGE : RED;
+    static constexpr int TRANS = 4 * 2 * RSLAB;                 // floats: per-wave epilogue slabs
+    static constexpr int LDS = STAGE > TRANS ? STAGE : TRANS;
     static constexpr int RQ = CH * 4 / 256;                     // float4 of r2 (and r1) per thread
     static constexpr int HL = CH * HQ / 256;                    // float4 of H per thread
     static_assert(RQ * 256 == CH * 4 && HL * 256 == CH * HQ, "chunk must tile the block");
@@ -76,7 +97,7 @@ struct RowsFold {
 template <int KTM>
 __device__ __forceinline__ void fold_rows_body(const FoldArgs &a, int ft) {
     using C = RowsFold<KTM>;
-    constexpr int KE = (KTM + 3) / 4;           // epilogue tiles per wave
+    constexpr int KE = (KTM + 3) / 4;           // component tiles per wave
     __shared__ float4 lds4[C::LDS / 4];
     float *lds = reinterpret_cast<float *>(lds4);
     float *sR2 = lds, *sR1 = lds + C::CH * 16, *sH = lds + C::CH * 32;
@@ -88,22 +109,6 @@ __device__ __forceinline__ void fold_rows_body(const FoldArgs &a, int ft) {
     const int n_hi = min(a.b, SLICE);
     const int sub = lane >> 4;             // frame within the group of 4
 
-    // epilogue operands of this wave's component tiles, loaded before the frames
-    double wq[KE][4], aq[KE][4], bq[KE][4];
-#pragma unroll
-    for (int u = 0; u < KE; ++u) {
-        const int kc = 16 * (w + 4 * u) + (lane & 15);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int f = f0 + 4 * sub + r;
-            const bool ok = w + 4 * u < KT && f < a.F && kc < a.K;
-            const size_t e = ok ? (size_t)f + (size_t)kc * a.F : 0;
-            wq[u][r] = ok ? a.W64[e] : 0.0;
-            aq[u][r] = ok ? a.A[e] / a.sc[kc] : 0.0;
-            bq[u][r] = ok ? a.B[e] * a.sc[kc] : 0.0;
-        }
-    }
-
     // minibatch loss: wave 1 of tile 0, lane l sums frames l, l + 64, ... in
     // order, then a fixed xor butterfly over the lanes
     if (a.d_loss_sum && ft == 0 && w == 1) {
@@ -114,12 +119,14 @@ __device__ __forceinline__ void fold_rows_body(const FoldArgs &a, int ft) {
         if (lane == 0) *a.d_loss_sum += s;
     }
 
-    floatx4 ca[KTM], cb[KTM];
+    floatx4 ca[KE][4], cb[KE][4];
 #pragma unroll
-    for (int kt = 0; kt < KTM; ++kt) {
-        ca[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
-        cb[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int u = 0; u < KE; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            ca[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
+            cb[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
     const float4 z4 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int c0 = 0; c0 < n_hi; c0 += C::CH) {
@@ -156,48 +163,68 @@ __device__ __forceinline__ void fold_rows_body(const FoldArgs &a, int ft) {
 #pragma unroll
         for (int i = 0; i < C::HL; ++i) {
             const int e = t + 256 * i;
-            *reinterpret_cast<float4 *>(sH + (e / C::HQ) * C::HS + 4 * (e % C::HQ)) = vh[i];
+            const int nr = e / C::HQ;
+            *reinterpret_cast<float4 *>(sH + nr * C::HS + C::hcol(nr, 4 * (e % C::HQ))) = vh[i];
         }
         __syncthreads();
         const int nmax = min(C::CH, n_hi - c0);
-#pragma unroll 4
-        for (int g0 = 4 * w; g0 < nmax; g0 += 16) {
-            const int nl = g0 + sub;
-            const float r2 = sR2[nl * 16 + (lane & 15)];
-            const float r1 = sR1[nl * 16 + (lane & 15)];
+#pragma unroll 2
+        for (int g0 = 0; g0 < nmax; g0 += 16) {
 #pragma unroll
-            for (int kt = 0; kt < KTM; ++kt) {
-                if (kt < KT) {
-                    const float hh = sH[nl * C::HS + 16 * kt + (lane & 15)];
-                    ca[kt] = mfma16(r2, hh, ca[kt]);
-                    cb[kt] = mfma16(r1, hh, cb[kt]);
+            for (int v = 0; v < 4; ++v) {
+                if (g0 + 4 * v >= nmax) break;
+                const int nl = g0 + 4 * v + sub;
+                const float r2 = sR2[nl * 16 + (lane & 15)];
+                const float r1 = sR1[nl * 16 + (lane & 15)];
+#pragma unroll
+                for (int u = 0; u < KE; ++u) {
+                    const int kt = w + 4 * u;
+                    if (kt < KT) {
+                        const float hh = sH[nl * C::HS + C::hcol(nl, 16 * kt + (lane & 15))];
+                        ca[u][v] = mfma16(r2, hh, ca[u][v]);
+                        cb[u][v] = mfma16(r1, hh, cb[u][v]);
+                    }
                 }
             }
         }
         __syncthreads();
     }
-    floatx4 *red = reinterpret_cast<floatx4 *>(lds);   // [4][KTM][2][64], after the last chunk
+    // epilogue operands of this wave's component tiles: element
+    // (f0 + lane % 16, 16 kt + 4 (lane / 16) + j) in pass j
+    const int fe = f0 + (lane & 15);
+    double wq[KE][4], aq[KE][4], bq[KE][4];
 #pragma unroll
-    for (int kt = 0; kt < KTM; ++kt) {
-        if (kt < KT) {
-            red[((w * KTM + kt) * 2 + 0) * 64 + lane] = ca[kt];
-            red[((w * KTM + kt) * 2 + 1) * 64 + lane] = cb[kt];
+    for (int u = 0; u < KE; ++u) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int kc = 16 * (w + 4 * u) + 4 * sub + j;
+            const bool ok = w + 4 * u < KT && fe < a.F && kc < a.K;
+            const size_t e = ok ? (size_t)fe + (size_t)kc * a.F : 0;
+            wq[u][j] = ok ? a.W64[e] : 0.0;
+            aq[u][j] = ok ? a.A[e] / a.sc[kc] : 0.0;
+            bq[u][j] = ok ? a.B[e] * a.sc[kc] : 0.0;
         }
     }
-    __syncthreads();
+
+    // epilogue through a wave-private slab pair (the staging area is free
+    // after the last chunk's barrier; a wave's own LDS accesses stay in order)
+    float *slab = lds + w * 2 * RSLAB;
 #pragma unroll
     for (int u = 0; u < KE; ++u) {
         const int kt = w + 4 * u;
         if (kt >= KT) continue;
-        auto at = [&](int v, int c) { return red[((v * KTM + kt) * 2 + c) * 64 + lane]; };
-        const floatx4 sa = ((at(0, 0) + at(1, 0)) + at(2, 0)) + at(3, 0);
-        const floatx4 sb = ((at(0, 1) + at(1, 1)) + at(2, 1)) + at(3, 1);
-        const int kc = 16 * kt + (lane & 15);
+        const floatx4 sa = ((ca[u][0] + ca[u][1]) + ca[u][2]) + ca[u][3];
+        const floatx4 sb = ((cb[u][0] + cb[u][1]) + cb[u][2]) + cb[u][3];
+        reinterpret_cast<floatx4 *>(slab)[red_pos(lane)] = sa;
+        reinterpret_cast<floatx4 *>(slab + RSLAB)[red_pos(lane)] = sb;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int f = f0 + 4 * sub + r;
-            if (f < a.F && kc < a.K)
-                epilogue(a, f, kc, double(sa[r]), double(sb[r]), wq[u][r], aq[u][r], bq[u][r]);
+        for (int j = 0; j < 4; ++j) {
+            const int cl = 4 * sub + j;
+            const float ea = red_elem(slab, lane & 15, cl);
+            const float eb = red_elem(slab + RSLAB, lane & 15, cl);
+            const int kc = 16 * kt + cl;
+            if (fe < a.F && kc < a.K)
+                epilogue(a, fe, kc, double(ea), double(eb), wq[u][j], aq[u][j], bq[u][j]);
         }
     }
 }
@@ -206,12 +233,14 @@ __device__ __forceinline__ void fold_rows_body(const FoldArgs &a, int ft) {
 // waves), so a single minibatch spreads over ceil(F/16) ceil(K/16) blocks.
 // Each element is computed exactly as fold_rows_body computes it (the same
 // MFMA chain per wave over the frames with (n / 4) mod 4 == w, the same wave
-// order, the same epilogue), so both give the same bits.
+// order, the same epilogue), so both give the same bits.  The four waves
+// share the tile's epilogue: wave w takes its columns 4 q + w.
 // nslices > 1: write the FP32 partial tile of slice `slice` instead of the
 // epilogue.
 __device__ __forceinline__ void fold_tile16_body(const FoldArgs &a, int tile, int slice,
                                                  int nslices) {
-    __shared__ floatx4 red[4][2][64];
+    __shared__ float4 red4[4 * 2 * RSLAB / 4];   // wave partials, slabs [4][2]
+    float *red = reinterpret_cast<float *>(red4);
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int tiles_f = (a.F + 15) / 16;
@@ -224,19 +253,18 @@ __device__ __forceinline__ void fold_tile16_body(const FoldArgs &a, int tile, in
     const int sub = lane >> 4;             // frame within the group of 4
     const bool fok = fa < a.F, kok = kb < a.K;
 
-    // epilogue operands (wave 0 only), loaded before the frame rounds
-    const int kc = k0 + (lane & 15);
-    double wq[4], aq[4], bq[4];
-    if (w == 0 && nslices == 1) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int f = f0 + 4 * sub + r;
-            const bool ok = f < a.F && kc < a.K;
-            const size_t e = ok ? (size_t)f + (size_t)kc * a.F : 0;
-            wq[r] = ok ? a.W64[e] : 0.0;
-            aq[r] = ok ? a.A[e] / a.sc[kc] : 0.0;
-            bq[r] = ok ? a.B[e] * a.sc[kc] : 0.0;
-        }
+    // epilogue: wave w takes element (f0 + lane % 16, k0 + 4 (lane / 16) + w);
+    // its operands are loaded before the frame rounds
+    const int fe = f0 + (lane & 15);
+    const int cl = 4 * sub + w;
+    const int kc = k0 + cl;
+    const bool eok = fe < a.F && kc < a.K;
+    double wq = 0.0, aq = 0.0, bq = 0.0;
+    if (eok && nslices == 1) {
+        const size_t e = (size_t)fe + (size_t)kc * a.F;
+        wq = a.W64[e];
+        aq = a.A[e] / a.sc[kc];
+        bq = a.B[e] * a.sc[kc];
     }
 
     // minibatch loss: wave 1 of tile 0, lane l sums frames l, l + 64, ... in
@@ -267,30 +295,20 @@ __device__ __forceinline__ void fold_tile16_body(const FoldArgs &a, int tile, in
             cb = mfma16(r1[g], hh[g], cb);
         }
     }
-    red[w][0][lane] = ca;
-    red[w][1][lane] = cb;
+    reinterpret_cast<floatx4 *>(red + (w * 2 + 0) * RSLAB)[red_pos(lane)] = ca;
+    reinterpret_cast<floatx4 *>(red + (w * 2 + 1) * RSLAB)[red_pos(lane)] = cb;
     __syncthreads();
-    if (w != 0) return;
-    ca = ((red[0][0][lane] + red[1][0][lane]) + red[2][0][lane]) + red[3][0][lane];
-    cb = ((red[0][1][lane] + red[1][1][lane]) + red[2][1][lane]) + red[3][1][lane];
+    auto at = [&](int v, int c) { return red_elem(red + (v * 2 + c) * RSLAB, lane & 15, cl); };
+    const float sa = ((at(0, 0) + at(1, 0)) + at(2, 0)) + at(3, 0);
+    const float sb = ((at(0, 1) + at(1, 1)) + at(2, 1)) + at(3, 1);
+    if (!eok) return;
     if (nslices == 1) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int f = f0 + 4 * sub + r;
-            if (f < a.F && kc < a.K)
-                epilogue(a, f, kc, double(ca[r]), double(cb[r]), wq[r], aq[r], bq[r]);
-        }
+        epilogue(a, fe, kc, double(sa), double(sb), wq, aq, bq);
     } else {
         const size_t fk = (size_t)a.F * a.K;
         float *pa = a.part + (size_t)slice * 2 * fk;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int f = f0 + 4 * sub + r;
-            if (f < a.F && kc < a.K) {
-                pa[f + (size_t)kc * a.F] = ca[r];
-                pa[fk + f + (size_t)kc * a.F] = cb[r];
-            }
-        }
+        pa[fe + (size_t)kc * a.F] = sa;
+        pa[fk + fe + (size_t)kc * a.F] = sb;
     }
 }
 

@@ -20,14 +20,14 @@ __device__ inline uint16_t w16_bits(double v, int kind, int wexp) {
 }
 
 struct W16Out {
-    uint16_t *r, *c;   // null when the handle has no 16-bit copies
+    uint16_t *r, *c;   // null when the handle has no such 16-bit copy
     int kind, wexp, KP, FR;
 };
 
 __device__ inline void store_w16(const W16Out &o, int f, int k, double w) {
-    if (!o.r) return;
+    if (!o.c) return;
     const uint16_t b = w16_bits(w, o.kind, o.wexp);
-    o.r[(size_t)f * o.KP + k] = b;
+    if (o.r) o.r[(size_t)f * o.KP + k] = b;
     o.c[(size_t)k * o.FR + f] = b;
 }
 
@@ -116,7 +116,7 @@ __device__ __forceinline__ void rescale_body(const RescaleArgs &a, int k, int b)
 
 inline W16Out w16_out(const OnlineDev &d) {
     W16Out o;
-    o.r = d.w16_kind ? d.W16r : nullptr;
+    o.r = d.w16_kind && d.w16_rows ? d.W16r : nullptr;
     o.c = d.w16_kind ? d.W16c : nullptr;
     o.kind = d.w16_kind;
     o.wexp = d.wexp;
