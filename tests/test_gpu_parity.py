@@ -348,6 +348,40 @@ def test_checkpoint_resume_is_bitwise(kernel):
 
 
 @pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_set_one_statistic_keeps_the_other(kernel):
+    """After rescaling steps, setting A alone leaves B's value unchanged (and
+    setting B alone leaves A's), bit for bit, and the next step continues from
+    the mix exactly as a handle initialised with it does."""
+    F, K, b = 97, 6, 16
+    say(f"set one statistic {kernel}")
+    V, W0 = synth.problem(F, K, 4 * b, seed=93)
+    Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+    Wt = torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV)
+    g = bd.OnlineISNMF(Wt, b, kernel=kernel)
+    for s in range(3):
+        g.step(Vt[s * b:(s + 1) * b])
+    W1, A1, B1, t1 = g.get()
+    A2 = A1 * 1.5
+    g.set(A=A2, t=t1)
+    _, Ag, Bg, _ = g.get()
+    assert torch.equal(Ag, A2) and torch.equal(Bg, B1)
+    B2 = B1 * 0.75
+    g.set(B=B2, t=t1)
+    _, Ag, Bg, _ = g.get()
+    assert torch.equal(Ag, A2) and torch.equal(Bg, B2)
+    W64 = g.get_w64()
+    h = bd.OnlineISNMF(W1, b, kernel=kernel, A0=A2, B0=B2)
+    h.set_w64(W64)
+    h.set(t=t1)
+    g.step(Vt[3 * b:])
+    h.step(Vt[3 * b:])
+    Wg, Ag, Bg, _ = g.get()
+    Wh, Ah, Bh, _ = h.get()
+    torch.cuda.synchronize()
+    assert torch.equal(Wg, Wh) and torch.equal(Ag, Ah) and torch.equal(Bg, Bh)
+
+
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
 def test_repeatable_bitwise(kernel):
     F, K, b = 513, 50, 128
     say(f"repeatable {kernel}")
