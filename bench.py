@@ -215,6 +215,35 @@ def bench_multipass(bd, torch, np, Vt, Wt, N, passes, seed):
             "loss_per_entry": loss.item() / (passes * N * F)}
 
 
+def bench_heldout(bd, synth, torch, np, g, Wt, dev, seed, start, n_test=8192):
+    """The paper's criterion (section 3): unseen frames of the same stream (the
+    n_test frames after the pass), their h fitted at a frozen dictionary, then
+    eq. (1) per matrix entry; at the learned W (handle g) and at W(0)."""
+    Vte = synth.frames(F, K, n_test, seed, start=start)
+    Vt = torch.from_numpy(np.ascontiguousarray(Vte.T)).to(dev)
+    # at the generator's true factors the expected divergence per entry is Euler's
+    # gamma (E[e - log e - 1] for e ~ Exp(1)): the floor a dictionary can reach
+    out = {"frames": n_test, "first_frame": start, "floor_per_entry": 0.5772156649015329}
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for name in ("W", "W0"):
+        h = g if name == "W" else bd.OnlineISNMF(Wt, B, inner_iters=ITERS)
+        H = torch.empty((n_test, K), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        e0.record()
+        for s0 in range(0, n_test, B):
+            h.fit(Vt[s0:s0 + B], H[s0:s0 + B])
+        e1.record()
+        torch.cuda.synchronize()
+        W = h.get()[0]
+        out[f"objective_{name}_per_entry"] = bd.objective(Vt, W, H).item() / F
+        if name == "W":
+            out["fit_frames_per_s"] = n_test / (e0.elapsed_time(e1) / 1e3)
+        else:
+            h.close()
+    return out
+
+
 def bench_served(bd, synth, torch, np, dev, S, n_chunks, duration_s, threads, seed0,
                  tune="latency"):
     """Continuous batching: S sessions (F in {257,513}, K in {32,64}, BF16
@@ -374,9 +403,11 @@ def main() -> int:
     fps = nframes / (ms / 1e3)
     assert g.status() == 0
     online_loss = loss.item() / nframes / F
-    g.close()
     print(f"[bench] fused FP32: {steps} steps, {ms:.1f} ms, {fps:.4g} frames/s", file=sys.stderr,
           flush=True)
+    heldout = bench_heldout(bd, synth, torch, np, g, Wt, dev, args.seed, N)
+    g.close()
+    print(f"[bench] held-out: {heldout}", file=sys.stderr, flush=True)
 
     # roofline of the fit kernel: HIP events around every fit launch of the same pass
     g = bd.OnlineISNMF(Wt, B, inner_iters=ITERS)
@@ -477,6 +508,7 @@ def main() -> int:
         "plain_fp32": {"value": plain_fps, "unit": "frames/s", "steps": p_steps,
                        "speedup_fused": fps / plain_fps},
         "online_loss_per_entry": online_loss,
+        "heldout": heldout,
         "forms": forms,
     }
     if not args.no_cpu:
