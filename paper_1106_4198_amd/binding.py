@@ -131,6 +131,16 @@ def _check(code: int, what: str):
         raise IsnmfError(code, what)
 
 
+def forgetting_rho(r: float, beta: int, n_frames: int) -> float:
+    """The weight of past statistics for forgetting factor r (section 2.3):
+    rho = r^(beta / N) with beta frames per W update and N frames in the set, so
+    that rho -> 1 as N grows and runs with different beta compare at equal r.
+    r = 0 with beta = N gives rho = 0, the batch algorithm."""
+    if not 0.0 <= r <= 1.0 or beta < 1 or n_frames < 1:
+        raise ValueError("need 0 <= r <= 1, beta >= 1, n_frames >= 1")
+    return float(r) ** (float(beta) / float(n_frames))
+
+
 def make_params(eps=1e-12, inner_iters=20, rho=1.0, normalize=True, warm=False,
                 precision="fp32", kernel="auto", update_w=True) -> Params:
     p = Params()

@@ -108,3 +108,18 @@ def test_product_path_does_not_touch_the_oracle():
                 src = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in src and "from oracle" not in src, fn
                 assert "isnmf_ref_" not in src, fn
+
+
+def test_forgetting_rho_follows_section_2_3():
+    """rho = r^(beta/N): r itself when beta = N, 1 in the limit of a large set,
+    0 for the batch reading (r = 0, beta = N), and equal r^(1/N) per frame
+    whatever beta (rho^(N/beta) = r)."""
+    from paper_1106_4198_amd import binding
+    assert binding.forgetting_rho(0.7, 1000, 1000) == pytest.approx(0.7, rel=0, abs=1e-15)
+    assert binding.forgetting_rho(0.0, 500, 500) == 0.0
+    assert binding.forgetting_rho(0.7, 1000, 10**12) == pytest.approx(1.0, abs=1e-9)
+    for beta in (1, 10, 128, 1000):
+        rho = binding.forgetting_rho(0.7, beta, 10**5)
+        assert rho ** (10**5 / beta) == pytest.approx(0.7, rel=1e-9)
+    with pytest.raises(ValueError):
+        binding.forgetting_rho(1.5, 10, 10)
