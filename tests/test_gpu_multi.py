@@ -80,6 +80,31 @@ def test_batched_equals_alone_bitwise():
     m.close()
 
 
+def test_streams_that_run_out_keep_their_state():
+    """Steps past a stream's last frame leave its W, A, B (and the column
+    scale still pending on A and B) untouched while the others go on."""
+    data = inputs(seed0=350)
+    steps = 12
+    say("streams running out, %d steps" % steps)
+    alone = handles(data)
+    for g, (W0, V, b, prec) in zip(alone, data):
+        for s in range(steps):
+            lo, hi = s * b, min((s + 1) * b, V.shape[0])
+            if lo < hi:
+                g.step(V[lo:hi])
+    mixed = handles(data)
+    m = bd.MultiISNMF(mixed, [d[1] for d in data], [d[2] for d in data], loss=False)
+    m.run(steps, graph=True)
+    torch.cuda.synchronize()
+    assert m.frames_left() == 0
+    for i, (ga, gm) in enumerate(zip(alone, mixed)):
+        sa, sm = state(ga), state(gm)
+        assert sa[3] == sm[3] == MIX[i][4], (i, sa[3], sm[3])
+        for x, y in zip(sa[:3], sm[:3]):
+            assert torch.equal(x, y), f"stream {i} {MIX[i]} differs after running out"
+    m.close()
+
+
 def test_graph_replays_match_eager_every_step():
     data = inputs(seed0=400)
     say("graph replay vs eager")
