@@ -124,6 +124,7 @@ FitClass fit_class(int F, int K, int prec);
 FitClass valu_class(int F, int K);
 // The 16-frame tile variant for (F, K) with BF16 products, or ok = 0.
 FitClass tile_class(int F, int K);
+FitClass stile_class(int F, int K);
 FitDesc make_fit_desc(const OnlineDev &d, const float *V, int ldv, int b, int iters, double eps,
                       int warm, float *Hb, int ldh);
 
@@ -161,7 +162,13 @@ hipError_t launch_fit_tile_multi(const FitClass &c, const FitDesc *d, const int2
 hipError_t launch_fit_tile_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
                                 int tiles, hipStream_t s);
 // Frames per batched work item of a fit class.
-inline int frames_per_item(const FitClass &c) { return c.cpw == -1 ? 128 : NF; }
+hipError_t launch_fit_stile(const FitDesc &a, const FitClass &c, int b, hipStream_t s);
+hipError_t launch_fit_stile_multi(const FitClass &c, const FitDesc *d, const int2 *items, int n,
+                                  const long long *cur, const int *beff, hipStream_t s);
+hipError_t launch_fit_stile_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
+                                 int tiles, hipStream_t s);
+// 16-frame tile variants (cpw -1 resident W, -2 streamed W): 128 frames per item
+inline int frames_per_item(const FitClass &c) { return c.cpw < 0 ? 128 : NF; }
 // Every fit variant valid for the shape (the default first); returns the count.
 int fit_candidates(int F, int K, int prec, FitClass *out, int max_out);
 // The variant the autotuner chose for (F, K, prec, b), or the default.

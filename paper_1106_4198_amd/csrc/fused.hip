@@ -78,9 +78,11 @@ int fit_candidates(int F, int K, int prec, FitClass *out, int max_out) {
         const FitClass v = valu_class(F, K);
         if (v.ok) add(v);
     }
-    if (prec == 1) {                 // the 16-frame tile variant (BF16)
+    if (prec == 1) {                 // the 16-frame tile variants (BF16)
         const FitClass t = tile_class(F, K);
         if (t.ok) add(t);
+        const FitClass st = stile_class(F, K);
+        if (st.ok) add(st);
     }
     if (prec != 0 && d.kmax <= 64) {
         const int nch = d.main_chunks < 1 ? 1 : d.main_chunks;
@@ -141,6 +143,7 @@ hipError_t launch_fused_fit(const OnlineDev &d, const FitClass &c, const float *
     const FitDesc a = make_fit_desc(d, V, ldv, b, iters, eps, warm, Hb, ldh);
     if (c.cpw == 0) return prec == 0 ? launch_fit_valu(a, c, b, s) : hipErrorNotSupported;
     if (c.cpw == -1) return prec == 1 ? launch_fit_tile(a, c, b, s) : hipErrorNotSupported;
+    if (c.cpw == -2) return prec == 1 ? launch_fit_stile(a, c, b, s) : hipErrorNotSupported;
     const int grid = (b + NF - 1) / NF;
     if (prec == 1) return launch_fit_single_p<1>(a, c, grid, s);
     if (prec == 2) return launch_fit_single_p<2>(a, c, grid, s);

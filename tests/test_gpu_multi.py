@@ -265,3 +265,47 @@ def test_batched_tile_streams_equal_alone_bitwise():
         m.close()
     finally:
         bd.tune_clear()
+
+
+def test_batched_streamed_tile_streams_equal_alone_bitwise():
+    """BF16 streams of different F and K on the streamed 16-frame tile variant
+    share one launch per component class (the variant does not depend on F),
+    beside streams on other variants, and match their runs alone."""
+    mix = [(513, 50, 128, "bf16", 300), (1025, 100, 64, "bf16", 150), (1025, 40, 32, "bf16", 90),
+           (257, 64, 40, "bf16", 100), (700, 128, 16, "bf16", 40), (513, 50, 64, "fp32", 200),
+           (129, 8, 16, "bf16", 40)]
+    say("batched streamed tile vs alone")
+    bd.tune_clear()
+    for (F, K, b, prec, N) in mix[:5]:
+        bd.tune_set(F, K, "bf16", 8, -2, 0)
+    try:
+        data = []
+        for i, (F, K, b, prec, N) in enumerate(mix):
+            V, W0 = synth.problem(F, K, N, seed=850 + i)
+            data.append((torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV),
+                         torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV), b, prec))
+        steps = 3
+        alone = handles(data)
+        for g, (W0, V, b, prec) in zip(alone, data):
+            for s in range(steps):
+                lo, hi = s * b, min((s + 1) * b, V.shape[0])
+                if lo < hi:
+                    g.step(V[lo:hi])
+        mixed = handles(data)
+        m = bd.MultiISNMF(mixed, [d[1] for d in data], [d[2] for d in data])
+        m.run(steps, graph=True)
+        torch.cuda.synchronize()
+        for i, (ga, gm) in enumerate(zip(alone, mixed)):
+            sa, sm = state(ga), state(gm)
+            assert sa[3] == sm[3], i
+            for x, y in zip(sa[:3], sm[:3]):
+                assert torch.equal(x, y), f"stream {i} {mix[i]} differs alone vs batched"
+        W0 = data[1][0].cpu().double().numpy().T
+        V = data[1][1].cpu().double().numpy().T
+        st = oracle.OnlineState(W0)
+        for s in range(steps):
+            st.step(V[:, s * 64:(s + 1) * 64], iters=20)
+        assert rel_fro(from_gpu_kf(state(mixed[1])[0]), st.W) <= 2e-2
+        m.close()
+    finally:
+        bd.tune_clear()

@@ -59,21 +59,28 @@ def test_one_step_error_is_small(precision, F, K, b):
     assert g.status() == 0
 
 
-def tile_variant(F, K):
-    """Make handles of shape (F, K) in BF16 use the 16-frame tile variant."""
+def tile_variant(F, K, cpw=-1):
+    """Make handles of shape (F, K) in BF16 use a 16-frame tile variant: W
+    resident in LDS (cpw -1) or streamed through it (cpw -2)."""
     bd.tune_clear()
-    bd.tune_set(F, K, "bf16", 8, -1, 0)
-    assert bd.tune_get(F, K, "bf16") == (8, -1, 0)
+    bd.tune_set(F, K, "bf16", 8, cpw, 0)
+    assert bd.tune_get(F, K, "bf16") == (8, cpw, 0)
 
 
-@pytest.mark.parametrize("F,K,b", [(513, 50, 128), (129, 8, 16), (257, 64, 33), (70, 5, 6),
-                                   (513, 33, 7), (640, 64, 20), (16, 1, 3), (200, 40, 17),
-                                   (257, 16, 1), (600, 64, 48), (513, 50, 300), (33, 32, 129)])
-def test_tile_variant_one_step(F, K, b):
-    """BF16 16-frame tile variant (16x16x32 MFMA) against the FP64 oracle at the
-    precision-form bound, from a mid-stream state."""
-    say(f"tile step F={F} K={K} b={b}")
-    tile_variant(F, K)
+TILE_SHAPES = [(513, 50, 128), (129, 8, 16), (257, 64, 33), (70, 5, 6), (513, 33, 7), (640, 64, 20),
+               (16, 1, 3), (200, 40, 17), (257, 16, 1), (600, 64, 48), (513, 50, 300), (33, 32, 129)]
+# the streamed variant also covers F > 640 and K > 64
+STILE_SHAPES = TILE_SHAPES + [(1025, 128, 128), (1025, 100, 37), (1025, 40, 130), (1026, 97, 16),
+                              (700, 65, 9), (257, 128, 64), (1025, 72, 1)]
+
+
+@pytest.mark.parametrize("cpw,F,K,b", [(-1,) + s for s in TILE_SHAPES] + [(-2,) + s for s in STILE_SHAPES])
+def test_tile_variant_one_step(cpw, F, K, b):
+    """BF16 16-frame tile variants (16x16x32 MFMA; W resident in LDS, or
+    streamed through it one 32-row step at a time) against the FP64 oracle at
+    the precision-form bound, from a mid-stream state."""
+    say(f"tile step cpw={cpw} F={F} K={K} b={b}")
+    tile_variant(F, K, cpw)
     try:
         V, W0 = synth.problem(F, K, 3 * b, seed=6)
         st = oracle.OnlineState(W0.astype(np.float64))

@@ -117,13 +117,15 @@ def test_served_form_rejects_the_valu_variant():
     srv.close()
 
 
-def test_served_tile_sessions_equal_alone_bitwise():
-    """BF16 sessions on the 16-frame tile variant (chunks of 1..300 frames,
-    several 128-frame tiles) are served bitwise as they run alone."""
-    say("served tile sessions vs alone")
+@pytest.mark.parametrize("cpw", [-1, -2])
+def test_served_tile_sessions_equal_alone_bitwise(cpw):
+    """BF16 sessions on a 16-frame tile variant (W resident in LDS or streamed
+    through it; chunks of 1..300 frames, several 128-frame tiles) are served
+    bitwise as they run alone."""
+    say(f"served tile sessions vs alone, cpw {cpw}")
     bd.tune_clear()
     for F, K in ((257, 32), (513, 64), (513, 32)):
-        bd.tune_set(F, K, "bf16", 8, -1, 0)
+        bd.tune_set(F, K, "bf16", 8, cpw, 0)
     try:
         rng = np.random.default_rng(11)
         data = []
