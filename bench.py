@@ -137,12 +137,13 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0):
     t0 = time.perf_counter()
     data = gen_streams(synth, shapes, seed0, threads)
     gen_s = time.perf_counter() - t0
-    # kernel variant per distinct shape, timed at a batched step's launch size
-    # (throughput: the frames of every stream of that shape in one launch)
+    # kernel variant per distinct shape, timed for throughput: at the frames of
+    # every stream of that shape, and at least 8192 (a launch that shares many
+    # streams of one variant, as the batched step's launches do, is that full)
     tuned, variants = 0, {}
     for (Fi, Ki) in sorted(set((int(a), int(b)) for a, b in zip(Fs, Ks))):
         nb = int(sum(int(bb) for a, b2, bb in zip(Fs, Ks, bs) if int(a) == Fi and int(b2) == Ki))
-        bd.autotune(Fi, Ki, max(nb, 1024), precision="bf16", trials=2)
+        bd.autotune(Fi, Ki, max(nb, 8192), precision="bf16", trials=2)
         variants[(Fi, Ki)] = bd.tune_get(Fi, Ki, "bf16")
         tuned += 1
     hs, Vs = [], []
@@ -172,7 +173,8 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0):
            "frac_bf16_peak": flops / (ms / 1e3) / PEAK_BF16_MFMA,
            "gen_s": round(gen_s, 1)}
     n_tile = sum(1 for v in variants.values() if v[1] == -1)
-    out["variants"] = {"shapes": tuned, "tile16x16x32": n_tile}
+    n_stile = sum(1 for v in variants.values() if v[1] == -2)
+    out["variants"] = {"shapes": tuned, "tile16x16x32": n_tile, "tile16x16x32_streamed": n_stile}
     if mixed:
         out["workload"] = ("F in {257,513,1025}, K ~ U[16,128], b in {32,64,128,256}, "
                            f"{steps} timed minibatches per stream; {tuned} shapes autotuned")
