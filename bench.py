@@ -84,8 +84,13 @@ def cpu_threads() -> int:
     return max(1, min(16, n))
 
 
-def cpu_baseline(V, W0, target_s: float):
-    """The FP64 oracle on the host cores over a bounded prefix of the stream."""
+CHECKPOINTS = (1, 10, 100, 1000)   # minibatch steps at which the forms' errors are reported
+
+
+def cpu_baseline(V, W0, target_s: float, snaps=None):
+    """The FP64 oracle on the host cores over a bounded prefix of the stream.
+    snaps (a dict, optional) receives the oracle's (W, A, B, loss sum) after
+    each step count in CHECKPOINTS that the prefix reaches."""
     import numpy as np
     import oracle
 
@@ -101,6 +106,8 @@ def cpu_baseline(V, W0, target_s: float):
     t0 = time.perf_counter()
     for s in range(steps):
         st.step(Vs[:, s * B:(s + 1) * B], iters=ITERS)
+        if snaps is not None and s + 1 in CHECKPOINTS:
+            snaps[s + 1] = (st.W.copy(), st.A.copy(), st.B.copy(), st.loss_sum)
     dt = time.perf_counter() - t0
     oracle.set_threads(1)
     return {"value": steps * B / dt, "unit": "frames/s", "cores": nt, "kind": "oracle",
@@ -109,6 +116,43 @@ def cpu_baseline(V, W0, target_s: float):
 
 
 PEAK_BF16_MFMA = 2500e12        # MI355X dense BF16 matrix peak, FLOP/s
+
+
+def form_accuracy(bd, torch, np, Vt, Wt, snaps, fp32_variant):
+    """Relative error (Frobenius) of W, A, B and of the online loss sum against
+    the FP64 oracle's snapshots, per form, at the checkpoints the oracle
+    reached: each form runs the same stream prefix from W(0).  The FP32 fused
+    form runs fp32_variant (nw, cpw, wg), the fit variant of the timed pass."""
+    cps = sorted(snaps)
+    out = {"checkpoints": cps, "reference": "FP64 oracle, same stream prefix from W(0)",
+           "measure": "||x - x_oracle||_F / ||x_oracle||_F; loss: |sum - sum_oracle| / sum_oracle"}
+    if not cps:
+        return out
+
+    def rel(x, y):
+        return float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
+    bd.tune_set(F, K, "fp32", *fp32_variant)
+    for name, kw in (("fp32", {}), ("bf16", {"precision": "bf16"}), ("fp16", {"precision": "fp16"}),
+                     ("fp32_plain", {"kernel": "plain"})):
+        g = bd.OnlineISNMF(Wt, B, inner_iters=ITERS, **kw)
+        loss = torch.zeros((), dtype=torch.float64, device=Vt.device)
+        rec = {"W": [], "A": [], "B": [], "loss": []}
+        done = 0
+        for c in cps:
+            g.run_pass(Vt[done * B:c * B], B, loss_sum=loss)
+            done = c
+            _, A, Bm, _ = g.get()
+            W64 = g.get_w64()
+            Wr, Ar, Br, lr = snaps[c]
+            rec["W"].append(rel(W64.cpu().double().numpy().T, Wr))
+            rec["A"].append(rel(A.cpu().numpy().T, Ar))
+            rec["B"].append(rel(Bm.cpu().numpy().T, Br))
+            rec["loss"].append(abs(loss.item() - lr) / lr)
+        assert g.status() == 0
+        g.close()
+        out[name] = rec
+    return out
 
 
 def gen_streams(synth, shapes, seed0, threads):
@@ -514,7 +558,11 @@ def main() -> int:
         "forms": forms,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(V, W0, args.cpu_seconds)
+        snaps = {}
+        out["cpu_baseline"] = cpu_baseline(V, W0, args.cpu_seconds, snaps)
+        out["accuracy"] = form_accuracy(bd, torch, np, Vt, Wt, snaps, (nw, cpw, wg))
+        print(f"[bench] accuracy vs the FP64 oracle: {out['accuracy']}", file=sys.stderr,
+              flush=True)
     print(json.dumps(out), flush=True)
     return 0
 
