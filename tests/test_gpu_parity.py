@@ -261,6 +261,61 @@ def test_large_config_one_step_fused():
     compare_step(513, 50, 64, 20, "fp32", "fused", seed=52, tol=1e-5, steps_before=3, b_max=128)
 
 
+def test_full_size_pass_sampled_steps_match_oracle():
+    """The benchmark's workload at full size, in the launch configuration it
+    times: F=513, K=50, b=128, I=20 over N=10^6 resident frames (7812 full
+    minibatches and a last one of 64), fused FP32 on the VALU fit variant.  At
+    sampled minibatches the GPU's state before the step goes to the oracle,
+    which takes the same step on the same frames; the GPU's state and h after
+    it must match to 1e-5.  Over the whole pass: the online loss adds up step by
+    step, W's columns sum to 1 after every rescale, and A, B stay positive."""
+    F, K, b, I, N = 513, 50, 128, 20, 1_000_000
+    nsteps = (N + b - 1) // b
+    sampled = (0, 1, 3907, nsteps - 2, nsteps - 1)   # first, mid-stream, last full, tail of 64
+    say(f"full-size pass F={F} K={K} b={b} N={N}, sampled steps {sampled}")
+    V = synth.frames(F, K, N, 2011, threads=8)
+    W0 = synth.initial_dictionary(F, K, 2011)
+    Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+    with valu_variant(F, K):
+        g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b, inner_iters=I)
+    loss = torch.zeros((), dtype=torch.float64, device=DEV)
+    step_losses = 0.0
+    done = 0
+    for s in sampled:
+        if s > done:   # the steps between samples, one isnmf_online_step each
+            g.run_pass(Vt[done * b:s * b], b, loss_sum=loss)
+        lo, hi = s * b, min((s + 1) * b, N)
+        W_before = from_gpu_kf(g.get_w64())
+        _, A, B, t = g.get()
+        assert t == lo
+        st = oracle.OnlineState(W_before, from_gpu_kf(A), from_gpu_kf(B), t)
+        l_before = loss.item()
+        H = torch.zeros((hi - lo, K), dtype=torch.float32, device=DEV)
+        g.step(Vt[lo:hi], H, loss)
+        Hr, _, fl = st.step(V[:, lo:hi].astype(np.float64), iters=I)
+        assert fl == 0
+        _, A, B, t = g.get()
+        assert t == hi
+        assert_close(from_gpu_kf(g.get_w64()), st.W, 1e-5, f"W after step {s}")
+        assert_close(from_gpu_kf(A), st.A, 1e-5, f"A after step {s}")
+        assert_close(from_gpu_kf(B), st.B, 1e-5, f"B after step {s}")
+        assert_close(H.cpu().double().numpy().T, Hr, 1e-5, f"H of step {s}")
+        step_loss = loss.item() - l_before
+        assert abs(step_loss - st.last_loss) <= 1e-6 * st.last_loss, (s, step_loss, st.last_loss)
+        step_losses += step_loss
+        done = s + 1
+    assert done == nsteps
+    W = from_gpu_kf(g.get_w64())
+    _, A, B, _ = g.get()
+    assert np.all(np.abs(W.sum(axis=0) - 1.0) <= 1e-12)
+    assert np.all(from_gpu_kf(A) > 0) and np.all(from_gpu_kf(B) > 0)
+    per_entry = loss.item() / N / F
+    print(f"[full-size] online loss per entry {per_entry:.6f}")
+    assert 0.5772 < per_entry < 0.7   # above the generator's floor (Euler's gamma), finite
+    assert g.status() == 0
+    g.close()
+
+
 # ---------------------------------------------------------------- batch MU and objective
 
 # W and H cross the batch ABI in FP32 between cycles, so even the FP64 device
