@@ -38,6 +38,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int WF = 16;       // frames per wave
 constexpr int NWT = 8;       // waves per workgroup
 constexpr int FPW = WF * NWT;  // frames per workgroup
+constexpr int PIPE_S_MAX = 17;  // contraction steps up to which the update loop is pipelined
 
 __device__ inline f4 mfma(bf16x8 a, bf16x8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -131,11 +132,12 @@ __device__ inline void body(const FitDesc &a, int n_first) {
         vp[t][1] = pack2(vprime(t, 2, v[2]), vprime(t, 3, v[3]));
     }
     if (bad) atomicOr(a.flags, FLAG_NONFINITE_V);
-    // unpacked where used: the empty asm keeps the compiler from hoisting
-    // the FP32 values out of the update loop (that would undo the packing)
+    // unpacked where used; the packed words are redefined by an empty asm at
+    // the start of every update (in place, no copies), which keeps the
+    // compiler from hoisting the FP32 values out of the update loop (that
+    // would undo the packing)
     auto vq = [&](int t, int j) {
-        uint32_t u = vp[t][j >> 1];
-        asm volatile("" : "+v"(u));
+        const uint32_t u = vp[t][j >> 1];
         return __uint_as_float((j & 1) ? (u & 0xffff0000u) : (u << 16));
     };
     // X accumulator start: eps, or 1 on rows past F (W = 0 there, x only needs to be > 0)
@@ -184,22 +186,35 @@ __device__ inline void body(const FitDesc &a, int n_first) {
         return x;
     };
 
+    // X operands of row tiles 2s and 2s + 1 (contraction step s), and the
+    // model products of those tiles from them
+    auto load_wx = [&](int s, bf16x8 (&o)[2][KS]) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int c = 0; c < KS; ++c)
+                o[u][c] = __builtin_bit_cast(bf16x8, wxl[((2 * s + u) * KS + c) * 64 + lane]);
+    };
+    auto model_ops = [&](int t, const bf16x8 (&ops)[KS]) {
+        f4 x = cinit(t);
+#pragma unroll
+        for (int c = 0; c < KS; ++c) x = mfma(ops[c], hb[c], x);
+        return x;
+    };
+
     int guard = 0;
     for (int it = 0; it < a.iters; ++it) {
+#pragma unroll
+        for (int t = 0; t < T; ++t) asm volatile("" : "+v"(vp[t][0]), "+v"(vp[t][1]));
         f4 na[MT], da[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             na[mt] = f4{0.f, 0.f, 0.f, 0.f};
             da[mt] = f4{0.f, 0.f, 0.f, 0.f};
         }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            // the W operands are re-read from LDS at every step (kept from
-            // being hoisted into registers: all of them would not fit), and
-            // the steps are not interleaved by the scheduler (live ranges)
-            asm volatile("" ::: "memory");
-            __builtin_amdgcn_sched_barrier(0);
-            const f4 x0 = model(2 * s), x1 = model(2 * s + 1);
+        // ratios r1 = 1/x, r2 = (eps + v)/x^2 of step s's rows from its model
+        // products, as the two bf16 B operands of NUM and DEN
+        auto ratios = [&](int s, const f4 &x0, const f4 &x1, bf16x8 &b1, bf16x8 &b2) {
             float r1[8], r2[8];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -208,17 +223,69 @@ __device__ inline void body(const FitDesc &a, int n_first) {
                 r1[4 + j] = __builtin_amdgcn_rcpf(x1[j]);
                 r2[4 + j] = vq(2 * s + 1, j) * r1[4 + j] * r1[4 + j];
             }
-            const bf16x8 b1 = __builtin_bit_cast(
+            b1 = __builtin_bit_cast(
                 bf16x8, uint4{pack2(r1[0], r1[1]), pack2(r1[2], r1[3]), pack2(r1[4], r1[5]),
                               pack2(r1[6], r1[7])});
-            const bf16x8 b2 = __builtin_bit_cast(
+            b2 = __builtin_bit_cast(
                 bf16x8, uint4{pack2(r2[0], r2[1]), pack2(r2[2], r2[3]), pack2(r2[4], r2[5]),
                               pack2(r2[6], r2[7])});
+        };
+        if constexpr (S <= PIPE_S_MAX) {
+            // Software pipeline over the contraction steps: step s + 1's model
+            // products are issued to the matrix pipe before step s's ratios are
+            // formed on the VALU, from X operands read from LDS one step ahead
+            // (register sets wx[s & 1]).  The products and sums are those of
+            // the plain order below, so the results are the same bits.
+            bf16x8 wx[2][2][KS];
+            load_wx(0, wx[0]);
+            f4 x0 = model_ops(0, wx[0][0]), x1 = model_ops(1, wx[0][1]);
+            if (S > 1) load_wx(1, wx[1]);
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const bf16x8 wt = __builtin_bit_cast(bf16x8, wnl[(s * MT + mt) * 64 + lane]);
-                na[mt] = mfma(wt, b2, na[mt]);
-                da[mt] = mfma(wt, b1, da[mt]);
+            for (int s = 0; s < S; ++s) {
+                // the W operands are re-read from LDS at every step (kept from
+                // being hoisted into registers: all of them would not fit), and
+                // the steps are not interleaved by the scheduler (live ranges)
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+                f4 y0 = ce, y1 = ce;
+                if (s + 1 < S) {
+                    y0 = model_ops(2 * s + 2, wx[(s + 1) & 1][0]);
+                    y1 = model_ops(2 * s + 3, wx[(s + 1) & 1][1]);
+                }
+                // this step's W^T operands, then the X operands of step s + 2:
+                // in that order the wait for the first leaves the second in flight
+                bf16x8 wt[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    wt[mt] = __builtin_bit_cast(bf16x8, wnl[(s * MT + mt) * 64 + lane]);
+                __builtin_amdgcn_sched_barrier(0);
+                if (s + 2 < S) load_wx(s + 2, wx[s & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+                bf16x8 b1, b2;
+                ratios(s, x0, x1, b1, b2);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    na[mt] = mfma(wt[mt], b2, na[mt]);
+                    da[mt] = mfma(wt[mt], b1, da[mt]);
+                }
+                x0 = y0;
+                x1 = y1;
+            }
+        } else {
+            // plain order (larger S: the pipeline's registers would spill)
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+                const f4 x0 = model(2 * s), x1 = model(2 * s + 1);
+                bf16x8 b1, b2;
+                ratios(s, x0, x1, b1, b2);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const bf16x8 wt = __builtin_bit_cast(bf16x8, wnl[(s * MT + mt) * 64 + lane]);
+                    na[mt] = mfma(wt, b2, na[mt]);
+                    da[mt] = mfma(wt, b1, da[mt]);
+                }
             }
         }
 #pragma unroll
