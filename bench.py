@@ -181,21 +181,52 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0):
     t0 = time.perf_counter()
     data = gen_streams(synth, shapes, seed0, threads)
     gen_s = time.perf_counter() - t0
-    # kernel variant per distinct shape, timed for throughput: at the frames of
-    # every stream of that shape, and at least 8192 (a launch that shares many
-    # streams of one variant, as the batched step's launches do, is that full)
-    tuned, variants = 0, {}
-    for (Fi, Ki) in sorted(set((int(a), int(b)) for a, b in zip(Fs, Ks))):
-        nb = int(sum(int(bb) for a, b2, bb in zip(Fs, Ks, bs) if int(a) == Fi and int(b2) == Ki))
-        bd.autotune(Fi, Ki, max(nb, 8192), precision="bf16", trials=2)
-        variants[(Fi, Ki)] = bd.tune_get(Fi, Ki, "bf16")
-        tuned += 1
-    hs, Vs = [], []
-    for (V, W0), b in zip(data, bs):
-        Vs.append(torch.from_numpy(np.ascontiguousarray(V.T)).to(dev))
-        hs.append(bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(dev), int(b),
-                                 precision="bf16"))
-    m = bd.MultiISNMF(hs, Vs, [int(x) for x in bs], loss=False)
+    Vs = [torch.from_numpy(np.ascontiguousarray(V.T)).to(dev) for V, _ in data]
+    shape_set = sorted(set((int(a), int(b)) for a, b in zip(Fs, Ks)))
+
+    def tune(floor):
+        # kernel variant per distinct shape, timed at the frames of every
+        # stream of that shape and at least `floor`
+        chosen = {}
+        for (Fi, Ki) in shape_set:
+            nb = int(sum(int(bb) for a, b2, bb in zip(Fs, Ks, bs) if int(a) == Fi and int(b2) == Ki))
+            bd.autotune(Fi, Ki, max(nb, floor), precision="bf16", trials=2)
+            chosen[(Fi, Ki)] = bd.tune_get(Fi, Ki, "bf16")
+        return chosen
+
+    def make():
+        hs = [bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(dev), int(b),
+                             precision="bf16") for (_, W0), b in zip(data, bs)]
+        return hs, bd.MultiISNMF(hs, Vs, [int(x) for x in bs], loss=False)
+
+    # Step-level choice of the tuning floor: a floor of 8192 frames tunes each
+    # shape for throughput (right when a shape's launch is full), 1024 leans
+    # to latency (right when a shape has few frames and one slow workgroup
+    # would hold the whole step).  With several shapes both are tried on the
+    # captured step itself (one warm-up and two timed replays, on streams of
+    # their own) and the faster is kept.
+    floors = [8192, 1024] if len(shape_set) > 1 else [8192]
+    trial = {}
+    for fl in floors:
+        bd.tune_clear()
+        variants = tune(fl)
+        if len(floors) > 1:
+            hs, m = make()
+            m.run(1, graph=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m.run(2, graph=True)
+            torch.cuda.synchronize()
+            trial[fl] = (time.perf_counter() - t0) / 2 * 1e3
+            m.close()
+            for h in hs:
+                h.close()
+    floor = min(trial, key=trial.get) if trial else floors[0]
+    if floor != floors[-1]:
+        bd.tune_clear()
+        variants = tune(floor)
+    tuned = len(shape_set)
+    hs, m = make()
     m.run(warm, graph=True)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -218,7 +249,9 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0):
            "gen_s": round(gen_s, 1)}
     n_tile = sum(1 for v in variants.values() if v[1] == -1)
     n_stile = sum(1 for v in variants.values() if v[1] == -2)
-    out["variants"] = {"shapes": tuned, "tile16x16x32": n_tile, "tile16x16x32_streamed": n_stile}
+    out["variants"] = {"shapes": tuned, "tile16x16x32": n_tile, "tile16x16x32_streamed": n_stile,
+                       "tune_floor_frames": floor,
+                       "floor_trial_ms_per_step": {str(k): round(v, 3) for k, v in trial.items()}}
     if mixed:
         out["workload"] = ("F in {257,513,1025}, K ~ U[16,128], b in {32,64,128,256}, "
                            f"{steps} timed minibatches per stream; {tuned} shapes autotuned")

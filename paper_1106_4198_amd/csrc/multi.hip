@@ -1,7 +1,8 @@
 // Batched form: many independent online streams (each its own W, A, B, F, K,
 // minibatch size) advanced by one minibatch per step with one fit launch per
 // kernel variant in use, one fold launch and one rescale launch for all
-// streams.  A step reads its per-stream frame cursors on the device, so it can
+// streams (the fit launches of different variants side by side on up to four
+// streams).  A step reads its per-stream frame cursors on the device, so it can
 // be captured once into a hipGraph and replayed.  Also the autotuner that picks
 // the fit variant for a shape.
 //
@@ -109,8 +110,18 @@ struct isnmf_multi {
     struct Group {
         FitClass c;
         int prec, off, n;
+        double cost;   // frames x F x K over its items (for the lane balance)
+        int lane;      // 0: the step's stream; i > 0: side[i - 1]
     };
     std::vector<Group> groups;
+    // The fit groups are independent (each stream is in exactly one), so a
+    // step forks them over up to LANES streams: one event after prepare, one
+    // join per side stream before the fold.  Each launch is bounded by its
+    // slowest workgroup; side by side those tails overlap instead of adding.
+    static constexpr int LANES = 4;
+    int nlanes = 1;
+    hipStream_t side[LANES - 1] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[LANES - 1] = {};
     int fold_off = 0, fold_n = 0, rs_off = 0, rs_n = 0;
     int fold_ktm = 1;   // fold instance: covers the widest stream's component tiles
     hipStream_t cap = nullptr;
@@ -208,20 +219,35 @@ size_t count_items(isnmf_online *const *h, const int *b, int S) {
 hipError_t enqueue_step(isnmf_multi *m, hipStream_t s) {
     const int blocks = (m->S + 255) / 256;
     prepare_kernel<<<blocks, 256, 0, s>>>(m->S, m->d_b, m->d_nf, m->d_cursor, m->d_beff);
+    if (m->nlanes > 1) {
+        hipError_t e = hipEventRecord(m->ev_fork, s);
+        for (int i = 0; e == hipSuccess && i < m->nlanes - 1; ++i)
+            e = hipStreamWaitEvent(m->side[i], m->ev_fork, 0);
+        if (e != hipSuccess) return e;
+    }
     for (const auto &g : m->groups) {
         hipError_t e;
+        const hipStream_t gs = g.lane ? m->side[g.lane - 1] : s;
         if (g.c.cpw == 0)
-            e = launch_fit_valu_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
+            e = launch_fit_valu_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else if (g.c.cpw == -1)
-            e = launch_fit_tile_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
+            e = launch_fit_tile_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else if (g.c.cpw == -2)
-            e = launch_fit_stile_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
+            e = launch_fit_stile_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else if (g.prec == 1)
-            e = launch_fit_multi_p<1>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
+            e = launch_fit_multi_p<1>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else if (g.prec == 2)
-            e = launch_fit_multi_p<2>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
+            e = launch_fit_multi_p<2>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else
-            e = launch_fit_multi_p<0>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, s);
+            e = launch_fit_multi_p<0>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
+        if (e != hipSuccess) return e;
+    }
+    if (m->nlanes > 1) {
+        hipError_t e = hipSuccess;
+        for (int i = 0; e == hipSuccess && i < m->nlanes - 1; ++i) {
+            e = hipEventRecord(m->ev_join[i], m->side[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, m->ev_join[i], 0);
+        }
         if (e != hipSuccess) return e;
     }
     if (m->fold_n) {
@@ -238,6 +264,17 @@ hipError_t enqueue_step(isnmf_multi *m, hipStream_t s) {
         rescale_multi_kernel<<<m->rs_n, 64, 0, s>>>(m->d_rs, m->d_upd, m->d_items + m->rs_off, m->d_beff);
     advance_kernel<<<blocks, 256, 0, s>>>(m->S, m->d_beff, m->d_cursor);
     return hipGetLastError();
+}
+
+void release_lanes(isnmf_multi *m) {
+    for (int i = 0; i < isnmf_multi::LANES - 1; ++i) {
+        if (m->side[i]) hipStreamDestroy(m->side[i]);
+        if (m->ev_join[i]) hipEventDestroy(m->ev_join[i]);
+        m->side[i] = nullptr;
+        m->ev_join[i] = nullptr;
+    }
+    if (m->ev_fork) hipEventDestroy(m->ev_fork);
+    m->ev_fork = nullptr;
 }
 
 void host_advance(isnmf_multi *m, hipStream_t s) {
@@ -334,8 +371,30 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         G.prec = std::get<5>(g.first);
         G.off = (int)items.size();
         G.n = (int)g.second.size();
+        G.cost = 0.0;
+        for (const int2 &it : g.second) {
+            const OnlineDev &d = *isnmf_handle_dev(handles[it.x]);
+            G.cost += (double)frames_per_item(G.c) * d.F * d.K;
+        }
+        G.lane = 0;
         items.insert(items.end(), g.second.begin(), g.second.end());
         m->groups.push_back(G);
+    }
+    // lanes: largest group first onto the least loaded lane
+    m->nlanes = std::min((int)m->groups.size(), isnmf_multi::LANES);
+    {
+        std::vector<int> order(m->groups.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return m->groups[x].cost > m->groups[y].cost; });
+        double load[isnmf_multi::LANES] = {};
+        for (const int gi : order) {
+            int best = 0;
+            for (int l = 1; l < m->nlanes; ++l)
+                if (load[l] < load[best]) best = l;
+            m->groups[gi].lane = best;
+            load[best] += m->groups[gi].cost;
+        }
     }
     // streams to XCDs by their fold tiles x components (the state they move)
     std::vector<size_t> state(S);
@@ -376,7 +435,15 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
     cp(m->d_nf, n_frames, sizeof(long long) * S);
     cp(m->d_items, items.data(), sizeof(int2) * items.size());
     if (e == hipSuccess) e = hipStreamSynchronize(st);   // host vectors go out of scope
+    if (m->nlanes > 1 && e == hipSuccess) {
+        e = hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming);
+        for (int i = 0; e == hipSuccess && i < m->nlanes - 1; ++i) {
+            e = hipStreamCreateWithFlags(&m->side[i], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_join[i], hipEventDisableTiming);
+        }
+    }
     if (e != hipSuccess) {
+        release_lanes(m);
         delete m;
         return ISNMF_EDEVICE;
     }
@@ -441,6 +508,9 @@ int isnmf_multi_destroy(isnmf_multi *m) {
     if (m->exec) hipGraphExecDestroy(m->exec);
     if (m->graph) hipGraphDestroy(m->graph);
     if (m->cap) hipStreamDestroy(m->cap);
+    for (int i = 0; i < m->nlanes - 1; ++i)
+        if (m->side[i] && hipStreamSynchronize(m->side[i]) != hipSuccess) e = hipErrorUnknown;
+    release_lanes(m);
     delete m;
     return e == hipSuccess ? ISNMF_OK : ISNMF_EDEVICE;
 }
