@@ -8,7 +8,8 @@
 // each session still follows Algorithm 1 minibatch by minibatch),
 // up to max_frames frames in total, and runs one minibatch step for all of
 // them: one fit launch per kernel variant in use, then one fold and one
-// rescale launch per variant, reading a small work list (session, frames,
+// rescale launch per variant (the variants' chains side by side on up to four
+// streams), reading a small work list (session, frames,
 // count) that reaches the device through a pinned ring buffer.  Up to
 // `inflight` steps are enqueued at once; chunks that arrive meanwhile join
 // the next step.  A chunk's latency is arrival to the end of its step.
@@ -172,6 +173,13 @@ struct isnmf_server {
     };
     std::vector<Slot> slots;
     int next_slot = 0;
+    // The groups of a step (one per variant and shape) touch disjoint
+    // sessions, so their fit -> fold -> rescale chains are forked over up to
+    // LANES streams (one event after the work-list copy, one join per side
+    // stream before the step's completion event).
+    static constexpr int LANES = 4;
+    hipStream_t side[LANES - 1] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[LANES - 1] = {};
     long long steps = 0, frames = 0;
     double busy_since = 0.0;
 };
@@ -250,7 +258,13 @@ int launch_step(isnmf_server *s) {
     if (hipMemcpyAsync(slot->dev, slot->host, sizeof(Work) * n, hipMemcpyHostToDevice, st) !=
         hipSuccess)
         return -1;
-    // launches per group of equal (variant, shape)
+    // groups of equal (variant, shape): [lo, hi) ranges of the sorted pick
+    struct Span {
+        int lo, hi, maxb;
+        double cost;
+        int lane;
+    };
+    std::vector<Span> spans;
     for (int lo = 0; lo < n;) {
         const auto &A = s->sess[pick[lo]];
         int hi = lo + 1, maxb = s->reqs[slot->reqs[lo]].n;
@@ -262,21 +276,54 @@ int launch_step(isnmf_server *s) {
             maxb = std::max(maxb, s->reqs[slot->reqs[hi]].n);
             ++hi;
         }
-        const int cnt = hi - lo;
-        const int tiles = (maxb + NF - 1) / NF;
-        if (serve_fit_any(A.prec, A.cls, s->d_fit, slot->dev + lo, cnt, tiles, maxb, st) != hipSuccess)
+        double cost = 0.0;
+        for (int i = lo; i < hi; ++i) cost += (double)s->reqs[slot->reqs[i]].n * A.F * A.K;
+        spans.push_back(Span{lo, hi, maxb, cost, 0});
+        lo = hi;
+    }
+    // lanes: largest group first onto the least loaded lane
+    const int nlanes = std::min((int)spans.size(), isnmf_server::LANES);
+    {
+        std::vector<int> order(spans.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return spans[x].cost > spans[y].cost; });
+        double load[isnmf_server::LANES] = {};
+        for (const int gi : order) {
+            int best = 0;
+            for (int l = 1; l < nlanes; ++l)
+                if (load[l] < load[best]) best = l;
+            spans[gi].lane = best;
+            load[best] += spans[gi].cost;
+        }
+    }
+    if (nlanes > 1) {
+        if (hipEventRecord(s->ev_fork, st) != hipSuccess) return -1;
+        for (int i = 0; i < nlanes - 1; ++i)
+            if (hipStreamWaitEvent(s->side[i], s->ev_fork, 0) != hipSuccess) return -1;
+    }
+    for (const Span &sp : spans) {
+        const auto &A = s->sess[pick[sp.lo]];
+        const hipStream_t ls = sp.lane ? s->side[sp.lane - 1] : st;
+        const int lo = sp.lo, cnt = sp.hi - sp.lo;
+        const int tiles = (sp.maxb + NF - 1) / NF;
+        if (serve_fit_any(A.prec, A.cls, s->d_fit, slot->dev + lo, cnt, tiles, sp.maxb, ls) !=
+            hipSuccess)
             return -1;
         const dim3 fg(cnt, (A.F + 15) / 16);
         switch (fold_ktm(A.K)) {
-            case 1: serve_fold_kernel<1><<<fg, 256, 0, st>>>(s->d_fold, slot->dev + lo); break;
-            case 2: serve_fold_kernel<2><<<fg, 256, 0, st>>>(s->d_fold, slot->dev + lo); break;
-            case 4: serve_fold_kernel<4><<<fg, 256, 0, st>>>(s->d_fold, slot->dev + lo); break;
-            default: serve_fold_kernel<8><<<fg, 256, 0, st>>>(s->d_fold, slot->dev + lo); break;
+            case 1: serve_fold_kernel<1><<<fg, 256, 0, ls>>>(s->d_fold, slot->dev + lo); break;
+            case 2: serve_fold_kernel<2><<<fg, 256, 0, ls>>>(s->d_fold, slot->dev + lo); break;
+            case 4: serve_fold_kernel<4><<<fg, 256, 0, ls>>>(s->d_fold, slot->dev + lo); break;
+            default: serve_fold_kernel<8><<<fg, 256, 0, ls>>>(s->d_fold, slot->dev + lo); break;
         }
-        serve_rescale_kernel<<<dim3(cnt, A.K), 64, 0, st>>>(s->d_rs, s->d_upd, slot->dev + lo);
-        lo = hi;
+        serve_rescale_kernel<<<dim3(cnt, A.K), 64, 0, ls>>>(s->d_rs, s->d_upd, slot->dev + lo);
     }
     if (hipGetLastError() != hipSuccess) return -1;
+    for (int i = 0; i < nlanes - 1; ++i)
+        if (hipEventRecord(s->ev_join[i], s->side[i]) != hipSuccess ||
+            hipStreamWaitEvent(st, s->ev_join[i], 0) != hipSuccess)
+            return -1;
     for (int i = 0; i < n; ++i) {
         auto &ss = s->sess[pick[i]];
         isnmf_handle_advance(ss.h, s->reqs[slot->reqs[i]].n, st);
@@ -286,6 +333,20 @@ int launch_step(isnmf_server *s) {
     s->steps += 1;
     s->frames += frames;
     return frames;
+}
+
+// frees the server's host resources (pinned work lists, events, side streams)
+void release(isnmf_server *s) {
+    for (auto &sl : s->slots) {
+        if (sl.host) hipHostFree(sl.host);
+        if (sl.ev) hipEventDestroy(sl.ev);
+    }
+    for (int i = 0; i < isnmf_server::LANES - 1; ++i) {
+        if (s->side[i]) hipStreamDestroy(s->side[i]);
+        if (s->ev_join[i]) hipEventDestroy(s->ev_join[i]);
+    }
+    if (s->ev_fork) hipEventDestroy(s->ev_fork);
+    delete s;
 }
 
 }  // namespace
@@ -340,6 +401,14 @@ int isnmf_server_create(isnmf_server **out, int max_sessions, int max_per_step, 
             delete s;
             return ISNMF_ENOMEM;
         }
+    }
+    bool ok = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; ok && i < isnmf_server::LANES - 1; ++i)
+        ok = hipStreamCreateWithFlags(&s->side[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&s->ev_join[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        release(s);
+        return ISNMF_EDEVICE;
     }
     *out = s;
     return ISNMF_OK;
@@ -472,11 +541,9 @@ double isnmf_server_clock(void) { return now_s(); }
 int isnmf_server_destroy(isnmf_server *s) {
     if (!s) return ISNMF_EINVAL;
     hipError_t e = hipStreamSynchronize(s->stream);
-    for (auto &sl : s->slots) {
-        if (sl.host) hipHostFree(sl.host);
-        if (sl.ev) hipEventDestroy(sl.ev);
-    }
-    delete s;
+    for (int i = 0; i < isnmf_server::LANES - 1; ++i)
+        if (s->side[i] && hipStreamSynchronize(s->side[i]) != hipSuccess) e = hipErrorUnknown;
+    release(s);
     return e == hipSuccess ? ISNMF_OK : ISNMF_EDEVICE;
 }
 
