@@ -304,12 +304,24 @@ __device__ inline void body(const FitDesc &a, int n_first) {
     }
     if (guard) atomicOr(a.flags, FLAG_GUARD_H);
 
-    // ---- final model: R1, R2 for the fold (FP32) and the frame loss
+    // ---- final model: R1, R2 for the fold (FP32) and the frame loss.  v (FP32)
+    // is read FPD row tiles ahead of its use, so that the loads are in flight
+    // during the tiles before (the update loop's registers are free here).
+    constexpr int FPD = 8;
+    float vf[T][4];
+#pragma unroll
+    for (int t = 0; t < FPD && t < T; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) vf[t][j] = load_v(t, j);
     double ls = 0.0;
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         asm volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
+        if (t + FPD < T) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) vf[t + FPD][j] = load_v(t + FPD, j);
+        }
         const f4 x = model(t);
         const int row0 = 16 * t + 4 * g;
         f4 r1, r2;
@@ -317,7 +329,7 @@ __device__ inline void body(const FitDesc &a, int n_first) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const float r = __builtin_amdgcn_rcpf(x[j]);
-            const float ve = vprime(t, j, load_v(t, j));
+            const float ve = vprime(t, j, vf[t][j]);
             r1[j] = r;
             r2[j] = ve * r * r;
             if (row0 + j < F) l += dis_term32(ve, r);
