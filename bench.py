@@ -197,7 +197,7 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0):
     def make():
         hs = [bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(dev), int(b),
                              precision="bf16") for (_, W0), b in zip(data, bs)]
-        return hs, bd.MultiISNMF(hs, Vs, [int(x) for x in bs], loss=False)
+        return hs, bd.MultiISNMF(hs, Vs, [int(x) for x in bs], loss=True)
 
     # Step-level choice of the tuning floor: a floor of 8192 frames tunes each
     # shape for throughput (right when a shape's launch is full), 1024 leans
@@ -357,6 +357,9 @@ def bench_served(bd, synth, torch, np, dev, S, n_chunks, duration_s, threads, se
     def run(arrivals, sess, lens):
         srv = bd.Server(max_sessions=S, max_per_step=S, max_frames=1 << 16, inflight=2)
         ids = [srv.open(h) for h in hs]
+        loss = torch.zeros(S, dtype=torch.float64, device=dev)   # each session's running loss
+        for i, sid in enumerate(ids):
+            srv.set_loss(sid, loss[i:i + 1])
         chunks = [chunk(int(sx), int(L)) for sx, L in zip(sess, lens)]
         t0 = bd.Server.clock()
         k = 0

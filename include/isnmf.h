@@ -288,6 +288,18 @@ int isnmf_server_create(isnmf_server **out, int max_sessions, int max_per_step, 
                         void *stream);
 /* Register a handle; *session receives its index. */
 int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *session);
+/*
+ * Running loss of a session (the diagnostic of Algorithm 1's online
+ * objective, eq. 1 with eps inside, section 2.3): from the next step on,
+ * each served chunk adds its sum of d_IS(eps + v, eps + W h) over the chunk's
+ * frames and rows, in FP64, to *d_loss_sum (a device scalar the caller owns
+ * and zeroes; NULL turns it off again).  The sum of one chunk is formed in the
+ * same order as isnmf_online_step's loss_sum for that chunk, so a session
+ * served in a mix accumulates the same bits as stepped alone chunk by chunk.
+ * Synchronizes the server's stream.  ISNMF_EINVAL for a session index not
+ * returned by isnmf_server_open.
+ */
+int isnmf_server_set_loss(isnmf_server *s, int session, double *d_loss_sum);
 /* Queue a chunk (device F x n_frames FP32, ldv >= F).  arrival: the client's
  * timestamp on isnmf_server_clock() (negative: now).  The frames must stay
  * valid until the chunk completes. */

@@ -79,6 +79,7 @@ def _load():
         "isnmf_server_workspace_size": (sz, [i, i, i]),
         "isnmf_server_create": (i, [ctypes.POINTER(vp), i, i, i, i, sz, vp, sz, vp]),
         "isnmf_server_open": (i, [vp, vp, sz, ctypes.POINTER(i)]),
+        "isnmf_server_set_loss": (i, [vp, i, vp]),
         "isnmf_server_submit": (i, [vp, i, vp, i, i, d, ctypes.POINTER(ctypes.c_longlong)]),
         "isnmf_server_pump": (i, [vp, ctypes.POINTER(i)]),
         "isnmf_server_pending": (i, [vp, ctypes.POINTER(ctypes.c_longlong),
@@ -111,6 +112,7 @@ EXPORTED = ("isnmf_params_default", "isnmf_strerror", "isnmf_online_workspace_si
             "isnmf_multi_run", "isnmf_multi_frames_left", "isnmf_multi_destroy",
             "isnmf_autotune", "isnmf_tune_get", "isnmf_tune_set", "isnmf_tune_clear",
             "isnmf_server_workspace_size", "isnmf_server_create", "isnmf_server_open",
+            "isnmf_server_set_loss",
             "isnmf_server_submit", "isnmf_server_pump", "isnmf_server_pending",
             "isnmf_server_drain", "isnmf_server_results", "isnmf_server_stats",
             "isnmf_server_clock", "isnmf_server_destroy",
@@ -400,6 +402,19 @@ class Server:
         _check(_lib.isnmf_server_open(self._s, g._h, fp, ctypes.byref(idx)), "isnmf_server_open")
         self.sessions.append(g)
         return idx.value
+
+    def set_loss(self, session: int, loss) -> None:
+        """Accumulate the session's running loss (sum of d_IS over its served
+        chunks, FP64) into `loss`, a float64 device scalar (None: stop)."""
+        p = None
+        if loss is not None:
+            _req(loss, torch.float64, name="loss")
+            if loss.numel() != 1:
+                raise ValueError("loss must be a single float64 element")
+            p = loss.data_ptr()
+            self._keep = getattr(self, "_keep", {})
+            self._keep[int(session)] = loss
+        _check(_lib.isnmf_server_set_loss(self._s, int(session), p), "isnmf_server_set_loss")
 
     def submit(self, session: int, V: torch.Tensor, arrival: float = -1.0) -> int:
         """V: (n, F) float32 frames on the device (kept alive until done)."""

@@ -453,6 +453,19 @@ int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *s
     return ISNMF_OK;
 }
 
+int isnmf_server_set_loss(isnmf_server *s, int session, double *d_loss_sum) {
+    if (!s || session < 0 || session >= (int)s->sess.size()) return ISNMF_EINVAL;
+    const isnmf_online *h = s->sess[session].h;
+    const isnmf_params &p = *isnmf_handle_params(h);
+    const FoldArgs fa = fold_args(*isnmf_handle_dev(h), 1, p.rho, p.update_w, nullptr, d_loss_sum);
+    // on the engine stream: steps enqueued before keep the previous target
+    if (hipMemcpyAsync(s->d_fold + session, &fa, sizeof fa, hipMemcpyHostToDevice, s->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return ISNMF_EDEVICE;
+    return ISNMF_OK;
+}
+
 int isnmf_server_submit(isnmf_server *s, int session, const float *V, int ldv, int n_frames,
                         double arrival, long long *request) {
     if (!s || session < 0 || session >= (int)s->sess.size() || !V || n_frames < 1) return ISNMF_EINVAL;

@@ -88,6 +88,50 @@ def test_served_sessions_equal_alone_bitwise():
     srv.close()
 
 
+def test_served_loss_equals_alone_bitwise():
+    """Each session's running loss (isnmf_server_set_loss) is the same FP64
+    bits as the session stepped alone with loss_sum, chunk by chunk; a
+    session without a target leaves the others' sums alone."""
+    S = 12
+    data = sessions(S, seed=21)
+    say(f"served loss vs alone, {S} sessions")
+    loss_alone = []
+    for W0, prec, chunks in data:
+        g = bd.OnlineISNMF(W0, 64, precision=prec)
+        ls = torch.zeros((), dtype=torch.float64, device=DEV)
+        for c in chunks:
+            g.step(c, None, ls)
+        loss_alone.append(ls)
+    srv = bd.Server(max_sessions=S, max_per_step=S, max_frames=600, inflight=2)
+    losses = torch.zeros(S, dtype=torch.float64, device=DEV)
+    ids = []
+    for i, (W0, prec, chunks) in enumerate(data):
+        g = bd.OnlineISNMF(W0, 64, precision=prec)
+        ids.append((g, srv.open(g)))
+        if i != 3:                      # session 3 keeps no running loss
+            srv.set_loss(ids[-1][1], losses[i:i + 1])
+    rng = np.random.default_rng(5)
+    order = [i for i, (_, _, ch) in enumerate(data) for _ in ch]
+    rng.shuffle(order)
+    nxt = [0] * S
+    for k, i in enumerate(order):
+        srv.submit(ids[i][1], data[i][2][nxt[i]])
+        nxt[i] += 1
+        if k % 4 == 0:
+            srv.pump()
+    srv.drain()
+    torch.cuda.synchronize()
+    for i in range(S):
+        if i == 3:
+            assert losses[i].item() == 0.0
+        else:
+            assert loss_alone[i].item() > 0.0
+            assert torch.equal(losses[i], loss_alone[i]), (i, losses[i].item(), loss_alone[i].item())
+    with pytest.raises(bd.IsnmfError):
+        srv.set_loss(S + 5, losses[0:1])
+    srv.close()
+
+
 def test_admission_by_hbm_footprint():
     say("admission")
     W0 = torch.rand((32, 257), device=DEV) + 0.5
