@@ -97,6 +97,8 @@ def test_einval_before_any_device_work():
     assert L.isnmf_online_step(None, fake, 10, 1, None, 2, None, None, None) == bd.EINVAL
     assert L.isnmf_batch_mu(None, 10, 10, 5, fake, 10, fake, 2, 2, 1, None, None, fake, 1 << 20, None) == bd.EINVAL
     assert L.isnmf_objective(fake, 9, fake, 10, fake, 2, 10, 2, 5, 0.0, fake, fake, 1 << 20, None) == bd.EINVAL
+    # a served session's running loss needs a server (checked before any device work)
+    assert L.isnmf_server_set_loss(None, 0, fake) == bd.EINVAL
 
 
 def test_product_path_does_not_touch_the_oracle():
