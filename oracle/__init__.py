@@ -206,16 +206,19 @@ def batch_cycle(V, W, H, eps: float = 1e-12, normalize: bool = True):
 
 
 def online_pass(V, W0, b: int, iters: int = 20, eps: float = 1e-12, rho: float = 1.0,
-                normalize: bool = True, A0=None, B0=None, keep_h: bool = False):
+                normalize: bool = True, A0=None, B0=None, keep_h: bool = False,
+                update_w: bool = True):
     """Fresh-restart one-pass run over all columns of V in minibatches of b
-    (the final partial minibatch is a short step).  Returns the final
-    OnlineState (and the collected H if keep_h)."""
+    (Algorithm 1 with beta = b; the final partial minibatch is a short step).
+    update_w = False freezes W (statistics still accumulate).  Returns the
+    final OnlineState (and the collected H if keep_h)."""
     V = _f64(V)
     st = OnlineState(W0, A0, B0)
     F, N = V.shape
     Hs = []
     for s in range(0, N, b):
-        Hb, _, _ = st.step(V[:, s:s + b], iters=iters, eps=eps, rho=rho, normalize=normalize)
+        Hb, _, _ = st.step(V[:, s:s + b], iters=iters, eps=eps, rho=rho, normalize=normalize,
+                           update_w=update_w)
         if keep_h:
             Hs.append(Hb)
     if keep_h:

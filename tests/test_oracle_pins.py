@@ -225,6 +225,59 @@ def test_frozen_w_online_equals_batch_closed_form():
     assert st.t == 23
 
 
+def test_online_pass_ragged_frozen_w_equals_batch_closed_form():
+    """The one-pass driver (Algorithm 1 with beta = b over a finite set, a short
+    last minibatch): with W frozen, rho = 1 and A0 = B0 = 0 the pass's A, B are
+    eq. (3) over ALL N frames at (W0, collected H) (section 2.2, "T fixed"), the
+    collected h of each frame is its own inner fit at W0 (the minibatch
+    partition does not matter), and the loss sums d_IS over every frame.  A pass
+    that dropped or duplicated the tail, or reordered frames, fails here."""
+    F, K, N, b, I, eps = 21, 4, 29, 8, 6, 1e-9           # 8, 8, 8, then a tail of 5
+    V, W0, _ = _rand_problem(F, K, N, seed=19)
+    st, H = oracle.online_pass(V, W0, b, iters=I, eps=eps, update_w=False, keep_h=True)
+    assert st.t == N and H.shape == (K, N)
+    assert np.array_equal(st.W, W0)
+    # eq. (3) written out with numpy at (W0, H), independent of the C statistics
+    X = eps + W0 @ H
+    A = (((eps + V) / X ** 2) @ H.T) * W0 ** 2
+    B = (1.0 / X) @ H.T
+    assert _relerr(st.A, A) < 1e-13
+    assert _relerr(st.B, B) < 1e-13
+    # without the tail the statistics are measurably different
+    At = (((eps + V[:, :24]) / X[:, :24] ** 2) @ H[:, :24].T) * W0 ** 2
+    assert _relerr(st.A, At) > 1e-3
+    # each frame's h is its own fit, whatever minibatch it fell in
+    for n in (0, 7, 8, 23, 24, 28):
+        h, fl = oracle.fit_h(V[:, n], W0, iters=I, eps=eps)
+        assert fl == 0 and _relerr(H[:, n], h) < 1e-14
+    # the running loss is sum_n d_IS(eps + v_n, eps + W0 h_n)
+    assert abs(st.loss_sum - oracle.dis(V, W0 @ H, eps)) <= 1e-12 * st.loss_sum
+
+
+def test_online_pass_K1_ragged_closed_form():
+    """K = 1, eps = 0, no rescaling, minibatches of 3 with a tail of 2: within a
+    minibatch every frame is fitted at the same w, so a_t = v_t / h_t and the
+    minibatch adds sum_t 1 / w to B; w = sqrt(A / B) after each minibatch."""
+    rng = np.random.default_rng(20)
+    F, N, b, I = 11, 14, 3, 7                           # 3,3,3,3, then 2
+    V = np.asfortranarray(rng.gamma(0.8, 2.0, size=(F, N)) + 1e-2)
+    w = rng.uniform(0.5, 1.5, size=F)
+    st = oracle.online_pass(V, w[:, None], b, iters=I, eps=0.0, normalize=False)
+    A = np.zeros(F)
+    B = np.zeros(F)
+    for s in range(0, N, b):
+        cols = range(s, min(s + b, N))
+        for t in cols:
+            m = float(np.mean(V[:, t] / w))
+            A += V[:, t] / m ** (1.0 - 2.0 ** (-I))
+            B += 1.0 / w
+        w = np.sqrt(A / B)
+    assert st.t == N
+    assert _relerr(st.A[:, 0], A) < 1e-12
+    assert _relerr(st.B[:, 0], B) < 1e-12
+    assert _relerr(st.W[:, 0], w) < 1e-12
+
+
 def test_K1_online_closed_form_recursion():
     """K = 1, eps = 0, no rescaling, b = 1:  a_t = v_t / h_t and b_t = 1 / w(t-1), so
     A_f = sum_t v_ft / h_t,  B_f = sum_t 1 / w_f(t-1),  w = sqrt(A/B), with h_t from
