@@ -88,15 +88,30 @@ typedef struct {
 
 typedef struct isnmf_online isnmf_online;   /* opaque handle */
 
-/* Fill *p with the defaults above. */
+/* Fill *p with the defaults above: Algorithm 1's inputs with eps of section
+ * 2.3, rho = 1 (no forgetting) and unit-norm columns.  Host only. */
 void isnmf_params_default(isnmf_params *p);
 
-/* Message for a status code (static string, never NULL). */
+/* Message for a status code (static string, never NULL).  Not part of the
+ * method: error reporting of the interface.  Host only. */
 const char *isnmf_strerror(int status);
+
+/*
+ * Weight of the past statistics for a forgetting factor r (section 2.3,
+ * scaling past data): rho = r^(beta / N), with beta frames per update of W
+ * and N frames in the data set, so that the past is discounted by r per pass
+ * over the N frames whatever beta is; rho -> 1 as N grows, and r = 0 with
+ * beta = N gives rho = 0, the batch algorithm.  The result is the
+ * isnmf_params.rho of a handle (A <- rho*A + sum a, B <- rho*B + sum b).
+ * Host only (no device work).  ISNMF_EINVAL unless 0 <= r <= 1, beta >= 1,
+ * n_frames >= 1 and host_rho != NULL.
+ */
+int isnmf_forgetting_rho(double r, long long beta, long long n_frames, double *host_rho);
 
 /* ------------------------------------------------------------------ online */
 
-/* Bytes of device workspace an online handle needs for frames of length F,
+/* Bytes of device workspace an online handle (Algorithm 1's state W, A, B of
+ * eq. (4), O(FK), plus the minibatch buffers) needs for frames of length F,
  * K components and minibatches of at most b_max frames.  0 on bad sizes. */
 size_t isnmf_online_workspace_size(int F, int K, int b_max, const isnmf_params *p);
 
@@ -175,6 +190,7 @@ int isnmf_online_fit(isnmf_online *h, const float *Vb, int ldv, int b, float *Hb
                      double *d_loss_sum, void *stream);
 
 /*
+ * Not part of the method: measurement hooks.
  * Per-launch timing of the fit kernel with HIP events on the launch stream.
  * enable != 0 starts recording an event pair around every fit launch of this
  * handle (up to `capacity` launches; later launches are not timed);
@@ -185,39 +201,52 @@ int isnmf_online_fit(isnmf_online *h, const float *Vb, int ldv, int b, float *Hb
 int isnmf_online_set_timing(isnmf_online *h, int enable, int capacity);
 int isnmf_online_timing(isnmf_online *h, long long *host_launches, double *host_total_ms);
 
-/* Copy the state out: W (device F x K FP32, ld F) or NULL, A, B (device
- * F x K FP64) or NULL, host_t (host) or NULL.  Enqueued on `stream`. */
+/* Copy the state of Algorithm 1 out: the dictionary W and the statistics A
+ * and B of eq. (4) (the sums of the a and b terms over the frames seen, past
+ * ones weighted by rho), and the frame counter t.  W: device F x K FP32
+ * (ld F) or NULL; A, B: device F x K FP64 (ld F) or NULL; host_t: host or
+ * NULL.  A and B come out with the last column rescale applied (A/s, B*s).
+ * Enqueued on `stream`. */
 int isnmf_online_get(const isnmf_online *h, float *W, double *A, double *B,
                      long long *host_t, void *stream);
 
-/* FP64 master copy of W (device F x K, ld F).  W is kept in FP64 between
- * steps in every mode; the FP32 (or BF16/FP16) copy is rounded from it. */
+/* FP64 master copy of Algorithm 1's W = sqrt(A/B) after the column rescale
+ * (device F x K, ld F).  W is kept in FP64 between steps in every mode; the
+ * FP32 (or BF16/FP16) copy is rounded from it.  Enqueued on `stream`. */
 int isnmf_online_get_w64(const isnmf_online *h, double *W, void *stream);
 
-/* Replace the state (checkpoint restore): W device FP32 F x K (ld F) or
- * NULL to keep, A, B device FP64 or NULL to keep, t the frame counter. */
+/* Replace the state of Algorithm 1 (checkpoint restore, or the inputs W(0),
+ * A(0), B(0) of a restart): W device FP32 F x K (ld F) or NULL to keep, the
+ * eq. (4) statistics A, B device FP64 F x K (ld F) or NULL to keep, t the
+ * frame counter (>= 0).  The next step reads them as Algorithm 1 reads its
+ * state at t.  Enqueued on `stream`. */
 int isnmf_online_set(isnmf_online *h, const float *W, const double *A, const double *B,
                      long long t, void *stream);
 
-/* As isnmf_online_set for an FP64 W (device F x K, ld F). */
+/* As isnmf_online_set for Algorithm 1's W given in FP64 (device F x K,
+ * ld F). */
 int isnmf_online_set_w64(isnmf_online *h, const double *W, void *stream);
 
-/* Synchronize the handle's last stream and read the sticky device flags:
+/* Not part of the method: error reporting (the 0/0 guards of the h update,
+ * section 2.1, and of W = sqrt(A/B), Algorithm 1).
+ * Synchronize the handle's last stream and read the sticky device flags:
  * bit 0 a non-finite value in V, bit 1 a guarded 0/0 in the h update, bit 2
  * a guarded 0/0 in W = sqrt(A/B) or the rescale.  Returns ISNMF_ENONFINITE
  * when bit 0 is set, ISNMF_OK otherwise.  Clears the flags. */
 int isnmf_online_status(isnmf_online *h, int *host_flags);
 
-/* Shape / mode queries. */
+/* Not part of the method: shape / mode queries of a handle (host only). */
 int isnmf_online_info(const isnmf_online *h, int *F, int *K, int *b_max, int *kernel_used);
 
-/* Free the handle (not the workspace). Waits for the handle's last stream. */
+/* Not part of the method: free the handle (not the workspace).  Waits for
+ * the handle's last stream. */
 int isnmf_online_destroy(isnmf_online *h);
 
 /* ------------------------------------------------------------ batched form */
 
 /*
- * Many independent online streams advanced together: each step fits one
+ * Many independent online streams of Algorithm 1 advanced together (one
+ * minibatch each per step, eq. (4) summed over it): each step fits one
  * minibatch of every stream that has frames left (fresh restarts), folds it
  * into that stream's A and B and updates its W -- exactly
  * isnmf_online_step on each handle, with one fit launch per kernel variant
@@ -236,44 +265,72 @@ int isnmf_online_destroy(isnmf_online *h);
  */
 typedef struct isnmf_multi isnmf_multi;
 
+/* Not part of the method: bytes of device workspace of a plan over these
+ * handles and minibatch sizes (descriptor tables, work lists, cursors).
+ * 0 on bad arguments. */
 size_t isnmf_multi_workspace_size(isnmf_online *const *handles, int S, const int *b);
 
+/* Create the plan (see above): one stream of Algorithm 1 per handle. */
 int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
                        const float *const *V, const int *ldv, const long long *n_frames,
                        const int *b, double *d_loss, void *workspace, size_t ws_bytes,
                        void *stream);
 
-/* One step for every stream with frames left.  The handles' frame counters
- * advance on the host. */
+/* One step of Algorithm 1 (one minibatch) for every stream with frames
+ * left.  The handles' frame counters advance on the host. */
 int isnmf_multi_step(isnmf_multi *m, void *stream);
 
-/* `steps` steps; use_graph != 0 captures one step into a hipGraph on first
- * use (on a private stream) and replays it on `stream`. */
+/* `steps` steps of Algorithm 1 as isnmf_multi_step; use_graph != 0 captures
+ * one step into a hipGraph on first use (on a private stream) and replays it
+ * on `stream`. */
 int isnmf_multi_run(isnmf_multi *m, int steps, int use_graph, void *stream);
 
-/* Largest number of frames any stream has left (host bookkeeping). */
+/* Not part of the method: largest number of frames any stream has left
+ * (host bookkeeping). */
 int isnmf_multi_frames_left(const isnmf_multi *m, long long *host_max_left);
 
+/* Not part of the method: wait for the plan's streams and free it (not the
+ * handles, not the workspace). */
 int isnmf_multi_destroy(isnmf_multi *m);
 
 /* ------------------------------------------------------------- served form */
 
 /*
- * Continuous-batching engine over many online sessions (fresh restarts).
- * Sessions are registered handles whose W, A, B stay resident.  Clients
- * submit chunks of frames already on the device; each engine step takes at
- * most one pending chunk per session (oldest first, at most max_per_step
- * chunks and max_frames frames), runs one minibatch step (b = chunk length)
- * for all of them in shared launches, and keeps up to `inflight` steps
- * enqueued while new arrivals join the next one.  Per session, chunks are
- * applied in submission order, exactly as isnmf_online_step would.
+ * Continuous-batching engine over many online sessions (fresh restarts):
+ * each session follows Algorithm 1 with one minibatch per chunk (beta = the
+ * chunk length, eq. (4) summed over it), its W, A, B resident on the device.
+ * Clients submit chunks of frames already on the device; each engine step
+ * takes at most one pending chunk per resident session (oldest first, at
+ * most max_per_step chunks and max_frames frames), runs one minibatch step
+ * (b = chunk length) for all of them in shared launches, and keeps up to
+ * `inflight` steps enqueued while new arrivals join the next one.  Per
+ * session, chunks are applied in submission order, exactly as
+ * isnmf_online_step would, so a session's result does not depend on what
+ * else shares the steps.
  *
+ * Admission by HBM footprint.  A session is RESIDENT (it holds one of
+ * max_sessions rows of the device descriptor tables and its `footprint` --
+ * its workspace bytes, or any figure the caller charges -- counts against
+ * hbm_budget) or WAITING in a first-in first-out queue.  The head of the
+ * queue is admitted as soon as a row is free and its footprint fits the
+ * budget the resident sessions leave; the queue keeps its order (a large
+ * head is not overtaken).  isnmf_server_close returns a session's row and
+ * footprint once its last submitted chunk has completed, and the next
+ * isnmf_server_pump (or the close itself) admits waiting sessions into them.
+ * Chunks submitted to a waiting session queue up and are served once it is
+ * admitted.  Session states: */
+typedef enum {
+    ISNMF_SESSION_WAITING = 0,   /* opened, not yet admitted              */
+    ISNMF_SESSION_RESIDENT = 1,  /* admitted; its chunks are served       */
+    ISNMF_SESSION_CLOSING = 2,   /* closed by the caller, chunks left     */
+    ISNMF_SESSION_CLOSED = 3     /* row and footprint returned; the server
+                                    no longer touches the handle          */
+} isnmf_session_state;
+
+/*
  * workspace: device memory of isnmf_server_workspace_size() bytes (descriptor
  *   tables and work lists), 256-byte aligned, caller-owned.  The server also
  *   allocates `inflight` small pinned host buffers and events.
- * hbm_budget: admission by HBM footprint -- isnmf_server_open fails with
- *   ISNMF_ENOMEM when the session's `footprint` (its workspace bytes, or any
- *   figure the caller charges) would exceed it.
  * Sessions must use the fused kernel: an MFMA tile variant with one 64-row
  * chunk per wave and K <= 64 (F <= 516), or the BF16 16-frame tile variant
  * (cpw = -1, F <= 640, K <= 64); chunks hold 1..min(b_max, 512, max_frames)
@@ -282,12 +339,50 @@ int isnmf_multi_destroy(isnmf_multi *m);
  */
 typedef struct isnmf_server isnmf_server;
 
+/* Not part of the method: bytes of device workspace of a server with
+ * max_sessions resident sessions
+ * (the rows of its descriptor tables), max_per_step chunks per engine step and
+ * `inflight` steps in flight.  0 on bad sizes. */
 size_t isnmf_server_workspace_size(int max_sessions, int max_per_step, int inflight);
+
+/* Create the engine (see above; each session one stream of Algorithm 1).
+ * hbm_budget: bytes of session footprint the resident sessions may hold
+ * together.  The server's steps run on `stream`. */
 int isnmf_server_create(isnmf_server **out, int max_sessions, int max_per_step, int max_frames,
                         int inflight, size_t hbm_budget, void *workspace, size_t ws_bytes,
                         void *stream);
-/* Register a handle; *session receives its index. */
+
+/*
+ * Open a session on handle h (one stream of Algorithm 1): *session receives
+ * its id (ids are never reused).  The session is admitted at once when the
+ * waiting queue is empty, a row is free and the footprint fits; otherwise it
+ * waits (isnmf_server_session_state).  ISNMF_ENOMEM when footprint alone
+ * exceeds hbm_budget (it could never be admitted); ISNMF_EINVAL when h is
+ * already open on this server and not closed; ISNMF_EUNSUPPORTED for a handle
+ * whose fit variant the engine does not run.  Admission enqueues the
+ * session's descriptors on the server's stream.
+ */
 int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *session);
+
+/*
+ * Close a session (Algorithm 1's stream ends): no further chunks are
+ * accepted (isnmf_server_submit returns ISNMF_ESTATE), chunks already
+ * submitted are still served in order, and once the last of them has
+ * completed the session's row and footprint return to the engine and it
+ * becomes CLOSED; the caller may then destroy the handle and free its
+ * workspace.  Closing twice is not an error.  Never blocks.
+ */
+int isnmf_server_close(isnmf_server *s, int session);
+
+/* Not part of the method: admission bookkeeping.  *state receives the
+ * session's isnmf_session_state (host only, never blocks). */
+int isnmf_server_session_state(const isnmf_server *s, int session, int *state);
+
+/* Not part of the method: footprint charged by the resident sessions, and the
+ * numbers of resident and waiting sessions (host pointers, any may be NULL). */
+int isnmf_server_admission(const isnmf_server *s, size_t *host_used, int *host_resident,
+                           int *host_waiting);
+
 /*
  * Running loss of a session (the diagnostic of Algorithm 1's online
  * objective, eq. 1 with eps inside, section 2.3): from the next step on,
@@ -296,44 +391,76 @@ int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *s
  * and zeroes; NULL turns it off again).  The sum of one chunk is formed in the
  * same order as isnmf_online_step's loss_sum for that chunk, so a session
  * served in a mix accumulates the same bits as stepped alone chunk by chunk.
- * Synchronizes the server's stream.  ISNMF_EINVAL for a session index not
- * returned by isnmf_server_open.
+ * For a resident session, synchronizes the server's stream; for a waiting
+ * one, takes effect at admission.  ISNMF_EINVAL for a session id not
+ * returned by isnmf_server_open, ISNMF_ESTATE for a closed session.
  */
 int isnmf_server_set_loss(isnmf_server *s, int session, double *d_loss_sum);
-/* Queue a chunk (device F x n_frames FP32, ldv >= F).  arrival: the client's
- * timestamp on isnmf_server_clock() (negative: now).  The frames must stay
- * valid until the chunk completes. */
+
+/* Queue a chunk, the next minibatch of the session's stream (Algorithm 1,
+ * beta = n_frames): device F x n_frames FP32, ldv >= F.  arrival: the
+ * client's timestamp on isnmf_server_clock() (negative: now).  The frames
+ * must stay valid until the chunk completes.  ISNMF_ESTATE once the session
+ * is closed or closing. */
 int isnmf_server_submit(isnmf_server *s, int session, const float *V, int ldv, int n_frames,
                         double arrival, long long *request);
-/* Retire finished steps and enqueue new ones (never blocks on the device). */
+
+/* Retire finished steps, release sessions closed meanwhile, admit waiting
+ * sessions, and enqueue new steps (the minibatch steps of Algorithm 1 for
+ * the chunks taken).  Never blocks on the device. */
 int isnmf_server_pump(isnmf_server *s, int *launched_frames);
+
+/* Not part of the method: chunks queued (resident and waiting sessions) and
+ * chunks in flight. */
 int isnmf_server_pending(const isnmf_server *s, long long *queued, long long *inflight);
-/* Run until every submitted chunk has completed (synchronizes). */
+
+/* Pump until every submitted chunk has completed (synchronizes): every
+ * queued minibatch step of Algorithm 1 is taken.
+ * ISNMF_ESTATE when chunks remain that only waiting sessions hold and nothing
+ * is in flight: no release can admit them until the caller closes sessions. */
 int isnmf_server_drain(isnmf_server *s);
-/* Completed chunks since the last call (host arrays of max_out entries, any
- * may be NULL): request id, session, frames, arrival, launch and completion
- * times in seconds on isnmf_server_clock(). */
+
+/* Not part of the method: completed chunks since the last call (host arrays
+ * of max_out entries, any may be NULL): request id, session, frames, arrival,
+ * launch and completion times in seconds on isnmf_server_clock(). */
 int isnmf_server_results(isnmf_server *s, int max_out, long long *req, int *session,
                          int *n_frames, double *arrival, double *start, double *done, int *count);
+
+/* Not part of the method: engine steps and frames served so far. */
 int isnmf_server_stats(const isnmf_server *s, long long *steps, long long *frames);
-/* Monotonic host clock in seconds used for arrival and completion times. */
+
+/* Not part of the method: monotonic host clock in seconds used for arrival
+ * and completion times. */
 double isnmf_server_clock(void);
+
+/* Not part of the method: wait for the engine's streams and free the server
+ * (not the handles, not the workspace). */
 int isnmf_server_destroy(isnmf_server *s);
 
 /* ------------------------------------------------------------- autotuner */
 
+/* Not part of the method: bytes of device workspace isnmf_autotune needs for
+ * (F, K, b) -- a scratch online state, b synthetic frames and a W(0).  0 on
+ * bad sizes. */
+size_t isnmf_autotune_workspace_size(int F, int K, int b, const isnmf_params *p);
+
 /*
+ * Not part of the method: kernel selection for the inner fit of Algorithm 1
+ * (the h updates of section 2.1 and the final ratios).
  * Time every fused-fit kernel variant valid for (F, K, precision) on
  * synthetic frames (b per launch, `trials` launches each) and record the
  * fastest in the process-wide tuning table; handles created afterwards with
- * that shape use it.  Allocates scratch device memory itself and
- * synchronizes `stream`.  out_variant: index of the chosen variant (0 is the
- * default); out_us: its average launch time in microseconds.
+ * that shape use it.  workspace: device memory of at least
+ * isnmf_autotune_workspace_size() bytes, 256-byte aligned, caller-owned (the
+ * call allocates no device memory).  Synchronizes `stream`.  out_variant:
+ * index of the chosen variant (0 is the default); out_us: its average launch
+ * time in microseconds.
  */
 int isnmf_autotune(int F, int K, int b, const isnmf_params *p, int trials, int *out_variant,
-                   double *out_us, void *stream);
+                   double *out_us, void *workspace, size_t ws_bytes, void *stream);
 
-/* Read / set / clear the tuning table (for persisting it between processes):
+/* Not part of the method: read / set / clear the tuning table (for
+ * persisting it between processes):
  * nw = waves per workgroup, cpw = 64-row chunks per wave, wg = W read from
  * its 16-bit copies in memory instead of registers.  cpw = 0 denotes the
  * FP32 VALU variant (one frame per workgroup of nw = 8 waves) and cpw = -1
@@ -348,7 +475,7 @@ void isnmf_tune_clear(void);
 
 /* ------------------------------------------------------------------- batch */
 
-/* Bytes of device workspace isnmf_batch_mu needs. */
+/* Bytes of device workspace isnmf_batch_mu (section 2.1) needs. */
 size_t isnmf_batch_workspace_size(int F, int K, int N, const isnmf_params *p);
 
 /*
@@ -365,7 +492,7 @@ int isnmf_batch_mu(const float *V, int ldv, int F, int N, float *W, int ldw,
                    float *H, int ldh, int K, int cycles, const isnmf_params *p,
                    double *d_obj_trace, void *workspace, size_t ws_bytes, void *stream);
 
-/* Bytes of device workspace isnmf_objective needs. */
+/* Bytes of device workspace isnmf_objective (eq. (1)) needs. */
 size_t isnmf_objective_workspace_size(int F, int K, int N);
 
 /*

@@ -48,6 +48,8 @@ def _load():
     sig = {
         "isnmf_params_default": (None, [P]),
         "isnmf_strerror": (ctypes.c_char_p, [i]),
+        "isnmf_forgetting_rho": (i, [d, ctypes.c_longlong, ctypes.c_longlong,
+                                     ctypes.POINTER(d)]),
         "isnmf_online_workspace_size": (sz, [i, i, i, P]),
         "isnmf_online_init": (i, [ctypes.POINTER(vp), i, i, i, P, vp, i, vp, vp, vp, sz, vp]),
         "isnmf_online_step": (i, [vp, vp, i, i, vp, i, vp, vp, vp]),
@@ -72,13 +74,18 @@ def _load():
         "isnmf_multi_run": (i, [vp, i, i, vp]),
         "isnmf_multi_frames_left": (i, [vp, ctypes.POINTER(ctypes.c_longlong)]),
         "isnmf_multi_destroy": (i, [vp]),
-        "isnmf_autotune": (i, [i, i, i, P, i, ctypes.POINTER(i), ctypes.POINTER(d), vp]),
+        "isnmf_autotune_workspace_size": (sz, [i, i, i, P]),
+        "isnmf_autotune": (i, [i, i, i, P, i, ctypes.POINTER(i), ctypes.POINTER(d), vp, sz, vp]),
         "isnmf_tune_get": (i, [i, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
         "isnmf_tune_set": (i, [i, i, i, i, i, i]),
         "isnmf_tune_clear": (None, []),
         "isnmf_server_workspace_size": (sz, [i, i, i]),
         "isnmf_server_create": (i, [ctypes.POINTER(vp), i, i, i, i, sz, vp, sz, vp]),
         "isnmf_server_open": (i, [vp, vp, sz, ctypes.POINTER(i)]),
+        "isnmf_server_close": (i, [vp, i]),
+        "isnmf_server_session_state": (i, [vp, i, ctypes.POINTER(i)]),
+        "isnmf_server_admission": (i, [vp, ctypes.POINTER(sz), ctypes.POINTER(i),
+                                       ctypes.POINTER(i)]),
         "isnmf_server_set_loss": (i, [vp, i, vp]),
         "isnmf_server_submit": (i, [vp, i, vp, i, i, d, ctypes.POINTER(ctypes.c_longlong)]),
         "isnmf_server_pump": (i, [vp, ctypes.POINTER(i)]),
@@ -103,15 +110,18 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ("isnmf_params_default", "isnmf_strerror", "isnmf_online_workspace_size",
+EXPORTED = ("isnmf_params_default", "isnmf_strerror", "isnmf_forgetting_rho",
+            "isnmf_online_workspace_size",
             "isnmf_online_init", "isnmf_online_step", "isnmf_online_get", "isnmf_online_get_w64",
             "isnmf_online_set", "isnmf_online_set_w64", "isnmf_online_status", "isnmf_online_info",
             "isnmf_online_destroy", "isnmf_online_pass", "isnmf_online_passes", "isnmf_online_fit",
             "isnmf_online_set_timing", "isnmf_online_timing",
             "isnmf_multi_workspace_size", "isnmf_multi_create", "isnmf_multi_step",
             "isnmf_multi_run", "isnmf_multi_frames_left", "isnmf_multi_destroy",
-            "isnmf_autotune", "isnmf_tune_get", "isnmf_tune_set", "isnmf_tune_clear",
+            "isnmf_autotune_workspace_size", "isnmf_autotune", "isnmf_tune_get", "isnmf_tune_set",
+            "isnmf_tune_clear",
             "isnmf_server_workspace_size", "isnmf_server_create", "isnmf_server_open",
+            "isnmf_server_close", "isnmf_server_session_state", "isnmf_server_admission",
             "isnmf_server_set_loss",
             "isnmf_server_submit", "isnmf_server_pump", "isnmf_server_pending",
             "isnmf_server_drain", "isnmf_server_results", "isnmf_server_stats",
@@ -134,13 +144,15 @@ def _check(code: int, what: str):
 
 
 def forgetting_rho(r: float, beta: int, n_frames: int) -> float:
-    """The weight of past statistics for forgetting factor r (section 2.3):
-    rho = r^(beta / N) with beta frames per W update and N frames in the set, so
-    that rho -> 1 as N grows and runs with different beta compare at equal r.
-    r = 0 with beta = N gives rho = 0, the batch algorithm."""
-    if not 0.0 <= r <= 1.0 or beta < 1 or n_frames < 1:
+    """The weight of past statistics for forgetting factor r (section 2.3),
+    computed by the library (isnmf_forgetting_rho): rho = r^(beta / N) with
+    beta frames per W update and N frames in the set."""
+    out = ctypes.c_double()
+    code = _lib.isnmf_forgetting_rho(float(r), int(beta), int(n_frames), ctypes.byref(out))
+    if code == EINVAL:
         raise ValueError("need 0 <= r <= 1, beta >= 1, n_frames >= 1")
-    return float(r) ** (float(beta) / float(n_frames))
+    _check(code, "isnmf_forgetting_rho")
+    return out.value
 
 
 def make_params(eps=1e-12, inner_iters=20, rho=1.0, normalize=True, warm=False,
@@ -393,15 +405,40 @@ class Server:
                                         inflight, int(hbm_budget), _ptr(self.workspace), nbytes,
                                         _stream(stream)), "isnmf_server_create")
         self._s = s
-        self.sessions = []
-        self._keep = {}
+        self.sessions = {}
+        self._loss = {}     # session id -> its running-loss tensor (read by the device)
+        self._chunks = {}   # request id -> its frames (read by the device until done)
+
+    WAITING, RESIDENT, CLOSING, CLOSED = 0, 1, 2, 3
 
     def open(self, g: "OnlineISNMF", footprint=None) -> int:
+        """Open a session on handle g; it is admitted at once or waits for
+        room (state()).  footprint defaults to g's workspace bytes."""
         fp = g.workspace.numel() if footprint is None else int(footprint)
         idx = ctypes.c_int()
         _check(_lib.isnmf_server_open(self._s, g._h, fp, ctypes.byref(idx)), "isnmf_server_open")
-        self.sessions.append(g)
+        self.sessions[idx.value] = g
         return idx.value
+
+    def close_session(self, session: int) -> None:
+        """No more chunks for this session; its footprint returns to the engine
+        once its submitted chunks have completed."""
+        _check(_lib.isnmf_server_close(self._s, int(session)), "isnmf_server_close")
+
+    def state(self, session: int) -> int:
+        st = ctypes.c_int()
+        _check(_lib.isnmf_server_session_state(self._s, int(session), ctypes.byref(st)),
+               "isnmf_server_session_state")
+        if st.value == self.CLOSED:
+            self._loss.pop(int(session), None)
+        return st.value
+
+    def admission(self):
+        """(footprint bytes held by resident sessions, resident, waiting)."""
+        u, r, w = ctypes.c_size_t(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.isnmf_server_admission(self._s, ctypes.byref(u), ctypes.byref(r),
+                                           ctypes.byref(w)), "isnmf_server_admission")
+        return u.value, r.value, w.value
 
     def set_loss(self, session: int, loss) -> None:
         """Accumulate the session's running loss (sum of d_IS over its served
@@ -412,9 +449,11 @@ class Server:
             if loss.numel() != 1:
                 raise ValueError("loss must be a single float64 element")
             p = loss.data_ptr()
-            self._keep = getattr(self, "_keep", {})
-            self._keep[int(session)] = loss
         _check(_lib.isnmf_server_set_loss(self._s, int(session), p), "isnmf_server_set_loss")
+        if loss is None:
+            self._loss.pop(int(session), None)
+        else:
+            self._loss[int(session)] = loss
 
     def submit(self, session: int, V: torch.Tensor, arrival: float = -1.0) -> int:
         """V: (n, F) float32 frames on the device (kept alive until done)."""
@@ -422,7 +461,7 @@ class Server:
         r = ctypes.c_longlong()
         _check(_lib.isnmf_server_submit(self._s, int(session), _ptr(V), _ld(V), V.shape[0],
                                         float(arrival), ctypes.byref(r)), "isnmf_server_submit")
-        self._keep[r.value] = V
+        self._chunks[r.value] = V
         return r.value
 
     def pump(self) -> int:
@@ -452,7 +491,7 @@ class Server:
                                          P(don), ctypes.byref(c)), "isnmf_server_results")
         n = c.value
         for r in req[:n]:
-            self._keep.pop(int(r), None)
+            self._chunks.pop(int(r), None)
         return {"req": req[:n], "session": ses[:n], "frames": nfr[:n], "arrival": arr[:n],
                 "start": sta[:n], "done": don[:n]}
 
@@ -483,8 +522,13 @@ def autotune(F: int, K: int, b: int, precision="bf16", inner_iters=20, trials=5,
     p = make_params(inner_iters=inner_iters, precision=precision)
     v = ctypes.c_int()
     us = ctypes.c_double()
+    nbytes = _lib.isnmf_autotune_workspace_size(int(F), int(K), int(b), ctypes.byref(p))
+    if nbytes == 0:
+        raise IsnmfError(EINVAL, "isnmf_autotune_workspace_size")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=torch.cuda.current_device())
     _check(_lib.isnmf_autotune(int(F), int(K), int(b), ctypes.byref(p), int(trials),
-                               ctypes.byref(v), ctypes.byref(us), _stream(stream)), "isnmf_autotune")
+                               ctypes.byref(v), ctypes.byref(us), _ptr(ws), nbytes,
+                               _stream(stream)), "isnmf_autotune")
     return v.value, us.value
 
 
@@ -555,3 +599,4 @@ def objective(V: torch.Tensor, W: torch.Tensor, H: torch.Tensor, eps=1e-12, stre
                                 float(eps), _ptr(out), _ptr(ws), nbytes, _stream(stream)),
            "isnmf_objective")
     return out
+

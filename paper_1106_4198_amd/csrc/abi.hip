@@ -208,6 +208,14 @@ const char *isnmf_strerror(int status) {
     }
 }
 
+int isnmf_forgetting_rho(double r, long long beta, long long n_frames, double *host_rho) {
+    if (!host_rho || !(r >= 0.0 && r <= 1.0) || beta < 1 || n_frames < 1) return ISNMF_EINVAL;
+    // r^(beta/N): the past is discounted by r per pass over N frames whatever
+    // the minibatch size; pow(0, x > 0) = 0 gives the batch reading at r = 0
+    *host_rho = pow(r, (double)beta / (double)n_frames);
+    return ISNMF_OK;
+}
+
 size_t isnmf_online_workspace_size(int F, int K, int b_max, const isnmf_params *pp) {
     if (F < 1 || K < 1 || b_max < 1) return 0;
     const isnmf_params p = resolve(pp);

@@ -517,29 +517,35 @@ int isnmf_multi_destroy(isnmf_multi *m) {
 
 // ----------------------------------------------------------------- autotuner
 
-int isnmf_autotune(int F, int K, int b, const isnmf_params *pp, int trials, int *out_variant,
-                   double *out_us, void *stream) {
+size_t isnmf_autotune_workspace_size(int F, int K, int b, const isnmf_params *pp) {
     isnmf_params p;
     isnmf_params_default(&p);
     if (pp) p = *pp;
-    if (F < 1 || K < 1 || b < 1 || trials < 1) return ISNMF_EINVAL;
+    if (F < 1 || K < 1 || b < 1) return 0;
+    const size_t ows = isnmf_online_workspace_size(F, K, b, &p);
+    if (ows == 0) return 0;
+    return ows + align256(sizeof(float) * (size_t)F * b) + align256(sizeof(float) * (size_t)F * K);
+}
+
+int isnmf_autotune(int F, int K, int b, const isnmf_params *pp, int trials, int *out_variant,
+                   double *out_us, void *workspace, size_t ws_bytes, void *stream) {
+    isnmf_params p;
+    isnmf_params_default(&p);
+    if (pp) p = *pp;
+    if (F < 1 || K < 1 || b < 1 || trials < 1 || !workspace || ((uintptr_t)workspace & 255))
+        return ISNMF_EINVAL;
     if (p.precision == ISNMF_FP64) return ISNMF_EUNSUPPORTED;
     const int prec = prec_of(p);
     FitClass cand[8];
     const int nc = fit_candidates(F, K, prec, cand, 8);
     if (nc == 0) return ISNMF_EUNSUPPORTED;
+    if (ws_bytes < isnmf_autotune_workspace_size(F, K, b, &p)) return ISNMF_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
-    // a scratch stream state on the device
+    // a scratch stream state, synthetic frames and W(0), all in the caller's workspace
     const size_t wsz = isnmf_online_workspace_size(F, K, b, &p);
-    void *ws = nullptr;
-    float *V = nullptr, *W0 = nullptr;
-    if (hipMalloc(&ws, wsz) != hipSuccess) return ISNMF_ENOMEM;
-    if (hipMalloc((void **)&V, sizeof(float) * (size_t)F * b) != hipSuccess ||
-        hipMalloc((void **)&W0, sizeof(float) * (size_t)F * K) != hipSuccess) {
-        hipFree(ws);
-        hipFree(V);
-        return ISNMF_ENOMEM;
-    }
+    void *ws = workspace;
+    float *V = (float *)((char *)workspace + wsz);
+    float *W0 = (float *)((char *)V + align256(sizeof(float) * (size_t)F * b));
     const long nv = (long)F * b, nw = (long)F * K;
     fill_kernel<<<(int)((nv + 255) / 256), 256, 0, s>>>(V, nv, 0.01f, 10.f, 7u);
     fill_kernel<<<(int)((nw + 255) / 256), 256, 0, s>>>(W0, nw, 0.5f, 1.f, 11u);
@@ -576,10 +582,7 @@ int isnmf_autotune(int F, int K, int b, const isnmf_params *pp, int trials, int 
     if (h) isnmf_online_destroy(h);
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
-    hipStreamSynchronize(s);
-    hipFree(ws);
-    hipFree(V);
-    hipFree(W0);
+    if (hipStreamSynchronize(s) != hipSuccess && st == ISNMF_OK) st = ISNMF_EDEVICE;
     if (st != ISNMF_OK) return st;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -17,6 +17,14 @@
 // Each chunk's arithmetic is that of isnmf_online_step on its session with
 // b = chunk length (same kernel bodies and variant, fixed-order sums), so a
 // session's result does not depend on what else shares the step.
+//
+// Admission: a session is resident (its descriptors in a row of the device
+// tables, its footprint charged to the HBM budget) or waiting in a FIFO.
+// The head of the FIFO is admitted as soon as a table row is free and its
+// footprint fits what the resident sessions leave of the budget; closing a
+// session returns its row and footprint once its last chunk has completed,
+// and the engine admits from the FIFO on its next pump.  Chunks of a waiting
+// session queue up and are served after admission.
 #include <math.h>
 
 #include <algorithm>
@@ -137,18 +145,32 @@ double now_s() {
 struct isnmf_server {
     // configuration
     size_t budget = 0, used = 0;
-    int max_frames = 0, max_sessions = 0, max_registered = 0, inflight = 2;
+    int max_frames = 0, max_sessions = 0, inflight = 2;
     hipStream_t stream = nullptr;
-    // sessions
+    // sessions (ids are indices of `sess`, never reused)
     struct Sess {
         isnmf_online *h;
-        int prec, ldv_unused;
+        int prec;
         FitClass cls;
         int F, K;
         size_t footprint;
+        int slot = -1;                 // row of the device tables while resident
+        int state = ISNMF_SESSION_WAITING;
+        bool closing = false;          // no more submits; release when idle
+        int inflight = 0;              // chunks launched and not yet retired
+        double *loss = nullptr;        // running-loss target (set_loss)
         std::deque<long long> queue;   // pending request ids, FIFO
     };
     std::vector<Sess> sess;
+    std::vector<int> slot_owner;       // session holding each table row, or -1
+    std::vector<int> free_slots;
+    std::deque<int> admit_q;           // waiting sessions, FIFO
+    int resident = 0;
+    // host mirrors of the device tables (the source of the admission copies)
+    std::vector<FitDesc> h_fit;
+    std::vector<FoldArgs> h_fold;
+    std::vector<RescaleArgs> h_rs;
+    std::vector<int> h_upd;
     FitDesc *d_fit = nullptr;
     FoldArgs *d_fold = nullptr;
     RescaleArgs *d_rs = nullptr;
@@ -190,8 +212,74 @@ int prec_of(const isnmf_params &p) {
     return p.precision == ISNMF_BF16 ? 1 : p.precision == ISNMF_FP16 ? 2 : 0;
 }
 
-// Retire finished steps: stamp completion times, free their sessions.
-void retire(isnmf_server *s) {
+// Write session `id`'s descriptors into its table row (host mirror, then an
+// asynchronous copy on the engine stream, ahead of any step that reads it).
+bool write_row(isnmf_server *s, int id) {
+    const auto &ss = s->sess[id];
+    const int r = ss.slot;
+    const OnlineDev &d = *isnmf_handle_dev(ss.h);
+    const isnmf_params &p = *isnmf_handle_params(ss.h);
+    s->h_fit[r] = make_fit_desc(d, nullptr, d.F, 1, p.inner_iters, p.eps, 0, nullptr, d.K);
+    s->h_fold[r] = fold_args(d, 1, p.rho, p.update_w, nullptr, ss.loss);
+    RescaleArgs ra = rescale_args(d, p.normalize, 0, nullptr, d.K);
+    ra.dwpart = nullptr;   // served steps report no dW
+    s->h_rs[r] = ra;
+    s->h_upd[r] = p.update_w;
+    hipStream_t st = s->stream;
+    return hipMemcpyAsync(s->d_fit + r, &s->h_fit[r], sizeof(FitDesc), hipMemcpyHostToDevice,
+                          st) == hipSuccess &&
+           hipMemcpyAsync(s->d_fold + r, &s->h_fold[r], sizeof(FoldArgs), hipMemcpyHostToDevice,
+                          st) == hipSuccess &&
+           hipMemcpyAsync(s->d_rs + r, &s->h_rs[r], sizeof(RescaleArgs), hipMemcpyHostToDevice,
+                          st) == hipSuccess &&
+           hipMemcpyAsync(s->d_upd + r, &s->h_upd[r], sizeof(int), hipMemcpyHostToDevice, st) ==
+               hipSuccess;
+}
+
+// Admit waiting sessions in FIFO order while a row is free and the head's
+// footprint fits the budget.
+bool admit(isnmf_server *s) {
+    while (!s->admit_q.empty() && !s->free_slots.empty()) {
+        const int id = s->admit_q.front();
+        auto &ss = s->sess[id];
+        if (s->used + ss.footprint > s->budget) break;   // head-of-line: FIFO order is kept
+        s->admit_q.pop_front();
+        ss.slot = s->free_slots.back();
+        s->free_slots.pop_back();
+        s->slot_owner[ss.slot] = id;
+        s->used += ss.footprint;
+        ss.state = ss.closing ? ISNMF_SESSION_CLOSING : ISNMF_SESSION_RESIDENT;
+        ++s->resident;
+        if (!write_row(s, id)) return false;
+    }
+    return true;
+}
+
+// Return a closing session's row and footprint once nothing of it is left.
+void release_if_idle(isnmf_server *s, int id) {
+    auto &ss = s->sess[id];
+    if (!ss.closing || ss.state == ISNMF_SESSION_CLOSED || !ss.queue.empty() || ss.inflight)
+        return;
+    if (ss.slot >= 0) {
+        s->slot_owner[ss.slot] = -1;
+        s->free_slots.push_back(ss.slot);
+        s->used -= ss.footprint;
+        --s->resident;
+        ss.slot = -1;
+    } else {
+        for (auto it = s->admit_q.begin(); it != s->admit_q.end(); ++it)
+            if (*it == id) {
+                s->admit_q.erase(it);
+                break;
+            }
+    }
+    ss.state = ISNMF_SESSION_CLOSED;
+}
+
+// Retire finished steps: stamp completion times, release sessions closed
+// meanwhile and admit waiting ones into the rows and budget they free.
+bool retire(isnmf_server *s) {
+    std::vector<int> touched;
     for (auto &sl : s->slots) {
         if (!sl.busy) continue;
         if (hipEventQuery(sl.ev) != hipSuccess) continue;
@@ -201,10 +289,15 @@ void retire(isnmf_server *s) {
             q.state = 2;
             q.done = t;
             s->done_list.push_back(r);
+            auto &ss = s->sess[q.sess];
+            --ss.inflight;
+            if (ss.closing) touched.push_back(q.sess);
         }
         sl.reqs.clear();
         sl.busy = false;
     }
+    for (const int id : touched) release_if_idle(s, id);
+    return admit(s);
 }
 
 // Form and enqueue one step from the pending chunks; returns frames launched.
@@ -219,9 +312,10 @@ int launch_step(isnmf_server *s) {
         }
     }
     if (!slot) return 0;
-    // at most one chunk per session, oldest request first across sessions
+    // at most one chunk per resident session, oldest request first across sessions
     std::vector<std::pair<double, int>> cand;
-    for (int i = 0; i < (int)s->sess.size(); ++i) {
+    for (const int i : s->slot_owner) {
+        if (i < 0) continue;
         const auto &ss = s->sess[i];
         if (!ss.queue.empty()) cand.push_back({s->reqs[ss.queue.front()].arrival, i});
     }
@@ -250,8 +344,9 @@ int launch_step(isnmf_server *s) {
         auto &q = s->reqs[r];
         q.state = 1;
         q.start = t;
-        slot->host[i] = Work{pick[i], q.n, q.V, q.ldv, 0};
+        slot->host[i] = Work{ss.slot, q.n, q.V, q.ldv, 0};
         slot->reqs.push_back(r);
+        ++ss.inflight;
     }
     const int n = (int)pick.size();
     hipStream_t st = s->stream;
@@ -376,7 +471,6 @@ int isnmf_server_create(isnmf_server **out, int max_sessions, int max_per_step, 
     s->max_frames = max_frames;
     s->max_sessions = max_per_step;
     s->inflight = inflight;
-    s->max_registered = max_sessions;
     s->stream = (hipStream_t)stream;
     char *p = (char *)workspace;
     s->d_fit = (FitDesc *)p;
@@ -387,7 +481,12 @@ int isnmf_server_create(isnmf_server **out, int max_sessions, int max_per_step, 
     p += align256(sizeof(RescaleArgs) * max_sessions);
     s->d_upd = (int *)p;
     p += align256(sizeof(int) * max_sessions);
-    s->sess.reserve(max_sessions);
+    s->slot_owner.assign(max_sessions, -1);
+    for (int r = max_sessions - 1; r >= 0; --r) s->free_slots.push_back(r);   // row 0 first
+    s->h_fit.resize(max_sessions);
+    s->h_fold.resize(max_sessions);
+    s->h_rs.resize(max_sessions);
+    s->h_upd.resize(max_sessions);
     s->slots.resize(inflight);
     for (auto &sl : s->slots) {
         sl.dev = (Work *)p;
@@ -416,7 +515,6 @@ int isnmf_server_create(isnmf_server **out, int max_sessions, int max_per_step, 
 
 int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *session) {
     if (!s || !h || !session) return ISNMF_EINVAL;
-    if ((int)s->sess.size() >= s->max_registered) return ISNMF_ENOMEM;
     const isnmf_params &p = *isnmf_handle_params(h);
     if (p.h_init == ISNMF_H_WARM) return ISNMF_EINVAL;
     if (isnmf_handle_kernel(h) != ISNMF_KERNEL_FUSED) return ISNMF_EUNSUPPORTED;
@@ -425,42 +523,67 @@ int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *s
     const bool tile16 = (c.cpw == -1 || c.cpw == -2) && prec_of(p) == 1;
     if (!tile16 && (c.wg || c.cpw != 1 || (c.nw != 4 && c.nw != 8) || c.kmax > 64))
         return ISNMF_EUNSUPPORTED;
-    if (s->used + footprint > s->budget) return ISNMF_ENOMEM;   // admission by HBM footprint
-    const int idx = (int)s->sess.size();
-    FitDesc fd = make_fit_desc(d, nullptr, d.F, 1, p.inner_iters, p.eps, 0, nullptr, d.K);
-    FoldArgs fa = fold_args(d, 1, p.rho, p.update_w, nullptr, nullptr);
-    RescaleArgs ra = rescale_args(d, p.normalize, 0, nullptr, d.K);
-    ra.dwpart = nullptr;   // served steps report no dW
-    const int upd = p.update_w;
-    hipStream_t st = s->stream;
-    if (hipMemcpyAsync(s->d_fit + idx, &fd, sizeof fd, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(s->d_fold + idx, &fa, sizeof fa, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(s->d_rs + idx, &ra, sizeof ra, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(s->d_upd + idx, &upd, sizeof upd, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return ISNMF_EDEVICE;
+    if (footprint > s->budget) return ISNMF_ENOMEM;   // could never be admitted
+    for (const auto &o : s->sess)
+        if (o.h == h && o.state != ISNMF_SESSION_CLOSED) return ISNMF_EINVAL;   // already open
     isnmf_server::Sess ss;
     ss.h = h;
     ss.prec = prec_of(p);
-    ss.ldv_unused = 0;
     ss.cls = c;
     ss.F = d.F;
     ss.K = d.K;
     ss.footprint = footprint;
-    s->sess.push_back(ss);
-    s->used += footprint;
-    *session = idx;
+    const int id = (int)s->sess.size();
+    try {
+        s->sess.push_back(ss);
+        s->admit_q.push_back(id);
+    } catch (...) {
+        if ((int)s->sess.size() > id) s->sess.pop_back();
+        return ISNMF_ENOMEM;
+    }
+    if (!admit(s)) return ISNMF_EDEVICE;
+    *session = id;
+    return ISNMF_OK;
+}
+
+int isnmf_server_close(isnmf_server *s, int session) {
+    if (!s || session < 0 || session >= (int)s->sess.size()) return ISNMF_EINVAL;
+    auto &ss = s->sess[session];
+    if (ss.closing) return ISNMF_OK;
+    ss.closing = true;
+    if (ss.state == ISNMF_SESSION_RESIDENT) ss.state = ISNMF_SESSION_CLOSING;
+    release_if_idle(s, session);
+    return admit(s) ? ISNMF_OK : ISNMF_EDEVICE;
+}
+
+int isnmf_server_session_state(const isnmf_server *s, int session, int *state) {
+    if (!s || !state || session < 0 || session >= (int)s->sess.size()) return ISNMF_EINVAL;
+    const auto &ss = s->sess[session];
+    *state = (ss.closing && ss.state == ISNMF_SESSION_WAITING) ? ISNMF_SESSION_CLOSING : ss.state;
+    return ISNMF_OK;
+}
+
+int isnmf_server_admission(const isnmf_server *s, size_t *host_used, int *host_resident,
+                           int *host_waiting) {
+    if (!s) return ISNMF_EINVAL;
+    if (host_used) *host_used = s->used;
+    if (host_resident) *host_resident = s->resident;
+    if (host_waiting) *host_waiting = (int)s->admit_q.size();
     return ISNMF_OK;
 }
 
 int isnmf_server_set_loss(isnmf_server *s, int session, double *d_loss_sum) {
     if (!s || session < 0 || session >= (int)s->sess.size()) return ISNMF_EINVAL;
-    const isnmf_online *h = s->sess[session].h;
-    const isnmf_params &p = *isnmf_handle_params(h);
-    const FoldArgs fa = fold_args(*isnmf_handle_dev(h), 1, p.rho, p.update_w, nullptr, d_loss_sum);
+    auto &ss = s->sess[session];
+    if (ss.state == ISNMF_SESSION_CLOSED) return ISNMF_ESTATE;
+    ss.loss = d_loss_sum;
+    if (ss.slot < 0) return ISNMF_OK;   // waiting: written at admission
+    const isnmf_params &p = *isnmf_handle_params(ss.h);
+    const int r = ss.slot;
+    s->h_fold[r] = fold_args(*isnmf_handle_dev(ss.h), 1, p.rho, p.update_w, nullptr, d_loss_sum);
     // on the engine stream: steps enqueued before keep the previous target
-    if (hipMemcpyAsync(s->d_fold + session, &fa, sizeof fa, hipMemcpyHostToDevice, s->stream) !=
-            hipSuccess ||
+    if (hipMemcpyAsync(s->d_fold + r, &s->h_fold[r], sizeof(FoldArgs), hipMemcpyHostToDevice,
+                       s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return ISNMF_EDEVICE;
     return ISNMF_OK;
@@ -469,7 +592,8 @@ int isnmf_server_set_loss(isnmf_server *s, int session, double *d_loss_sum) {
 int isnmf_server_submit(isnmf_server *s, int session, const float *V, int ldv, int n_frames,
                         double arrival, long long *request) {
     if (!s || session < 0 || session >= (int)s->sess.size() || !V || n_frames < 1) return ISNMF_EINVAL;
-    const auto &ss = s->sess[session];
+    auto &ss = s->sess[session];
+    if (ss.closing) return ISNMF_ESTATE;
     const OnlineDev &d = *isnmf_handle_dev(ss.h);
     if (ldv < d.F || n_frames > d.b_max || n_frames > 512 || n_frames > s->max_frames)
         return ISNMF_EINVAL;
@@ -481,16 +605,19 @@ int isnmf_server_submit(isnmf_server *s, int session, const float *V, int ldv, i
     q.arrival = arrival < 0 ? now_s() : arrival;
     q.start = q.done = 0.0;
     q.state = 0;
-    s->reqs.push_back(q);
-    const long long id = (long long)s->reqs.size() - 1;
-    s->sess[session].queue.push_back(id);
-    if (request) *request = id;
+    try {
+        s->reqs.push_back(q);
+        ss.queue.push_back((long long)s->reqs.size() - 1);
+    } catch (...) {
+        return ISNMF_ENOMEM;
+    }
+    if (request) *request = (long long)s->reqs.size() - 1;
     return ISNMF_OK;
 }
 
 int isnmf_server_pump(isnmf_server *s, int *launched_frames) {
     if (!s) return ISNMF_EINVAL;
-    retire(s);
+    if (!retire(s)) return ISNMF_EDEVICE;
     int total = 0;
     for (;;) {
         const int f = launch_step(s);
@@ -519,6 +646,9 @@ int isnmf_server_drain(isnmf_server *s) {
         long long q = 0, f = 0;
         isnmf_server_pending(s, &q, &f);
         if (q == 0 && f == 0) return ISNMF_OK;
+        // nothing in flight after a pump: what is queued belongs to waiting
+        // sessions that no release can admit until the caller closes some
+        if (f == 0) return ISNMF_ESTATE;
         if (hipStreamSynchronize(s->stream) != hipSuccess) return ISNMF_EDEVICE;
     }
 }

@@ -125,3 +125,83 @@ def test_forgetting_rho_follows_section_2_3():
         assert rho ** (10**5 / beta) == pytest.approx(0.7, rel=1e-9)
     with pytest.raises(ValueError):
         binding.forgetting_rho(1.5, 10, 10)
+
+
+# a citation of the paper, or an interface entry marked as not part of the method
+CITE = re.compile(r"section \d|eq\. ?\(?\d|Algorithm 1|Not part of the method", re.I)
+
+
+def _entries_with_comments():
+    """(function name, the comment block directly above its declaration).
+    Declarations that follow one another with no blank line share the
+    comment above the first of them."""
+    lines = open(HEADER).read().split("\n")
+    out, in_comment = [], False
+    for i, ln in enumerate(lines):
+        starts_comment = ln.lstrip().startswith("/*")
+        if not in_comment and not starts_comment:
+            m = re.match(r"^\S.*?\b(isnmf_[a-z0-9_]+)\s*\(", ln)
+            if m:
+                j, comment = i - 1, ""
+                while j >= 0 and lines[j].strip():
+                    if lines[j].rstrip().endswith("*/"):
+                        k = j
+                        while "/*" not in lines[k]:
+                            k -= 1
+                        comment = "\n".join(lines[k:j + 1])
+                        break
+                    j -= 1
+                out.append((m.group(1), comment))
+        if "/*" in ln and "*/" not in ln[ln.index("/*"):]:
+            in_comment = True
+        if in_comment and "*/" in ln:
+            in_comment = False
+    return out
+
+
+def test_every_header_entry_cites_its_passage():
+    """Each declared entry point has a comment that cites the passage of the
+    paper defining its operation (section, equation or Algorithm 1), or says
+    it is not part of the method (interface bookkeeping)."""
+    entries = _entries_with_comments()
+    assert len({n for n, _ in entries}) == len(_declared())
+    flat = [(n, re.sub(r"\s*\n\s*\*?\s*", " ", c)) for n, c in entries]
+    missing = [n for n, c in flat if not CITE.search(c)]
+    assert not missing, missing
+
+
+def test_binding_holds_no_arithmetic_of_the_method():
+    """The Python binding only marshals arguments: no power, exponential,
+    logarithm, square root or division on values (sizes aside), no math or
+    numpy arithmetic module calls."""
+    import ast
+    src = open(os.path.join(ROOT, "paper_1106_4198_amd", "binding.py")).read()
+    tree = ast.parse(src)
+    bad = []
+    for node in ast.walk(tree):
+        if isinstance(node, ast.BinOp) and isinstance(node.op, (ast.Pow, ast.Div)):
+            bad.append(ast.unparse(node))
+        if isinstance(node, (ast.Import, ast.ImportFrom)):
+            names = [a.name for a in node.names] + [getattr(node, "module", None) or ""]
+            if any(n in ("math", "cmath") for n in names):
+                bad.append("import math")
+        if isinstance(node, ast.Attribute) and isinstance(node.value, ast.Name) and \
+                node.value.id in ("np", "numpy", "math", "torch") and \
+                node.attr in ("exp", "log", "sqrt", "power", "pow", "log2", "log1p", "expm1"):
+            bad.append(ast.unparse(node))
+    assert not bad, bad
+
+
+def test_forgetting_rho_is_a_library_call():
+    """rho = r^(beta/N) (section 2.3) is computed by the library (a host-only
+    call); the binding forwards to it."""
+    from paper_1106_4198_amd import binding as bd
+    r = ctypes.c_double()
+    L = bd.lib()
+    assert L.isnmf_forgetting_rho(0.7, 1000, 1000, ctypes.byref(r)) == bd.OK
+    assert r.value == 0.7
+    assert L.isnmf_forgetting_rho(0.7, 10, 0, ctypes.byref(r)) == bd.EINVAL
+    assert L.isnmf_forgetting_rho(-0.1, 10, 10, ctypes.byref(r)) == bd.EINVAL
+    assert L.isnmf_forgetting_rho(0.5, 0, 10, ctypes.byref(r)) == bd.EINVAL
+    assert L.isnmf_forgetting_rho(0.5, 1, 10, None) == bd.EINVAL
+    assert bd.forgetting_rho(0.25, 2, 4) == 0.5

@@ -133,18 +133,160 @@ def test_served_loss_equals_alone_bitwise():
 
 
 def test_admission_by_hbm_footprint():
+    """A session whose footprint alone exceeds the budget is refused; one that
+    does not fit beside the resident ones waits, and is admitted when a
+    resident session closes."""
     say("admission")
     W0 = torch.rand((32, 257), device=DEV) + 0.5
     g1 = bd.OnlineISNMF(W0, 64, precision="bf16")
     g2 = bd.OnlineISNMF(W0, 64, precision="bf16")
     fp = g1.workspace.numel()
     srv = bd.Server(max_sessions=4, max_per_step=4, max_frames=256, hbm_budget=fp + fp // 2)
-    srv.open(g1)
+    s1 = srv.open(g1)
+    s2 = srv.open(g2)
+    assert srv.state(s1) == srv.RESIDENT and srv.state(s2) == srv.WAITING
+    assert srv.admission() == (fp, 1, 1)
     with pytest.raises(bd.IsnmfError) as ei:
-        srv.open(g2)
+        srv.open(bd.OnlineISNMF(W0, 64, precision="bf16"), footprint=2 * fp)
     assert ei.value.code == bd.ENOMEM
+    with pytest.raises(bd.IsnmfError) as ei:
+        srv.open(g1)                       # already open
+    assert ei.value.code == bd.EINVAL
     with pytest.raises(bd.IsnmfError):
-        srv.submit(0, torch.rand((300, 257), device=DEV))   # above max_frames
+        srv.submit(s1, torch.rand((300, 257), device=DEV))   # above max_frames
+    srv.close_session(s1)                  # idle: released at once, s2 admitted
+    assert srv.state(s1) == srv.CLOSED and srv.state(s2) == srv.RESIDENT
+    assert srv.admission() == (fp, 1, 0)
+    with pytest.raises(bd.IsnmfError) as ei:
+        srv.submit(s1, torch.rand((8, 257), device=DEV))
+    assert ei.value.code == bd.ESTATE
+    srv.close()
+
+
+def _admission_mix(budget_sessions, S, seed, max_sessions):
+    data = sessions(S, seed=seed)
+    alone = []
+    for W0, prec, chunks in data:
+        g = bd.OnlineISNMF(W0, 64, precision=prec)
+        ls = torch.zeros((), dtype=torch.float64, device=DEV)
+        for c in chunks:
+            g.step(c, None, ls)
+        alone.append((g, ls))
+    fp = max(bd.OnlineISNMF(W0, 64, precision=prec).workspace.numel() for W0, prec, _ in data)
+    budget = budget_sessions * fp
+    srv = bd.Server(max_sessions=max_sessions, max_per_step=S, max_frames=600, inflight=2,
+                    hbm_budget=budget)
+    served, losses = [], torch.zeros(S, dtype=torch.float64, device=DEV)
+    for i, (W0, prec, chunks) in enumerate(data):
+        g = bd.OnlineISNMF(W0, 64, precision=prec)
+        sid = srv.open(g, footprint=fp)
+        srv.set_loss(sid, losses[i:i + 1])
+        served.append((g, sid))
+    assert srv.admission()[1] == min(budget_sessions, max_sessions)
+    assert srv.admission()[2] == S - min(budget_sessions, max_sessions)
+    # every chunk submitted up front; each session closed after its last chunk
+    rng = np.random.default_rng(seed + 1)
+    order = [i for i, (_, _, ch) in enumerate(data) for _ in ch]
+    rng.shuffle(order)
+    nxt = [0] * S
+    peak = 0
+    for k, i in enumerate(order):
+        srv.submit(served[i][1], data[i][2][nxt[i]])
+        nxt[i] += 1
+        if nxt[i] == len(data[i][2]):
+            srv.close_session(served[i][1])
+        if k % 3 == 0:
+            srv.pump()
+        used, res, _ = srv.admission()
+        assert used <= budget and res <= max_sessions
+        peak = max(peak, res)
+    srv.drain()
+    assert all(srv.state(sid) == srv.CLOSED for _, sid in served)
+    assert srv.admission() == (0, 0, 0)
+    res = srv.results()
+    assert len(res["req"]) == len(order)
+    torch.cuda.synchronize()
+    for i, ((ga, la), (gs, _)) in enumerate(zip(alone, served)):
+        _, Aa, Ba, ta = ga.get()
+        _, As, Bs, ts = gs.get()
+        assert ta == ts
+        assert torch.equal(ga.get_w64(), gs.get_w64()), i
+        assert torch.equal(Aa, As) and torch.equal(Ba, Bs), i
+        assert torch.equal(losses[i], la), i
+    srv.close()
+    return peak
+
+
+@pytest.mark.parametrize("budget_sessions,max_sessions", [(2, 16), (5, 3)])
+def test_admission_queue_serves_every_session_bitwise(budget_sessions, max_sessions):
+    """A budget (or a table) smaller than the sessions forces queueing: sessions
+    wait in order, are admitted as others close, and each ends bitwise equal to
+    the same session stepped alone, running loss included."""
+    say(f"admission queue: budget {budget_sessions} sessions, {max_sessions} rows")
+    peak = _admission_mix(budget_sessions, 14, seed=41 + budget_sessions, max_sessions=max_sessions)
+    assert peak <= min(budget_sessions, max_sessions)
+
+
+def test_drain_reports_sessions_that_cannot_be_admitted():
+    """With the budget held by an open, idle session, a waiting session's
+    chunks cannot run: drain says so instead of spinning, and serves them once
+    the holder closes."""
+    say("drain with a blocked queue")
+    W0 = torch.rand((32, 257), device=DEV) + 0.5
+    g1 = bd.OnlineISNMF(W0, 64, precision="bf16")
+    g2 = bd.OnlineISNMF(W0, 64, precision="bf16")
+    fp = g1.workspace.numel()
+    srv = bd.Server(max_sessions=4, max_per_step=4, max_frames=256, hbm_budget=fp)
+    s1, s2 = srv.open(g1), srv.open(g2)
+    V = torch.rand((16, 257), device=DEV) + 0.1
+    srv.submit(s2, V)
+    with pytest.raises(bd.IsnmfError) as ei:
+        srv.drain()
+    assert ei.value.code == bd.ESTATE
+    srv.close_session(s1)
+    srv.drain()
+    assert srv.state(s2) == srv.RESIDENT
+    assert len(srv.results()["req"]) == 1
+    srv.close()
+
+
+def test_server_keeps_chunks_and_loss_targets_alive():
+    """The binding keeps submitted frames and running-loss targets alive on
+    its own (by request id and by session id, separately): with the caller's
+    references dropped and set_loss interleaved with submits, every session
+    still ends bitwise equal to the session stepped alone."""
+    say("server keep-alive")
+    S = 6
+    data = sessions(S, seed=77)
+    alone = []
+    for W0, prec, chunks in data:
+        g = bd.OnlineISNMF(W0, 64, precision=prec)
+        ls = torch.zeros((), dtype=torch.float64, device=DEV)
+        for c in chunks:
+            g.step(c, None, ls)
+        alone.append((g, ls.item()))
+    srv = bd.Server(max_sessions=S, max_per_step=S, max_frames=600, inflight=2)
+    served = []
+    for W0, prec, _ in data:
+        g = bd.OnlineISNMF(W0, 64, precision=prec)
+        served.append((g, srv.open(g)))
+    order = [i for i, (_, _, ch) in enumerate(data) for _ in ch]
+    nxt = [0] * S
+    for k, i in enumerate(order):
+        srv.submit(served[i][1], data[i][2][nxt[i]].clone())   # caller keeps no reference
+        nxt[i] += 1
+        if nxt[i] == 1:
+            srv.set_loss(served[i][1], torch.zeros((1,), dtype=torch.float64, device=DEV))
+    data = None
+    import gc
+    gc.collect()
+    for _ in range(4):                       # churn the caching allocator
+        torch.rand((1 << 20,), device=DEV).mul_(2.0)
+    srv.drain()
+    torch.cuda.synchronize()
+    for i, ((ga, la), (gs, sid)) in enumerate(zip(alone, served)):
+        assert torch.equal(ga.get_w64(), gs.get_w64()), i
+        assert srv._loss[sid].item() == la, i
     srv.close()
 
 
