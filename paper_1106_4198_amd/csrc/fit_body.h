@@ -21,8 +21,11 @@
 // FP32 (PREC 0) runs v_mfma_f32_4x4x1_16b (one contraction step per
 // instruction); the 16-bit forms (PREC 1 = BF16, 2 = FP16) run
 // v_mfma_f32_4x4x4_16b (four steps) on W * 2^s and h * 2^-s (s = round(log2
-// F), exact power-of-two scales so W h is unchanged and FP16 keeps its range);
-// accumulation is FP32 throughout.  W stays in registers in both operand
+// F), exact power-of-two scales so W h is unchanged); accumulation is FP32
+// throughout.  FP16 also scales each frame's h operand by a power of two that
+// brings its largest entry to [2^14, 2^15) at every update, undone on the FP32
+// model values, so the operand keeps its range whatever the frame's amplitude
+// (h grows with the amplitude of v, section 2.1's scale invariance).  W stays in registers in both operand
 // layouts (WG = false) or, for shapes too large for the register file, is
 // read from its 16-bit row- and column-major copies in HBM/L2 (WG = true).
 // The per-wave num/den partials meet in LDS once per iteration; every wave then
@@ -78,11 +81,13 @@ __device__ inline float max_over_quads(float v) {
     return v;
 }
 
-// 2^(14 - e) for m in [2^e, 2^(e+1)): maps m into [2^14, 2^15).  1 for m = 0.
+// 2^(14 - e) for m in [2^e, 2^(e+1)): maps m into [2^14, 2^15).  1 for m = 0;
+// the exponent is held to [-100, 100] so the scale and its inverse stay
+// normal FP32 numbers.
 __device__ inline float pow2_scale(float m) {
     if (!(m > 0.f) || !isfinite(m)) return 1.f;
     const int e = (int)((__float_as_uint(m) >> 23) & 0xff) - 127;
-    return ldexpf(1.f, 14 - e);
+    return ldexpf(1.f, max(-100, min(100, 14 - e)));
 }
 
 // Scheduling fence: operand loads issued before it stay ahead of the MFMAs
@@ -213,8 +218,21 @@ __device__ __forceinline__ void fit_body(const FitDesc &a, int tile) {
             if (k < K) v = (a.warm && fvalid) ? a.Hb[(size_t)fr * a.ldh + k] : 1.f;
             hu[h][m] = v;
         }
-    // the X operand copy of h (FP32, or 16-bit scaled by hscale)
+    // the X operand copy of h (FP32, or 16-bit scaled by hscale; FP16 also by
+    // the frame's power of two hsc, whose inverse hinv the model applies)
+    float hinv = 1.f;
     auto store_h = [&]() {
+        float hsc = a.hscale;
+        if constexpr (PREC == 2) {
+            float m = 0.f;
+#pragma unroll
+            for (int h = 0; h < KH; ++h)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) m = fmaxf(m, hu[h][i]);
+            const float p = pow2_scale(max_over_quads(m) * a.hscale);
+            hsc = a.hscale * p;
+            hinv = 1.f / p;   // exact: a power of two
+        }
 #pragma unroll
         for (int h = 0; h < KH; ++h) {
             const int k0 = 64 * h + 4 * q;
@@ -224,8 +242,7 @@ __device__ __forceinline__ void fit_body(const FitDesc &a, int tile) {
                         floatx4{hu[h][0], hu[h][1], hu[h][2], hu[h][3]};
                 else
                     *reinterpret_cast<v4h *>(&hs16[w][n][k0]) =
-                        pack4<PREC>(hu[h][0] * a.hscale, hu[h][1] * a.hscale, hu[h][2] * a.hscale,
-                                    hu[h][3] * a.hscale);
+                        pack4<PREC>(hu[h][0] * hsc, hu[h][1] * hsc, hu[h][2] * hsc, hu[h][3] * hsc);
             }
         }
     };
@@ -284,8 +301,13 @@ __device__ __forceinline__ void fit_body(const FitDesc &a, int tile) {
                     x0 = mfma16b<PREC>(wa, hp[g % (D + 1)], x0);
             }
         }
+        if constexpr (PREC == 2) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) xv[i] = eps + (x0[i] + x1[i]);
+            for (int i = 0; i < 4; ++i) xv[i] = eps + (x0[i] + x1[i]) * hinv;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xv[i] = eps + (x0[i] + x1[i]);
+        }
     };
     // tail row t on the VALU: x for frame fr, identical in the 16 lanes of fr
     auto tail_model = [&](int t) {

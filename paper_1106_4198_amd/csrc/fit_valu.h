@@ -216,7 +216,7 @@ __device__ inline void body(const FitDesc &a, int fr) {
             const float ir = __builtin_amdgcn_rcpf(xs);
             a.R1[(size_t)fr * a.FR + f] = ir;
             a.R2[(size_t)fr * a.FR + f] = es * ir * ir;
-            lsum += double(dis_term32(es, ir));
+            lsum += dis_term(double(es), double(xs));   // FP64 term, as the objective
         }
     };
     finish_row(0);

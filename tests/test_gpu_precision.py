@@ -147,3 +147,42 @@ def test_pass_accuracy_matches_stated_tolerance(precision):
     orf = oracle.objective(V[:, ::97].astype(np.float64), st.W, Hr)
     print(f"[precision] {precision} final objective rel {abs(og - orf) / orf:.2e}")
     assert abs(og - orf) <= 1e-3 * orf
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+@pytest.mark.parametrize("scale_exp", [-20, 20])
+def test_step_is_amplitude_invariant(precision, scale_exp):
+    """IS-NMF's fitted h scales with the frames' amplitude (section 2.1: the
+    divergence is scale invariant, so h follows v).  The 16-bit forms keep
+    their products in range whatever the amplitude: frames 2^-20 and 2^20
+    times the generator's still meet the precision form's bounds against the
+    FP64 oracle, which takes the same scaled frames."""
+    F, K, b = 513, 50, 64
+    say(f"amplitude {precision} 2^{scale_exp}")
+    V, W0 = synth.problem(F, K, 3 * b, seed=12)
+    V = (V.astype(np.float64) * 2.0 ** scale_exp).astype(np.float32)   # exact: a power of two
+    st = oracle.OnlineState(W0.astype(np.float64))
+    st.step(V[:, :b].astype(np.float64), iters=20)
+    st.step(V[:, b:2 * b].astype(np.float64), iters=20)
+    bd.tune_clear()
+    g = bd.OnlineISNMF(to_gpu_kf(st.W, np.float32, torch), b, precision=precision,
+                       A0=to_gpu_kf(st.A, np.float64, torch), B0=to_gpu_kf(st.B, np.float64, torch))
+    assert g.kernel_used == "fused"
+    g.set_w64(to_gpu_kf(st.W, np.float64, torch))
+    Vb = V[:, 2 * b:3 * b]
+    loss = torch.zeros((), dtype=torch.float64, device=DEV)
+    H = torch.zeros((b, K), dtype=torch.float32, device=DEV)
+    g.step(torch.from_numpy(np.ascontiguousarray(Vb.T)).to(DEV), H, loss)
+    Hr, _, _ = st.step(Vb.astype(np.float64), iters=20)
+    eW = rel_fro(from_gpu_kf(g.get_w64()), st.W)
+    _, A, B, _ = g.get()
+    eA = rel_fro(from_gpu_kf(A), st.A)
+    eB = rel_fro(from_gpu_kf(B), st.B)
+    eH = rel_fro(H.cpu().double().numpy().T, Hr)
+    el = abs(loss.item() - st.last_loss) / st.last_loss
+    print(f"[amplitude] {precision} 2^{scale_exp}: W {eW:.2e} A {eA:.2e} B {eB:.2e} H {eH:.2e} "
+          f"loss {el:.2e}")
+    assert np.isfinite(H.cpu().numpy()).all()
+    assert eW < 2e-2 and eA < 2e-2 and eB < 2e-2 and eH < 5e-2
+    assert el < 1e-3
+    assert g.status() == 0
