@@ -84,13 +84,27 @@ def cpu_threads() -> int:
     return max(1, min(16, n))
 
 
-CHECKPOINTS = (1, 10, 100, 1000)   # minibatch steps at which the forms' errors are reported
+# minibatch steps at which the forms' errors are reported; 7813 is the end of
+# the pass over 10^6 frames (7812 full minibatches and one of 64 frames)
+CHECKPOINTS = (1, 10, 100, 1000, 7813)
 
 
-def cpu_baseline(V, W0, target_s: float, snaps=None):
-    """The FP64 oracle on the host cores over a bounded prefix of the stream.
-    snaps (a dict, optional) receives the oracle's (W, A, B, loss sum) after
-    each step count in CHECKPOINTS that the prefix reaches."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(V, W0, target_s: float, snaps=None, accuracy_steps: int = 0):
+    """The FP64 oracle on the host cores over a bounded prefix of the stream
+    (the timed sample).  With snaps (a dict), the same oracle run continues,
+    untimed, to accuracy_steps minibatches, and snaps receives its (W, A, B,
+    loss sum) after each step count in CHECKPOINTS it reaches."""
     import numpy as np
     import oracle
 
@@ -103,14 +117,29 @@ def cpu_baseline(V, W0, target_s: float, snaps=None):
     steps = max(2, min(2048, int(target_s / max(one, 1e-3))))
     Vs = V[:, :steps * B].astype(np.float64)
     st = oracle.OnlineState(W0.astype(np.float64))
+
+    def snap(s):
+        if snaps is not None and s in CHECKPOINTS:
+            snaps[s] = (st.W.copy(), st.A.copy(), st.B.copy(), st.loss_sum)
+
     t0 = time.perf_counter()
     for s in range(steps):
         st.step(Vs[:, s * B:(s + 1) * B], iters=ITERS)
-        if snaps is not None and s + 1 in CHECKPOINTS:
-            snaps[s + 1] = (st.W.copy(), st.A.copy(), st.B.copy(), st.loss_sum)
+        snap(s + 1)
     dt = time.perf_counter() - t0
+    del Vs
+    if snaps is not None:
+        last = min(accuracy_steps, (V.shape[1] + B - 1) // B)
+        t1 = time.perf_counter()
+        for s in range(steps, last):
+            st.step(V[:, s * B:(s + 1) * B].astype(np.float64), iters=ITERS)
+            snap(s + 1)
+        if last > steps:
+            print(f"[bench] oracle continued to minibatch {last} for the accuracy checkpoints "
+                  f"({time.perf_counter() - t1:.1f} s, untimed)", file=sys.stderr, flush=True)
     oracle.set_threads(1)
     return {"value": steps * B / dt, "unit": "frames/s", "cores": nt, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"first {steps} minibatches ({steps * B} frames) of the same stream, "
                       f"F={F} K={K} b={B} I={ITERS}, FP64, {dt:.1f} s"}
 
@@ -262,6 +291,38 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0):
     return out
 
 
+def bench_batch_mu(bd, torch, np, Vt, Wt, N, cycles):
+    """Batch MU (section 2.1) over the first N frames from W(0), H = 1, with the
+    objective of eq. (1) after every cycle.  Algorithmic work per cycle: the
+    H update (W H and the pair W^T r2, W^T r1), the statistics of eq. (3) at
+    the new H (W H again and the rank-N products) and the objective's W H:
+    7 F K N multiply-adds."""
+    V = Vt[:N]
+
+    def fresh():
+        return Wt.clone(), torch.ones((N, K), dtype=torch.float32, device=Vt.device)
+
+    W, H = fresh()
+    bd.batch_mu(V, W, H, 1)                         # warm-up (and workspace allocation)
+    torch.cuda.synchronize()
+    W, H = fresh()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    tr = bd.batch_mu(V, W, H, cycles)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    tr = tr.cpu().numpy()
+    flops = 2.0 * 7 * F * K * N * cycles
+    return {"value": cycles / (ms / 1e3), "unit": "cycles/s", "frames": N, "cycles": cycles,
+            "ms_per_cycle": ms / cycles, "frame_cycles_per_s": N * cycles / (ms / 1e3),
+            "achieved_tflops": flops / (ms / 1e3) / 1e12,
+            "frac_fp32_peak": flops / (ms / 1e3) / PEAK_FP32_MFMA,
+            "objective_per_entry": [float(tr[0]) / F, float(tr[-1]) / F],
+            "monotone": bool(np.all(np.diff(tr) <= 1e-6 * tr[:-1]))}
+
+
 def bench_multipass(bd, torch, np, Vt, Wt, N, passes, seed):
     """Warm-restart passes over a finite set of N frames (section 2.3): H of
     all N frames resident, each pass in its own seeded random order, FP32
@@ -408,6 +469,11 @@ def main() -> int:
     ap.add_argument("--plain-steps", type=int, default=100)
     ap.add_argument("--form-steps", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--accuracy-steps", type=int, default=CHECKPOINTS[-1],
+                    help="minibatches the oracle runs for the accuracy checkpoints "
+                         "(default: the whole pass; the oracle part is untimed)")
+    ap.add_argument("--batch-mu-frames", type=int, default=100_000)
+    ap.add_argument("--batch-mu-cycles", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=2011)
     ap.add_argument("--batch-streams", type=int, default=256)
@@ -544,6 +610,9 @@ def main() -> int:
     plain_fps = p_steps * B / (e0.elapsed_time(e1) / 1e3)
     gp.close()
 
+    forms["batch_mu"] = bench_batch_mu(bd, torch, np, Vt, Wt, min(N, args.batch_mu_frames),
+                                       args.batch_mu_cycles)
+    print(f"[bench] batch MU: {forms['batch_mu']}", file=sys.stderr, flush=True)
     forms["multipass"] = bench_multipass(bd, torch, np, Vt, Wt, min(N, 65536), 3, args.seed + 7)
     print(f"[bench] multipass: {forms['multipass']['value']:.4g} frames/s", file=sys.stderr,
           flush=True)
@@ -595,7 +664,7 @@ def main() -> int:
     }
     if not args.no_cpu:
         snaps = {}
-        out["cpu_baseline"] = cpu_baseline(V, W0, args.cpu_seconds, snaps)
+        out["cpu_baseline"] = cpu_baseline(V, W0, args.cpu_seconds, snaps, args.accuracy_steps)
         out["accuracy"] = form_accuracy(bd, torch, np, Vt, Wt, snaps, (nw, cpw, wg))
         print(f"[bench] accuracy vs the FP64 oracle: {out['accuracy']}", file=sys.stderr,
               flush=True)

@@ -347,6 +347,39 @@ def test_batch_mu_matches_oracle(precision, kernel, tol):
     assert rel_fro(H.cpu().double().numpy().T, Hr) <= max(tol, 1e-5) * 10
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("kernel", ["fused", "plain"])
+def test_batch_mu_at_benchmark_shape_matches_oracle(kernel):
+    """Batch MU (section 2.1) at F = 513, K = 50 over N = 20480 frames: the
+    fold sums 40 slices of 512 frames; four cycles against the oracle's
+    cycles, objective of every cycle and the final W and H."""
+    F, K, N, C = 513, 50, 20480, 4
+    say(f"batch MU F={F} K={K} N={N} cycles={C} fp32/{kernel}")
+    V, W0 = synth.problem(F, K, N, seed=62)
+    oracle.set_threads(16)
+    try:
+        Wr, Hr, V64 = W0.astype(np.float64), np.ones((K, N)), V.astype(np.float64)
+        objs = []
+        for _ in range(C):
+            Wr, Hr, o, fl = oracle.batch_cycle(V64, Wr, Hr)
+            assert fl == 0
+            objs.append(o)
+    finally:
+        oracle.set_threads(1)
+    Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+    W = torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV)
+    H = torch.ones((N, K), dtype=torch.float32, device=DEV)
+    tr = bd.batch_mu(Vt, W, H, C, kernel=kernel)
+    torch.cuda.synchronize()
+    tr = tr.cpu().numpy()
+    for c in range(C):
+        assert abs(tr[c] - objs[c]) <= 1e-6 * objs[c], (c, tr[c], objs[c])
+        if c:
+            assert tr[c] <= tr[c - 1] * (1 + 1e-6)
+    assert_close(from_gpu_kf(W), Wr, 1e-4, "W")
+    assert rel_fro(H.cpu().double().numpy().T, Hr) <= 1e-4
+
+
 def test_objective_matches_oracle():
     F, K, N = 200, 12, 77
     say("objective")
