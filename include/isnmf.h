@@ -505,6 +505,25 @@ int isnmf_objective(const float *V, int ldv, const float *W, int ldw, const floa
                     int F, int K, int N, double eps, double *d_out,
                     void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * objective of isnmf_objective, same kernels, same bits, with no workspace
+ * argument.  Its per-frame partial sums live in a fixed array of
+ * ISNMF_OBJECTIVE_NOALLOC_MAX_FRAMES doubles (8 MiB) inside the library, one
+ * copy per GPU, held until the process ends; the call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).  N above the
+ * maximum returns ISNMF_EINVAL before any device work.  Every call on a GPU
+ * shares that GPU's array, and each call writes every partial it reads, so
+ * calls that follow one another on a stream need nothing cleared; calls that
+ * overlap on one GPU (different streams or threads, not ordered) race and
+ * must not be issued.  Other arguments as isnmf_objective.
+ */
+#define ISNMF_OBJECTIVE_NOALLOC_MAX_FRAMES (1 << 20)
+int isnmf_objective_noalloc(const float *V, int ldv, const float *W, int ldw, const float *H,
+                            int ldh, int F, int K, int N, double eps, double *d_out,
+                            void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -101,6 +101,7 @@ def _load():
         "isnmf_batch_mu": (i, [vp, i, i, i, vp, i, vp, i, i, i, P, vp, vp, sz, vp]),
         "isnmf_objective_workspace_size": (sz, [i, i, i]),
         "isnmf_objective": (i, [vp, i, vp, i, vp, i, i, i, i, d, vp, vp, sz, vp]),
+        "isnmf_objective_noalloc": (i, [vp, i, vp, i, vp, i, i, i, i, d, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -127,7 +128,8 @@ EXPORTED = ("isnmf_params_default", "isnmf_strerror", "isnmf_forgetting_rho",
             "isnmf_server_drain", "isnmf_server_results", "isnmf_server_stats",
             "isnmf_server_clock", "isnmf_server_destroy",
             "isnmf_batch_workspace_size", "isnmf_batch_mu",
-            "isnmf_objective_workspace_size", "isnmf_objective")
+            "isnmf_objective_workspace_size", "isnmf_objective", "isnmf_objective_noalloc")
+OBJECTIVE_NOALLOC_MAX_FRAMES = 1 << 20   # ISNMF_OBJECTIVE_NOALLOC_MAX_FRAMES
 
 
 def lib():
@@ -600,3 +602,19 @@ def objective(V: torch.Tensor, W: torch.Tensor, H: torch.Tensor, eps=1e-12, stre
            "isnmf_objective")
     return out
 
+
+def objective_noalloc(V: torch.Tensor, W: torch.Tensor, H: torch.Tensor, out: torch.Tensor,
+                      eps=1e-12, stream=None):
+    """As objective(), through isnmf_objective_noalloc: no workspace, the
+    library's own fixed per-device buffer (N <= OBJECTIVE_NOALLOC_MAX_FRAMES).
+    out: a float64 device scalar the caller owns; the result is written there."""
+    _req(V, torch.float32, name="V")
+    _req(W, torch.float32, name="W")
+    N, F = V.shape
+    K = W.shape[0]
+    _req(H, torch.float32, (N, K), "H")
+    _req(out, torch.float64, name="out")
+    _check(_lib.isnmf_objective_noalloc(_ptr(V), _ld(V), _ptr(W), _ld(W), _ptr(H), _ld(H), F, K,
+                                        N, float(eps), _ptr(out), _stream(stream)),
+           "isnmf_objective_noalloc")
+    return out

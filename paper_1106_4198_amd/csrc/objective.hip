@@ -2,11 +2,19 @@
 //   (1/N) sum_n sum_f d_IS(eps + V_fn, eps + (W H)_fn)
 // The model value is formed in FP32, every divergence term and every sum in
 // FP64, in a fixed order (per-frame block sums, then frames in index order).
+#include <mutex>
+
 #include "common.h"
 #include "devmath.h"
 
 namespace isnmf {
 namespace {
+
+// Per-frame partial sums of isnmf_objective_noalloc, for callers that cannot
+// allocate: one copy per GPU, held until the process ends.  Host code never
+// uses this name as an address; it takes the device address from
+// hipGetSymbolAddress (scratch_ptr below) on each device.
+__device__ __align__(256) double scratch[ISNMF_OBJECTIVE_NOALLOC_MAX_FRAMES];
 
 // Block per frame n.
 __global__ void objective_frames(const float *__restrict__ V, int ldv,
@@ -53,6 +61,29 @@ __global__ void objective_total(int N, const double *__restrict__ frame_buf,
 
 }  // namespace
 
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[MAX_DEVICES] = {};
+
+hipError_t scratch_ptr(double **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch[dev] = p;
+    }
+    *out = (double *)g_scratch[dev];
+    return hipSuccess;
+}
+
 hipError_t launch_objective(const float *V, int ldv, const float *W, int ldw, const float *H,
                             int ldh, int F, int K, int N, double eps, double *frame_buf,
                             double *d_out, hipStream_t s) {
@@ -63,3 +94,20 @@ hipError_t launch_objective(const float *V, int ldv, const float *W, int ldw, co
 }
 
 }  // namespace isnmf
+
+extern "C" int isnmf_objective_noalloc(const float *V, int ldv, const float *W, int ldw,
+                                       const float *H, int ldh, int F, int K, int N, double eps,
+                                       double *d_out, void *stream) {
+    using namespace isnmf;
+    if (!V || !W || !H || !d_out || F < 1 || K < 1 || N < 0 || ldv < F || ldw < F || ldh < K ||
+        !(eps >= 0.0))
+        return ISNMF_EINVAL;
+    if (N > ISNMF_OBJECTIVE_NOALLOC_MAX_FRAMES) return ISNMF_EINVAL;
+    double *buf = nullptr;
+    if (scratch_ptr(&buf) != hipSuccess) return ISNMF_EDEVICE;
+    // every partial the total reads is written by the same call first
+    return launch_objective(V, ldv, W, ldw, H, ldh, F, K, N, eps, buf, d_out,
+                            (hipStream_t)stream) == hipSuccess
+               ? ISNMF_OK
+               : ISNMF_EDEVICE;
+}
