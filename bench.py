@@ -196,8 +196,9 @@ def gen_streams(synth, shapes, seed0, threads):
         return list(ex.map(one, range(len(shapes))))
 
 
-def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0):
-    """S streams advanced together, BF16 products, one replayed hipGraph per step."""
+def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0, precision="bf16"):
+    """S streams advanced together, one replayed hipGraph per step; BF16
+    products, or FP32 (the metric's own arithmetic)."""
     rng = np.random.default_rng(seed0)
     if mixed:
         Fs = rng.choice([257, 513, 1025], size=S)
@@ -219,13 +220,13 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0):
         chosen = {}
         for (Fi, Ki) in shape_set:
             nb = int(sum(int(bb) for a, b2, bb in zip(Fs, Ks, bs) if int(a) == Fi and int(b2) == Ki))
-            bd.autotune(Fi, Ki, max(nb, floor), precision="bf16", trials=2)
-            chosen[(Fi, Ki)] = bd.tune_get(Fi, Ki, "bf16")
+            bd.autotune(Fi, Ki, max(nb, floor), precision=precision, trials=2)
+            chosen[(Fi, Ki)] = bd.tune_get(Fi, Ki, precision)
         return chosen
 
     def make():
         hs = [bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(dev), int(b),
-                             precision="bf16") for (_, W0), b in zip(data, bs)]
+                             precision=precision) for (_, W0), b in zip(data, bs)]
         return hs, bd.MultiISNMF(hs, Vs, [int(x) for x in bs], loss=True)
 
     # Step-level choice of the tuning floor: a floor of 8192 frames tunes each
@@ -271,14 +272,17 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0):
     m.close()
     for h in hs:
         h.close()
+    peak = PEAK_BF16_MFMA if precision == "bf16" else PEAK_FP32_MFMA
     out = {"value": frames / (ms / 1e3), "unit": "frames/s", "streams": S, "steps": steps,
-           "ms_per_step": ms / steps, "precision": "bf16", "graph": True,
+           "ms_per_step": ms / steps, "precision": precision, "graph": True,
            "achieved_tflops": flops / (ms / 1e3) / 1e12,
-           "frac_bf16_peak": flops / (ms / 1e3) / PEAK_BF16_MFMA,
+           f"frac_{precision}_peak": flops / (ms / 1e3) / peak,
            "gen_s": round(gen_s, 1)}
     n_tile = sum(1 for v in variants.values() if v[1] == -1)
     n_stile = sum(1 for v in variants.values() if v[1] == -2)
+    n_t32 = sum(1 for v in variants.values() if v[1] == -3)
     out["variants"] = {"shapes": tuned, "tile16x16x32": n_tile, "tile16x16x32_streamed": n_stile,
+                       "tile16x16x4_fp32": n_t32,
                        "tune_floor_frames": floor,
                        "floor_trial_ms_per_step": {str(k): round(v, 3) for k, v in trial.items()}}
     if mixed:
@@ -622,6 +626,12 @@ def main() -> int:
         forms["batched_uniform"] = bench_batched(bd, synth, torch, np, dev, args.batch_streams,
                                                  args.batch_steps, thr, False, 70000)
         print(f"[bench] batched uniform: {forms['batched_uniform']['value']:.4g} frames/s",
+              file=sys.stderr, flush=True)
+        # the roofline run in the metric's own arithmetic: FP32 products
+        forms["batched_uniform_fp32"] = bench_batched(bd, synth, torch, np, dev,
+                                                      args.batch_streams, args.batch_steps, thr,
+                                                      False, 70000, precision="fp32")
+        print(f"[bench] batched uniform FP32: {forms['batched_uniform_fp32']}",
               file=sys.stderr, flush=True)
         forms["batched_mixed"] = bench_batched(bd, synth, torch, np, dev, args.batch_streams,
                                                max(2, args.batch_steps // 2), thr, True, 80000)

@@ -110,9 +110,12 @@ struct ServeWork {
 // fit_body.h (cpw >= 1: NW waves x CPW chunks of 64 rows, NF frames per
 // workgroup), the VALU variant of fit_valu.h (cpw = 0: one frame per
 // workgroup of nw = 8 waves, rf row sets and kmax / 8 components per
-// thread), or the 16-frame tile variant of fit_tile.h (cpw = -1: BF16
+// thread), the 16-frame tile variant of fit_tile.h (cpw = -1: BF16
 // products, nw = 8 waves of 16 frames each, rf = ceil(F / 32) contraction
-// steps of 32 rows, kmax = 32 ceil(K / 32)).
+// steps of 32 rows, kmax = 32 ceil(K / 32)), its streamed form of
+// fit_stile.h (cpw = -2), or the FP32 16-frame tile variant of fit_t32.h
+// (cpw = -3: nw = 8 waves of 16 frames, rf = ceil(F / 16) row tiles,
+// kmax = 16 ceil(K / 16)).
 struct FitClass {
     int ok;
     int nw, cpw, kmax, wg;
@@ -125,6 +128,8 @@ FitClass valu_class(int F, int K);
 // The 16-frame tile variant for (F, K) with BF16 products, or ok = 0.
 FitClass tile_class(int F, int K);
 FitClass stile_class(int F, int K);
+// The FP32 16-frame tile variant for (F, K), or ok = 0.
+FitClass t32_class(int F, int K);
 FitDesc make_fit_desc(const OnlineDev &d, const float *V, int ldv, int b, int iters, double eps,
                       int warm, float *Hb, int ldh);
 
@@ -167,7 +172,13 @@ hipError_t launch_fit_stile_multi(const FitClass &c, const FitDesc *d, const int
                                   const long long *cur, const int *beff, hipStream_t s);
 hipError_t launch_fit_stile_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
                                  int tiles, hipStream_t s);
-// 16-frame tile variants (cpw -1 resident W, -2 streamed W): 128 frames per item
+// FP32 16-frame tile variant launches: b frames, n batched items, or a served work list.
+hipError_t launch_fit_t32(const FitDesc &a, const FitClass &c, int b, hipStream_t s);
+hipError_t launch_fit_t32_multi(const FitClass &c, const FitDesc *d, const int2 *items, int n,
+                                const long long *cur, const int *beff, hipStream_t s);
+hipError_t launch_fit_t32_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
+                               int tiles, hipStream_t s);
+// 16-frame tile variants (cpw -1 resident W, -2 streamed W, -3 FP32): 128 frames per item
 inline int frames_per_item(const FitClass &c) { return c.cpw < 0 ? 128 : NF; }
 // Every fit variant valid for the shape (the default first); returns the count.
 int fit_candidates(int F, int K, int prec, FitClass *out, int max_out);

@@ -13,6 +13,8 @@
 //                             elsewhere
 //   BF16, F <= 640, K <= 64:  the 16-frame tile variant, a tuning candidate
 //                             (throughput over many frames)
+//   FP32, K <= 64:            the FP32 16-frame tile variant (16x16x4 FP32
+//                             MFMA, W in LDS), a tuning candidate (throughput)
 #include <math.h>
 
 #include "common.h"
@@ -77,6 +79,10 @@ int fit_candidates(int F, int K, int prec, FitClass *out, int max_out) {
     if (prec == 0 && d.cpw != 0) {   // the VALU variant, when the default is an MFMA tile
         const FitClass v = valu_class(F, K);
         if (v.ok) add(v);
+    }
+    if (prec == 0) {                 // the FP32 16-frame tile variant (throughput)
+        const FitClass t = t32_class(F, K);
+        if (t.ok) add(t);
     }
     if (prec == 1) {                 // the 16-frame tile variants (BF16)
         const FitClass t = tile_class(F, K);
@@ -144,6 +150,7 @@ hipError_t launch_fused_fit(const OnlineDev &d, const FitClass &c, const float *
     if (c.cpw == 0) return prec == 0 ? launch_fit_valu(a, c, b, s) : hipErrorNotSupported;
     if (c.cpw == -1) return prec == 1 ? launch_fit_tile(a, c, b, s) : hipErrorNotSupported;
     if (c.cpw == -2) return prec == 1 ? launch_fit_stile(a, c, b, s) : hipErrorNotSupported;
+    if (c.cpw == -3) return prec == 0 ? launch_fit_t32(a, c, b, s) : hipErrorNotSupported;
     const int grid = (b + NF - 1) / NF;
     if (prec == 1) return launch_fit_single_p<1>(a, c, grid, s);
     if (prec == 2) return launch_fit_single_p<2>(a, c, grid, s);

@@ -234,6 +234,8 @@ hipError_t enqueue_step(isnmf_multi *m, hipStream_t s) {
             e = launch_fit_tile_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else if (g.c.cpw == -2)
             e = launch_fit_stile_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
+        else if (g.c.cpw == -3)
+            e = launch_fit_t32_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else if (g.prec == 1)
             e = launch_fit_multi_p<1>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else if (g.prec == 2)

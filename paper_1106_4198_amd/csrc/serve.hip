@@ -130,6 +130,9 @@ hipError_t serve_fit_any(int prec, const FitClass &c, const FitDesc *tab, const 
     if (c.cpw == -2)
         return prec == 1 ? launch_fit_stile_work(c, tab, work, n, (max_b + 127) / 128, s)
                          : hipErrorNotSupported;
+    if (c.cpw == -3)
+        return prec == 0 ? launch_fit_t32_work(c, tab, work, n, (max_b + 127) / 128, s)
+                         : hipErrorNotSupported;
     if (prec == 1) return serve_fit<1>(c, tab, work, n, tiles, s);
     if (prec == 2) return serve_fit<2>(c, tab, work, n, tiles, s);
     return serve_fit<0>(c, tab, work, n, tiles, s);
@@ -520,7 +523,8 @@ int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *s
     if (isnmf_handle_kernel(h) != ISNMF_KERNEL_FUSED) return ISNMF_EUNSUPPORTED;
     const OnlineDev &d = *isnmf_handle_dev(h);
     const FitClass &c = *isnmf_handle_class(h);
-    const bool tile16 = (c.cpw == -1 || c.cpw == -2) && prec_of(p) == 1;
+    const bool tile16 = ((c.cpw == -1 || c.cpw == -2) && prec_of(p) == 1) ||
+                        (c.cpw == -3 && prec_of(p) == 0);
     if (!tile16 && (c.wg || c.cpw != 1 || (c.nw != 4 && c.nw != 8) || c.kmax > 64))
         return ISNMF_EUNSUPPORTED;
     if (footprint > s->budget) return ISNMF_ENOMEM;   // could never be admitted

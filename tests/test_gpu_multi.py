@@ -309,3 +309,46 @@ def test_batched_streamed_tile_streams_equal_alone_bitwise():
         m.close()
     finally:
         bd.tune_clear()
+
+
+def test_fp32_tile_batched_equals_alone_bitwise():
+    """FP32 16-frame tile variant in the batched form: streams of one shape and
+    of mixed shapes (several groups of the variant, 128-frame items and ragged
+    last minibatches) give the bits of the same streams run alone."""
+    shapes = [(513, 50, 128, 300), (513, 50, 128, 256), (257, 64, 64, 200), (129, 8, 200, 390),
+              (592, 64, 33, 70), (1025, 32, 128, 130)]
+    say("fp32 tile batched vs alone")
+    bd.tune_clear()
+    for F, K, _, _ in shapes:
+        bd.tune_set(F, K, "fp32", 8, -3, 0)
+    try:
+        data = []
+        for i, (F, K, b, N) in enumerate(shapes):
+            V, W0 = synth.problem(F, K, N, seed=500 + i)
+            data.append((torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV),
+                         torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV), b))
+        steps = 3
+        alone, loss_alone = [], []
+        for W0, V, b in data:
+            g = bd.OnlineISNMF(W0, b)
+            ls = torch.zeros((), dtype=torch.float64, device=DEV)
+            for s in range(steps):
+                lo, hi = s * b, min((s + 1) * b, V.shape[0])
+                if lo < hi:
+                    g.step(V[lo:hi], None, ls)
+            alone.append(g)
+            loss_alone.append(ls)
+        mixed = [bd.OnlineISNMF(W0, b) for W0, _, b in data]
+        m = bd.MultiISNMF(mixed, [d[1] for d in data], [d[2] for d in data])
+        m.run(1, graph=False)
+        m.run(steps - 1, graph=True)
+        torch.cuda.synchronize()
+        for i, (ga, gm) in enumerate(zip(alone, mixed)):
+            sa, sm = state(ga), state(gm)
+            assert sa[3] == sm[3], i
+            for x, y in zip(sa[:3], sm[:3]):
+                assert torch.equal(x, y), f"stream {i} {shapes[i]} differs alone vs batched"
+            assert torch.equal(loss_alone[i], m.loss[i]), i
+        m.close()
+    finally:
+        bd.tune_clear()

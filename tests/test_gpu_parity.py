@@ -185,6 +185,49 @@ def test_valu_large_config_and_repeatability():
         assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
 
 
+# ---------------------------------------------------------------- one step, FP32 16-frame tile
+
+@contextlib.contextmanager
+def t32_variant(F, K):
+    """Handles of shape (F, K) created inside use the FP32 16-frame tile
+    variant (16x16x4 FP32 MFMA, W in LDS; a throughput tuning entry)."""
+    bd.tune_clear()
+    bd.tune_set(F, K, "fp32", 8, -3, 0)
+    assert bd.tune_get(F, K, "fp32") == (8, -3, 0)
+    try:
+        yield
+    finally:
+        bd.tune_clear()
+
+
+# shapes across every m-tile count (K up to 16, 32, 48, 64), row tiles from 1 to the
+# LDS limit of each (F <= 592 at K <= 64, 784 at K <= 48, 1136 at K <= 32), ragged
+# minibatches, one and several 128-frame workgroups
+T32_SHAPES = [(129, 8, 1), (513, 50, 128), (257, 64, 7), (65, 16, 9), (64, 3, 4), (68, 33, 6),
+              (3, 2, 5), (200, 52, 13), (592, 64, 20), (513, 50, 300), (784, 48, 40),
+              (1025, 32, 33), (1088, 16, 129), (33, 32, 129), (16, 1, 3), (513, 17, 64),
+              (577, 49, 17)]
+
+
+@pytest.mark.parametrize("F,K,b", T32_SHAPES)
+def test_step_fp32_t32(F, K, b):
+    with t32_variant(F, K):
+        compare_step(F, K, b, 20, "fp32", "fused", seed=29, tol=1e-5)
+
+
+def test_step_fp32_t32_variants():
+    with t32_variant(130, 10):
+        compare_step(130, 10, 11, 6, "fp32", "fused", seed=22, tol=1e-5, warm=True)
+        compare_step(130, 10, 11, 6, "fp32", "fused", seed=23, tol=1e-5, rho=0.7)
+        compare_step(130, 10, 11, 6, "fp32", "fused", seed=24, tol=1e-5, normalize=False)
+        compare_step(130, 10, 11, 6, "fp32", "fused", seed=25, tol=1e-5, update_w=False)
+        compare_step(130, 10, 5, 6, "fp32", "fused", seed=26, tol=1e-5, b_max=16)
+        compare_step(130, 10, 5, 0, "fp32", "fused", seed=28, tol=1e-5)
+    with t32_variant(513, 50):
+        compare_step(513, 50, 128, 20, "fp32", "fused", seed=51, tol=1e-5, steps_before=3)
+        compare_step(513, 50, 200, 20, "fp32", "fused", seed=53, tol=1e-5, warm=True)
+
+
 def test_fp32_wide_F_uses_the_valu_variant():
     W0 = torch.rand((40, 1025), dtype=torch.float32, device=DEV) + 0.5
     g = bd.OnlineISNMF(W0, 4, kernel="auto")

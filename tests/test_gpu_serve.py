@@ -351,3 +351,49 @@ def test_served_tile_sessions_equal_alone_bitwise(cpw):
         srv.close()
     finally:
         bd.tune_clear()
+
+
+def test_served_fp32_tile_sessions_equal_alone_bitwise():
+    """Sessions on the FP32 16-frame tile variant in the served form."""
+    say("served fp32 tile")
+    bd.tune_clear()
+    bd.tune_set(513, 64, "fp32", 8, -3, 0)
+    bd.tune_set(257, 32, "fp32", 8, -3, 0)
+    try:
+        rng = np.random.default_rng(9)
+        data = []
+        for i in range(6):
+            F, K = [(513, 64), (257, 32)][i % 2]
+            lens = rng.integers(1, 300, size=3)
+            V, W0 = synth.problem(F, K, int(lens.sum()), seed=700 + i)
+            Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+            o, chunks = 0, []
+            for L in lens:
+                chunks.append(Vt[o:o + int(L)])
+                o += int(L)
+            data.append((torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), chunks))
+        alone = []
+        for W0, chunks in data:
+            g = bd.OnlineISNMF(W0, 512)
+            for c in chunks:
+                g.step(c)
+            alone.append(g)
+        srv = bd.Server(max_sessions=6, max_per_step=6, max_frames=4096, inflight=2)
+        served = []
+        for W0, _ in data:
+            g = bd.OnlineISNMF(W0, 512)
+            served.append((g, srv.open(g)))
+        for k in range(3):
+            for i, (_, chunks) in enumerate(data):
+                srv.submit(served[i][1], chunks[k])
+            srv.pump()
+        srv.drain()
+        torch.cuda.synchronize()
+        for i, (ga, (gs, _)) in enumerate(zip(alone, served)):
+            assert torch.equal(ga.get_w64(), gs.get_w64()), i
+            _, Aa, Ba, _ = ga.get()
+            _, As, Bs, _ = gs.get()
+            assert torch.equal(Aa, As) and torch.equal(Ba, Bs), i
+        srv.close()
+    finally:
+        bd.tune_clear()
