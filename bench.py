@@ -486,6 +486,10 @@ def main() -> int:
     ap.add_argument("--serve-chunks", type=int, default=4096)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and served forms")
+    ap.add_argument("--only", default="",
+                    help="comma-separated forms to run besides the timed pass (bf16, fp16, plain, "
+                         "batch_mu, multipass, batched_uniform, batched_uniform_fp32, "
+                         "batched_mixed, served, served_throughput); default all")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic, to scale rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
@@ -596,55 +600,71 @@ def main() -> int:
         gf.close()
         return v
 
+    only = set(x for x in args.only.split(",") if x)
+
+    def want(name):
+        return not only or name in only
+
     f_steps = max(1, min(args.form_steps, steps))
     forms = {p: {"value": time_form(p, f_steps), "unit": "frames/s", "steps": f_steps}
-             for p in ("bf16", "fp16")}
+             for p in ("bf16", "fp16") if want(p)}
 
     # the plain FP32 path (one op per launch) over a prefix, same shapes
+    plain_fps = None
     p_steps = max(1, min(args.plain_steps, steps))
-    gp = bd.OnlineISNMF(Wt, B, inner_iters=ITERS, kernel="plain")
-    gp.run_pass(Vt[:B], B)
-    torch.cuda.synchronize()
-    gp.close()
-    gp = bd.OnlineISNMF(Wt, B, inner_iters=ITERS, kernel="plain")
-    e0.record()
-    gp.run_pass(Vt[:p_steps * B], B)
-    e1.record()
-    torch.cuda.synchronize()
-    plain_fps = p_steps * B / (e0.elapsed_time(e1) / 1e3)
-    gp.close()
+    if want("plain"):
+        gp = bd.OnlineISNMF(Wt, B, inner_iters=ITERS, kernel="plain")
+        gp.run_pass(Vt[:B], B)
+        torch.cuda.synchronize()
+        gp.close()
+        gp = bd.OnlineISNMF(Wt, B, inner_iters=ITERS, kernel="plain")
+        e0.record()
+        gp.run_pass(Vt[:p_steps * B], B)
+        e1.record()
+        torch.cuda.synchronize()
+        plain_fps = p_steps * B / (e0.elapsed_time(e1) / 1e3)
+        gp.close()
 
-    forms["batch_mu"] = bench_batch_mu(bd, torch, np, Vt, Wt, min(N, args.batch_mu_frames),
-                                       args.batch_mu_cycles)
-    print(f"[bench] batch MU: {forms['batch_mu']}", file=sys.stderr, flush=True)
-    forms["multipass"] = bench_multipass(bd, torch, np, Vt, Wt, min(N, 65536), 3, args.seed + 7)
-    print(f"[bench] multipass: {forms['multipass']['value']:.4g} frames/s", file=sys.stderr,
-          flush=True)
+    if want("batch_mu"):
+        forms["batch_mu"] = bench_batch_mu(bd, torch, np, Vt, Wt, min(N, args.batch_mu_frames),
+                                           args.batch_mu_cycles)
+        print(f"[bench] batch MU: {forms['batch_mu']}", file=sys.stderr, flush=True)
+    if want("multipass"):
+        forms["multipass"] = bench_multipass(bd, torch, np, Vt, Wt, min(N, 65536), 3,
+                                             args.seed + 7)
+        print(f"[bench] multipass: {forms['multipass']['value']:.4g} frames/s", file=sys.stderr,
+              flush=True)
 
     if not args.no_forms:
         thr = cpu_threads()
-        forms["batched_uniform"] = bench_batched(bd, synth, torch, np, dev, args.batch_streams,
-                                                 args.batch_steps, thr, False, 70000)
-        print(f"[bench] batched uniform: {forms['batched_uniform']['value']:.4g} frames/s",
-              file=sys.stderr, flush=True)
-        # the roofline run in the metric's own arithmetic: FP32 products
-        forms["batched_uniform_fp32"] = bench_batched(bd, synth, torch, np, dev,
-                                                      args.batch_streams, args.batch_steps, thr,
-                                                      False, 70000, precision="fp32")
-        print(f"[bench] batched uniform FP32: {forms['batched_uniform_fp32']}",
-              file=sys.stderr, flush=True)
-        forms["batched_mixed"] = bench_batched(bd, synth, torch, np, dev, args.batch_streams,
-                                               max(2, args.batch_steps // 2), thr, True, 80000)
-        print(f"[bench] batched mixed: {forms['batched_mixed']['value']:.4g} frames/s",
-              file=sys.stderr, flush=True)
-        forms["served"] = bench_served(bd, synth, torch, np, dev, args.serve_sessions,
-                                       args.serve_chunks, args.serve_seconds, thr, 90000)
-        print(f"[bench] served: {forms['served']}", file=sys.stderr, flush=True)
-        forms["served_throughput"] = bench_served(bd, synth, torch, np, dev, args.serve_sessions,
-                                                  args.serve_chunks, args.serve_seconds, thr,
-                                                  90000, tune="throughput")
-        print(f"[bench] served (throughput variants): {forms['served_throughput']}",
-              file=sys.stderr, flush=True)
+        if want("batched_uniform"):
+            forms["batched_uniform"] = bench_batched(bd, synth, torch, np, dev, args.batch_streams,
+                                                     args.batch_steps, thr, False, 70000)
+            print(f"[bench] batched uniform: {forms['batched_uniform']['value']:.4g} frames/s",
+                  file=sys.stderr, flush=True)
+        if want("batched_uniform_fp32"):
+            # the roofline run in the metric's own arithmetic: FP32 products
+            forms["batched_uniform_fp32"] = bench_batched(bd, synth, torch, np, dev,
+                                                          args.batch_streams, args.batch_steps,
+                                                          thr, False, 70000, precision="fp32")
+            print(f"[bench] batched uniform FP32: {forms['batched_uniform_fp32']}",
+                  file=sys.stderr, flush=True)
+        if want("batched_mixed"):
+            forms["batched_mixed"] = bench_batched(bd, synth, torch, np, dev, args.batch_streams,
+                                                   max(2, args.batch_steps // 2), thr, True, 80000)
+            print(f"[bench] batched mixed: {forms['batched_mixed']['value']:.4g} frames/s",
+                  file=sys.stderr, flush=True)
+        if want("served"):
+            forms["served"] = bench_served(bd, synth, torch, np, dev, args.serve_sessions,
+                                           args.serve_chunks, args.serve_seconds, thr, 90000)
+            print(f"[bench] served: {forms['served']}", file=sys.stderr, flush=True)
+        if want("served_throughput"):
+            forms["served_throughput"] = bench_served(bd, synth, torch, np, dev,
+                                                      args.serve_sessions, args.serve_chunks,
+                                                      args.serve_seconds, thr, 90000,
+                                                      tune="throughput")
+            print(f"[bench] served (throughput variants): {forms['served_throughput']}",
+                  file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
@@ -667,7 +687,7 @@ def main() -> int:
                                 "E~Exp(1), seeded PCG64"},
         "roofline": roofline,
         "plain_fp32": {"value": plain_fps, "unit": "frames/s", "steps": p_steps,
-                       "speedup_fused": fps / plain_fps},
+                       "speedup_fused": fps / plain_fps if plain_fps else None},
         "online_loss_per_entry": online_loss,
         "heldout": heldout,
         "forms": forms,

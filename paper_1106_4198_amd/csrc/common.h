@@ -115,7 +115,7 @@ struct ServeWork {
 // steps of 32 rows, kmax = 32 ceil(K / 32)), its streamed form of
 // fit_stile.h (cpw = -2), or the FP32 16-frame tile variant of fit_t32.h
 // (cpw = -3: nw = 8 waves of 16 frames, rf = ceil(F / 16) row tiles,
-// kmax = 16 ceil(K / 16)).
+// kmax = K).
 struct FitClass {
     int ok;
     int nw, cpw, kmax, wg;

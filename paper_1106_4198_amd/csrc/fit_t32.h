@@ -36,6 +36,8 @@
 // the number of row tiles T = ceil(F / 16) is a run-time value.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 #include "devmath.h"
 
@@ -61,12 +63,27 @@ __host__ __device__ constexpr size_t lds_bytes(int T, int MT) {
 // Row tiles the LDS holds at MT m-tiles: F <= 16 t_max(MT).
 __host__ __device__ constexpr int t_max(int MT) { return (int)(LDS_MAX / lds_bytes(1, MT)); }
 
-template <int MT>
+// Word 3 of a raw (unswizzled, stride 0) buffer descriptor on gfx9-family
+// chips: 32-bit data format, every out-of-range dword reads as 0.
+constexpr int BUFFER_DWORD3 = 0x00020000;
+
+// Global-memory view of a pointer: loads through it are global (vector memory)
+// instructions, whose completion counter LDS waits do not include.
+typedef const float __attribute__((address_space(1))) gfloat;
+__device__ inline gfloat *gptr(const float *p) { return (gfloat *)p; }
+
+// MT m-tiles of 16 components run on the matrix pipe; the KR <= 4 components
+// after them (16 MT .. 16 MT + KR - 1: K = 50 is 3 m-tiles and 2 remainder
+// components) run on the VALU, instead of a fourth m-tile of which 14 of 16
+// rows would be zero.  The remainder columns sit in the pitch padding of the
+// LDS rows, so the LDS layout is the same.
+template <int MT, int KR>
 __device__ inline void body(const FitDesc &a, int n_first) {
     constexpr int P = pitch(MT);
+    static_assert(KR >= 0 && KR <= 4 && 16 * MT + KR <= P, "remainder fits the pitch padding");
     extern __shared__ float wl[];   // [16 T][P]
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
     const int g = lane >> 4;
     const int n = lane & 15;
     const int F = a.F, K = a.K;
@@ -74,39 +91,78 @@ __device__ inline void body(const FitDesc &a, int n_first) {
     const int fr = n_first + WF * w + n;   // this lane's frame (B / C column)
     const bool fok = fr < a.b;
     const float eps = a.eps;
-    const float *vrow = a.V + (size_t)(fok ? fr : 0) * a.ldv;
 
-    // ---- W into LDS (zero past F and K); consecutive threads read consecutive
-    // rows of a column of the column-major FP32 copy
+    // ---- W into LDS (zero past F and K, every column of the pitch): thread r
+    // takes row r, with every load issued before the first is used
     {
-        const int rows = 16 * T, cols = 16 * MT;
-        for (int e = threadIdx.x; e < rows * cols; e += NWT * 64) {
-            const int c = e / rows, r = e - c * rows;
-            wl[r * P + c] = (r < F && c < K) ? a.W[r + (size_t)c * F] : 0.f;
+        gfloat *W = gptr(a.W);
+        for (int r = threadIdx.x; r < 16 * T; r += NWT * 64) {
+            const bool rok = r < F;
+#pragma unroll
+            for (int c4 = 0; c4 < P / 4; ++c4) {
+                f4 q;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int c = 4 * c4 + j;
+                    const bool ok = rok && c < K;
+                    const float x = W[ok ? r + (size_t)c * F : 0];
+                    q[j] = ok ? x : 0.f;
+                }
+                *reinterpret_cast<f4 *>(wl + r * P + 4 * c4) = q;
+            }
         }
     }
 
-    // eps + v at the lane's rows 16t + 4g + j of its frame (0 past F and for
-    // frames past the minibatch)
+    // v at the lane's rows 16t + 4g + j of its frame, through a buffer
+    // descriptor per wave whose range ends at the last float of the
+    // minibatch's last frame: a load past it (rows past F of that frame,
+    // frames past the minibatch) returns 0 in hardware, so the loads need no
+    // clamps.  Rows past F of the other frames read the next frame; only the
+    // last row tile (t = T - 1) has such rows, and TAIL (a compile-time flag)
+    // marks the code that may meet it and masks them.  A wave's frames never
+    // mix (each is one column of every product), so lanes past the
+    // minibatch compute on zeros and their results are dropped.
+    const int f0w = n_first + WF * w;
+    const int nval = max(0, min(WF, a.b - f0w));
+    const int nrec = nval ? (int)(((size_t)(nval - 1) * a.ldv + F) * sizeof(float)) : 0;
+    const __amdgpu_buffer_rsrc_t vrsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(a.V + (size_t)f0w * a.ldv), (short)0, nrec, BUFFER_DWORD3);
+    const int voff = (n * a.ldv + 4 * g) * (int)sizeof(float);
+    // one 16-byte load per tile (each dword range-checked on its own)
     auto load_v = [&](int t) {
-        f4 v;
-        const int r0 = 16 * t + 4 * g;
+        return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(vrsrc, voff + 64 * t, 0, 0));
+    };
+    // eps + v, and 0 on rows past F
+    auto vprime = [&](int t, const f4 &v, auto tail) {
+        f4 o;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) v[j] = (fok && r0 + j < F) ? eps + vrow[r0 + j] : 0.f;
-        return v;
+        for (int j = 0; j < 4; ++j) o[j] = eps + v[j];
+        if constexpr (decltype(tail)::value) {
+            const int r0 = 16 * t + 4 * g;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (r0 + j >= F) o[j] = 0.f;
+        }
+        return o;
     };
     // X accumulator start: eps, or 1 on rows past F (W = 0 there; x only needs to be > 0)
-    auto cinit = [&](int t) {
+    auto cinit = [&](int t, auto tail) {
         f4 c = {eps, eps, eps, eps};
-        const int r0 = 16 * t + 4 * g;
+        if constexpr (decltype(tail)::value) {
+            const int r0 = 16 * t + 4 * g;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (r0 + j >= F) c[j] = 1.f;
+            for (int j = 0; j < 4; ++j)
+                if (r0 + j >= F) c[j] = 1.f;
+        }
         return c;
     };
-
-    // ---- h (FP32): lane (g, n) holds components 16 mt + 4 g + j of frame n
+    constexpr std::true_type TAIL{};
+    constexpr std::false_type FULL{};
+    // ---- h (FP32): lane (g, n) holds components 16 mt + 4 g + j of frame n;
+    // hr[i] is remainder component 16 MT + i of frame n (the same in the four
+    // lanes of the frame)
     float hq[MT][4];
+    float hr[KR > 0 ? KR : 1];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -114,8 +170,11 @@ __device__ inline void body(const FitDesc &a, int n_first) {
             const int k = 16 * mt + 4 * g + j;
             hq[mt][j] = k < K ? ((a.warm && fok) ? a.Hb[(size_t)fr * a.ldh + k] : 1.f) : 0.f;
         }
-    // slots j of the last m-tile that hold any component < K
-    const int jlast = min(4, K - 16 * (MT - 1));
+#pragma unroll
+    for (int i = 0; i < KR; ++i) {
+        const int k = 16 * MT + i;
+        hr[i] = k < K ? ((a.warm && fok) ? a.Hb[(size_t)fr * a.ldh + k] : 1.f) : 0.f;
+    }
     __syncthreads();   // W in LDS
 
     // X operands of row tile t: components 16 mt + 4g .. + 3 of row 16t + n
@@ -124,19 +183,39 @@ __device__ inline void body(const FitDesc &a, int n_first) {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) o[mt] = *reinterpret_cast<const f4 *>(p + 16 * mt);
     };
-    auto model_ops = [&](int t, const f4 (&o)[MT]) {
-        f4 x = cinit(t);
+    // W^T operands of row tile t: component 16 mt + n of rows 16t + 4g + j; and
+    // the remainder components of those rows (one 16-byte read per row, the
+    // same address in the 16 lanes of a row group)
+    auto load_wt = [&](int t, float (&o)[4][MT], f4 (&r)[4]) {
+        const float *p = wl + (16 * t + 4 * g) * P;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) o[j][mt] = p[j * P + 16 * mt + n];
+            if constexpr (KR > 0) r[j] = *reinterpret_cast<const f4 *>(p + j * P + 16 * MT);
+        }
+    };
+    // matrix-pipe part of the model: two accumulation chains (even and odd slots)
+    auto model_ops = [&](int t, const f4 (&o)[MT], auto tail) {
+        f4 x0 = cinit(t, tail), x1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (mt < MT - 1 || j < jlast) x = mfma(o[mt][j], hq[mt][j], x);
-        return x;
+            for (int j = 0; j < 4; ++j) {
+                if (j & 1)
+                    x1 = mfma(o[mt][j], hq[mt][j], x1);
+                else
+                    x0 = mfma(o[mt][j], hq[mt][j], x0);
+            }
+        return x0 + x1;
     };
-    auto model = [&](int t) {
-        f4 o[MT];
-        load_wx(t, o);
-        return model_ops(t, o);
+    // the remainder components' part of the model, added to the matrix part
+    auto model_rest = [&](f4 x, const f4 (&r)[4]) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < KR; ++i) x[j] = fmaf(r[j][i], hr[i], x[j]);
+        return x;
     };
 
     int guard = 0;
@@ -147,31 +226,27 @@ __device__ inline void body(const FitDesc &a, int n_first) {
             na[mt] = f4{0.f, 0.f, 0.f, 0.f};
             da[mt] = f4{0.f, 0.f, 0.f, 0.f};
         }
+        float nr[KR > 0 ? KR : 1], dr[KR > 0 ? KR : 1];
+#pragma unroll
+        for (int i = 0; i < KR; ++i) nr[i] = dr[i] = 0.f;
         // Software pipeline over the row tiles: tile t + 1's model products go
-        // to the matrix pipe before tile t's ratios are formed, and v of tile
-        // t + 2 is in flight meanwhile.  Same products and sums as tile by
-        // tile, so the same bits.
-        f4 x = model(0);
-        f4 v0 = load_v(0);
-        f4 v1 = T > 1 ? load_v(1) : v0;
-        for (int t = 0; t < T; ++t) {
-            f4 xn = x;
-            if (t + 1 < T) xn = model(t + 1);
-            f4 v2 = v1;
-            if (t + 2 < T) v2 = load_v(t + 2);
-            // W^T operands of the tile: component 16 mt + n of rows 16t + 4g + j
-            float wt[4][MT];
-            const float *p = wl + (16 * t + 4 * g) * P + n;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) wt[j][mt] = p[j * P + 16 * mt];
-            float r1[4], r2[4];
+        // to the matrix pipe before tile t's ratios are formed; the LDS
+        // operands of the next tiles and v two tiles ahead are in flight
+        // meanwhile.  The loop takes two tiles per trip, so the register sets
+        // alternate by name (no copies that would wait on the loads).  Same
+        // products and sums as tile by tile, so the same bits.
+        auto ratios = [&](int t, const f4 &xm, const f4 (&wr)[4], const f4 &v, float (&r1)[4],
+                          float (&r2)[4], auto tail) {
+            const f4 x = model_rest(xm, wr);
+            const f4 ve = vprime(t, v, tail);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 r1[j] = __builtin_amdgcn_rcpf(x[j]);
-                r2[j] = v0[j] * r1[j] * r1[j];
+                r2[j] = ve[j] * r1[j] * r1[j];
             }
+        };
+        auto numden = [&](const float (&wt)[4][MT], const f4 (&wr)[4], const float (&r1)[4],
+                          const float (&r2)[4]) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -179,10 +254,51 @@ __device__ inline void body(const FitDesc &a, int n_first) {
                     na[mt] = mfma(wt[j][mt], r2[j], na[mt]);
                     da[mt] = mfma(wt[j][mt], r1[j], da[mt]);
                 }
-            x = xn;
-            v0 = v1;
-            v1 = v2;
-        }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < KR; ++i) {
+                    nr[i] = fmaf(wr[j][i], r2[j], nr[i]);
+                    dr[i] = fmaf(wr[j][i], r1[j], dr[i]);
+                }
+        };
+        f4 wx[MT];
+        float wt0[4][MT], wt1[4][MT];
+        f4 wr0[4], wr1[4];
+        load_wx(0, wx);
+        f4 x0 = model_ops(0, wx, TAIL), x1 = x0;
+        if (T > 1) load_wx(1, wx);
+        load_wt(0, wt0, wr0);
+        f4 va = load_v(0), vb = load_v(1);   // tile 1 of T = 1 reads zeros or the next frame, unused
+        // One trip: tiles t and t + 1 (if any), with the model of the tile after
+        // each and v two tiles ahead.  tail: a tile the trip touches may be T - 1.
+        auto trip = [&](int t, auto tail) {
+            constexpr bool TL = decltype(tail)::value;   // else tiles t .. t + 3 all exist
+            float r1[4], r2[4];
+            // tile t: X(t) in x0, v(t) in va, W^T operands in wt0, wr0
+            __builtin_amdgcn_sched_barrier(0);
+            if (!TL || t + 1 < T) x1 = model_ops(t + 1, wx, tail);
+            __builtin_amdgcn_sched_barrier(0);
+            if (!TL || t + 2 < T) load_wx(t + 2, wx);
+            load_wt(TL ? min(t + 1, T - 1) : t + 1, wt1, wr1);
+            ratios(t, x0, wr0, va, r1, r2, tail);
+            va = load_v(TL ? min(t + 2, T - 1) : t + 2);
+            numden(wt0, wr0, r1, r2);
+            if (TL && t + 1 >= T) return;
+            // tile t + 1: X(t+1) in x1, v(t+1) in vb, W^T operands in wt1, wr1
+            __builtin_amdgcn_sched_barrier(0);
+            if (!TL || t + 2 < T) x0 = model_ops(t + 2, wx, tail);
+            __builtin_amdgcn_sched_barrier(0);
+            if (!TL || t + 3 < T) load_wx(t + 3, wx);
+            load_wt(TL ? min(t + 2, T - 1) : t + 2, wt0, wr0);
+            ratios(t + 1, x1, wr1, vb, r1, r2, tail);
+            vb = load_v(TL ? min(t + 3, T - 1) : t + 3);
+            numden(wt1, wr1, r1, r2);
+        };
+        // trips whose tiles t .. t + 3 all lie before the last tile need no masks
+        int t = 0;
+        for (; t + 3 < T - 1; t += 2) trip(t, FULL);
+        for (; t < T; t += 2) trip(t, TAIL);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -195,6 +311,23 @@ __device__ inline void body(const FitDesc &a, int n_first) {
                         guard = 1;
                 }
             }
+        // remainder components: the four row groups' partial sums of the
+        // frame, combined by a fixed xor butterfly (the same bits in the four
+        // lanes), then the same update in each
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            float N = nr[i], D = dr[i];
+            N += __shfl_xor(N, 16, 64);
+            D += __shfl_xor(D, 16, 64);
+            N += __shfl_xor(N, 32, 64);
+            D += __shfl_xor(D, 32, 64);
+            if (16 * MT + i < K) {
+                if (D > 0.f && N >= 0.f)
+                    hr[i] *= __builtin_amdgcn_sqrtf(N * __builtin_amdgcn_rcpf(D));
+                else if (fok)
+                    guard = 1;
+            }
+        }
     }
     if (guard) atomicOr(a.flags, FLAG_GUARD_H);
 
@@ -202,22 +335,33 @@ __device__ inline void body(const FitDesc &a, int n_first) {
     // objective), and the check of v
     double ls = 0.0;
     int bad = 0;
-    f4 x = model(0);
+    f4 wx[MT];
+    float wt_unused[4][MT];
+    f4 wr[4];
+    load_wx(0, wx);
+    f4 x = model_ops(0, wx, TAIL);
+    f4 v0 = load_v(0);
     for (int t = 0; t < T; ++t) {
+        load_wt(t, wt_unused, wr);
         f4 xn = x;
-        if (t + 1 < T) xn = model(t + 1);
+        if (t + 1 < T) {
+            load_wx(t + 1, wx);
+            xn = model_ops(t + 1, wx, TAIL);
+        }
+        const f4 v1 = load_v(min(t + 1, T - 1));
+        const f4 xf = model_rest(x, wr);
         const int r0 = 16 * t + 4 * g;
         f4 r1, r2;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const bool ok = fok && r0 + j < F;
-            const float v = ok ? vrow[r0 + j] : 0.f;
+            const float v = ok ? v0[j] : 0.f;
             bad |= !isfinite(v);
             const float ve = eps + v;
-            const float r = __builtin_amdgcn_rcpf(x[j]);
+            const float r = __builtin_amdgcn_rcpf(xf[j]);
             r1[j] = ok ? r : 0.f;
             r2[j] = ok ? ve * r * r : 0.f;
-            if (ok) ls += dis_term(a.epsd + double(v), double(x[j]));
+            if (ok) ls += dis_term(a.epsd + double(v), double(xf[j]));
         }
         // FR is a multiple of 64, so rows r0 .. r0 + 3 lie in the frame's buffer row
         if (fok) {
@@ -225,6 +369,7 @@ __device__ inline void body(const FitDesc &a, int n_first) {
             *reinterpret_cast<f4 *>(a.R2 + (size_t)fr * a.FR + r0) = r2;
         }
         x = xn;
+        v0 = v1;
     }
     if (bad) atomicOr(a.flags, FLAG_NONFINITE_V);
     // frame n's loss: lanes n, n + 16, n + 32, n + 48, in that order
@@ -243,17 +388,27 @@ __device__ inline void body(const FitDesc &a, int n_first) {
                     if (a.Hb) a.Hb[(size_t)fr * a.ldh + k] = hq[mt][j];
                 }
             }
+        if (g == 0) {
+#pragma unroll
+            for (int i = 0; i < KR; ++i) {
+                const int k = 16 * MT + i;
+                if (k < K) {
+                    a.Hi[(size_t)fr * a.KP + k] = hr[i];
+                    if (a.Hb) a.Hb[(size_t)fr * a.ldh + k] = hr[i];
+                }
+            }
+        }
     }
 }
 
-template <int MT>
+template <int MT, int KR>
 __global__ __launch_bounds__(NWT * 64) void fit_t32_kernel(FitDesc a) {
-    body<MT>(a, blockIdx.x * FPW);
+    body<MT, KR>(a, blockIdx.x * FPW);
 }
 
 // Batched form: item = (stream, tile of 128 frames); tiles past the stream's
 // minibatch of this step exit.
-template <int MT>
+template <int MT, int KR>
 __global__ __launch_bounds__(NWT * 64) void fit_t32_multi_kernel(const FitDesc *__restrict__ descs,
                                                                  const int2 *__restrict__ items,
                                                                  const long long *__restrict__ cursor,
@@ -266,11 +421,11 @@ __global__ __launch_bounds__(NWT * 64) void fit_t32_multi_kernel(const FitDesc *
     a.b = b;
     a.V += c * a.ldv;
     if (a.Hb) a.Hb += c * a.ldh;
-    body<MT>(a, it.y * FPW);
+    body<MT, KR>(a, it.y * FPW);
 }
 
 // Served form: grid (chunk i, 128-frame tile j) over a step's work list.
-template <int MT>
+template <int MT, int KR>
 __global__ __launch_bounds__(NWT * 64) void fit_t32_work_kernel(const FitDesc *__restrict__ tab,
                                                                 const ServeWork *__restrict__ work) {
     const ServeWork wk = work[blockIdx.x];
@@ -279,8 +434,65 @@ __global__ __launch_bounds__(NWT * 64) void fit_t32_work_kernel(const FitDesc *_
     a.b = wk.b;
     a.V = wk.V;
     a.ldv = wk.ldv;
-    body<MT>(a, blockIdx.y * FPW);
+    body<MT, KR>(a, blockIdx.y * FPW);
 }
+
+template <int MT, int KR>
+hipError_t run(const FitDesc *a, int b, const FitDesc *d, const int2 *items, int n,
+               const long long *cur, const int *beff, const FitDesc *tab, const ServeWork *work,
+               int tiles, int T, hipStream_t s) {
+    if (T < 1 || T > t_max(MT)) return hipErrorInvalidValue;
+    const size_t lds = lds_bytes(T, MT);
+    // the largest dynamic LDS any launch of the kernel asks for, set once
+    static const hipError_t a1 = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&fit_t32_kernel<MT, KR>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+    static const hipError_t a2 = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&fit_t32_multi_kernel<MT, KR>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+    static const hipError_t a3 = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&fit_t32_work_kernel<MT, KR>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+    if (work) {
+        if (a3 != hipSuccess) return a3;
+        fit_t32_work_kernel<MT, KR><<<dim3(n, tiles), NWT * 64, lds, s>>>(tab, work);
+    } else if (d) {
+        if (a2 != hipSuccess) return a2;
+        fit_t32_multi_kernel<MT, KR><<<n, NWT * 64, lds, s>>>(d, items, cur, beff);
+    } else {
+        if (a1 != hipSuccess) return a1;
+        fit_t32_kernel<MT, KR><<<(b + FPW - 1) / FPW, NWT * 64, lds, s>>>(*a);
+    }
+    return hipGetLastError();
+}
+
+// Launch of the (MT, KR) instance; explicitly instantiated per MT in
+// fit_t32_m*.hip so the instances build in parallel.
+template <int MT>
+hipError_t launch_mt(int KR, const FitDesc *a, int b, const FitDesc *d, const int2 *items, int n,
+                     const long long *cur, const int *beff, const FitDesc *tab,
+                     const ServeWork *work, int tiles, int T, hipStream_t s) {
+    if constexpr (MT == MT_MAX) {
+        if (KR != 0) return hipErrorNotSupported;
+        return run<MT, 0>(a, b, d, items, n, cur, beff, tab, work, tiles, T, s);
+    } else {
+        switch (KR) {
+            case 0: return run<MT, 0>(a, b, d, items, n, cur, beff, tab, work, tiles, T, s);
+            case 1: return run<MT, 1>(a, b, d, items, n, cur, beff, tab, work, tiles, T, s);
+            case 2: return run<MT, 2>(a, b, d, items, n, cur, beff, tab, work, tiles, T, s);
+            case 3: return run<MT, 3>(a, b, d, items, n, cur, beff, tab, work, tiles, T, s);
+            case 4: return run<MT, 4>(a, b, d, items, n, cur, beff, tab, work, tiles, T, s);
+            default: return hipErrorNotSupported;
+        }
+    }
+}
+
+#define ISNMF_T32_SIG(MTV)                                                                     \
+    hipError_t launch_mt<MTV>(int, const FitDesc *, int, const FitDesc *, const int2 *, int,   \
+                              const long long *, const int *, const FitDesc *,                 \
+                              const ServeWork *, int, int, hipStream_t)
+#define ISNMF_T32_EXTERN(MTV) extern template ISNMF_T32_SIG(MTV);
+#define ISNMF_T32_INSTANTIATE(MTV) template ISNMF_T32_SIG(MTV);
 
 }  // namespace t32
 }  // namespace isnmf

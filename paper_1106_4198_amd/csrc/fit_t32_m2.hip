@@ -1,0 +1,8 @@
+// Instances of the FP32 16-frame tile fit with 2 m-tile(s) of components on the matrix pipe.
+#include "fit_t32.h"
+
+namespace isnmf {
+namespace t32 {
+ISNMF_T32_INSTANTIATE(2)
+}  // namespace t32
+}  // namespace isnmf

@@ -200,13 +200,14 @@ def t32_variant(F, K):
         bd.tune_clear()
 
 
-# shapes across every m-tile count (K up to 16, 32, 48, 64), row tiles from 1 to the
-# LDS limit of each (F <= 592 at K <= 64, 784 at K <= 48, 1136 at K <= 32), ragged
-# minibatches, one and several 128-frame workgroups
+# shapes across every split of K into matrix-pipe m-tiles (1..4) and VALU
+# remainder components (0..4: K = 8, 16, 33, 35, 49, 50, 52, 64, ...), row tiles
+# from 1 to the LDS limit of each split (F <= 592 at 4 m-tiles, 784 at 3, 1136 at
+# 2), ragged minibatches, one and several 128-frame workgroups
 T32_SHAPES = [(129, 8, 1), (513, 50, 128), (257, 64, 7), (65, 16, 9), (64, 3, 4), (68, 33, 6),
               (3, 2, 5), (200, 52, 13), (592, 64, 20), (513, 50, 300), (784, 48, 40),
               (1025, 32, 33), (1088, 16, 129), (33, 32, 129), (16, 1, 3), (513, 17, 64),
-              (577, 49, 17)]
+              (577, 49, 17), (784, 52, 20), (300, 35, 40), (1088, 36, 8), (257, 20, 130)]
 
 
 @pytest.mark.parametrize("F,K,b", T32_SHAPES)
