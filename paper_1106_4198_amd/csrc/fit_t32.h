@@ -177,6 +177,9 @@ __device__ inline void body(const FitDesc &a, int n_first) {
     }
     __syncthreads();   // W in LDS
 
+    // remainder operands of a row: KR floats (2 or 4 read at once)
+    typedef float RV __attribute__((ext_vector_type(KR <= 2 ? 2 : 4)));
+
     // X operands of row tile t: components 16 mt + 4g .. + 3 of row 16t + n
     auto load_wx = [&](int t, f4 (&o)[MT]) {
         const float *p = wl + (16 * t + n) * P + 4 * g;
@@ -186,31 +189,27 @@ __device__ inline void body(const FitDesc &a, int n_first) {
     // W^T operands of row tile t: component 16 mt + n of rows 16t + 4g + j; and
     // the remainder components of those rows (one 16-byte read per row, the
     // same address in the 16 lanes of a row group)
-    auto load_wt = [&](int t, float (&o)[4][MT], f4 (&r)[4]) {
+    auto load_wt = [&](int t, float (&o)[4][MT], RV (&r)[4]) {
         const float *p = wl + (16 * t + 4 * g) * P;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) o[j][mt] = p[j * P + 16 * mt + n];
-            if constexpr (KR > 0) r[j] = *reinterpret_cast<const f4 *>(p + j * P + 16 * MT);
+            if constexpr (KR > 0) r[j] = *reinterpret_cast<const RV *>(p + j * P + 16 * MT);
         }
     };
-    // matrix-pipe part of the model: two accumulation chains (even and odd slots)
+    // matrix-pipe part of the model: one accumulation chain (the matrix pipe
+    // accumulates back to back); its result is read a half trip later
     auto model_ops = [&](int t, const f4 (&o)[MT], auto tail) {
-        f4 x0 = cinit(t, tail), x1 = {0.f, 0.f, 0.f, 0.f};
+        f4 x = cinit(t, tail);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (j & 1)
-                    x1 = mfma(o[mt][j], hq[mt][j], x1);
-                else
-                    x0 = mfma(o[mt][j], hq[mt][j], x0);
-            }
-        return x0 + x1;
+            for (int j = 0; j < 4; ++j) x = mfma(o[mt][j], hq[mt][j], x);
+        return x;
     };
     // the remainder components' part of the model, added to the matrix part
-    auto model_rest = [&](f4 x, const f4 (&r)[4]) {
+    auto model_rest = [&](f4 x, const RV (&r)[4]) {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -235,7 +234,7 @@ __device__ inline void body(const FitDesc &a, int n_first) {
         // meanwhile.  The loop takes two tiles per trip, so the register sets
         // alternate by name (no copies that would wait on the loads).  Same
         // products and sums as tile by tile, so the same bits.
-        auto ratios = [&](int t, const f4 &xm, const f4 (&wr)[4], const f4 &v, float (&r1)[4],
+        auto ratios = [&](int t, const f4 &xm, const RV (&wr)[4], const f4 &v, float (&r1)[4],
                           float (&r2)[4], auto tail) {
             const f4 x = model_rest(xm, wr);
             const f4 ve = vprime(t, v, tail);
@@ -245,7 +244,7 @@ __device__ inline void body(const FitDesc &a, int n_first) {
                 r2[j] = ve[j] * r1[j] * r1[j];
             }
         };
-        auto numden = [&](const float (&wt)[4][MT], const f4 (&wr)[4], const float (&r1)[4],
+        auto numden = [&](const float (&wt)[4][MT], const RV (&wr)[4], const float (&r1)[4],
                           const float (&r2)[4]) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -262,43 +261,56 @@ __device__ inline void body(const FitDesc &a, int n_first) {
                     dr[i] = fmaf(wr[j][i], r1[j], dr[i]);
                 }
         };
-        f4 wx[MT];
+        f4 wx0[MT], wx1[MT];
         float wt0[4][MT], wt1[4][MT];
-        f4 wr0[4], wr1[4];
-        load_wx(0, wx);
-        f4 x0 = model_ops(0, wx, TAIL), x1 = x0;
-        if (T > 1) load_wx(1, wx);
+        RV wr0[4], wr1[4];
+        load_wx(0, wx0);
+        f4 x0 = model_ops(0, wx0, TAIL), x1 = x0;
+        if (T > 1) load_wx(1, wx1);
         load_wt(0, wt0, wr0);
-        f4 va = load_v(0), vb = load_v(1);   // tile 1 of T = 1 reads zeros or the next frame, unused
-        // One trip: tiles t and t + 1 (if any), with the model of the tile after
-        // each and v two tiles ahead.  tail: a tile the trip touches may be T - 1.
-        auto trip = [&](int t, auto tail) {
-            constexpr bool TL = decltype(tail)::value;   // else tiles t .. t + 3 all exist
+        // v four tiles ahead: tiles past T read zeros or the next frame, unused
+        // (issued in tile order: the loop's waits count them in that order)
+        f4 vq[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            vq[i] = load_v(i);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // One tile: X(tt) in xc, v(tt) in vc, W^T operands in wtc/wrc, X operands
+        // of tile tt + 1 in wxc.  First the LDS reads of the operands of tiles
+        // tt + 1 (W^T, into wtn/wrn) and tt + 2 (X, into wxn); then the model of
+        // tile tt + 1 on the matrix pipe with this tile's ratios on the VALU
+        // beside it, NUM/DEN of this tile, and v of tile tt + 4 into vc.
+        // tail: a tile it touches may be T - 1.
+        auto tile = [&](int tt, f4 &xc, f4 &xn, f4 &vc, f4 (&wxc)[MT], f4 (&wxn)[MT],
+                        float (&wtc)[4][MT], float (&wtn)[4][MT], RV (&wrc)[4], RV (&wrn)[4],
+                        auto tail) {
+            constexpr bool TL = decltype(tail)::value;   // else tiles tt .. tt + 4 all exist
             float r1[4], r2[4];
-            // tile t: X(t) in x0, v(t) in va, W^T operands in wt0, wr0
             __builtin_amdgcn_sched_barrier(0);
-            if (!TL || t + 1 < T) x1 = model_ops(t + 1, wx, tail);
-            __builtin_amdgcn_sched_barrier(0);
-            if (!TL || t + 2 < T) load_wx(t + 2, wx);
-            load_wt(TL ? min(t + 1, T - 1) : t + 1, wt1, wr1);
-            ratios(t, x0, wr0, va, r1, r2, tail);
-            va = load_v(TL ? min(t + 2, T - 1) : t + 2);
-            numden(wt0, wr0, r1, r2);
-            if (TL && t + 1 >= T) return;
-            // tile t + 1: X(t+1) in x1, v(t+1) in vb, W^T operands in wt1, wr1
-            __builtin_amdgcn_sched_barrier(0);
-            if (!TL || t + 2 < T) x0 = model_ops(t + 2, wx, tail);
-            __builtin_amdgcn_sched_barrier(0);
-            if (!TL || t + 3 < T) load_wx(t + 3, wx);
-            load_wt(TL ? min(t + 2, T - 1) : t + 2, wt0, wr0);
-            ratios(t + 1, x1, wr1, vb, r1, r2, tail);
-            vb = load_v(TL ? min(t + 3, T - 1) : t + 3);
-            numden(wt1, wr1, r1, r2);
+            if (!TL || tt + 2 < T) load_wx(tt + 2, wxn);
+            load_wt(TL ? min(tt + 1, T - 1) : tt + 1, wtn, wrn);
+            __builtin_amdgcn_sched_barrier(0);   // the next operands in flight first
+            if (!TL || tt + 1 < T) xn = model_ops(tt + 1, wxc, tail);
+            ratios(tt, xc, wrc, vc, r1, r2, tail);
+            vc = load_v(tt + 4);
+            numden(wtc, wrc, r1, r2);
         };
-        // trips whose tiles t .. t + 3 all lie before the last tile need no masks
+        // four tiles per trip, so the register sets rotate by name
+        auto trip = [&](int t, auto tail) {
+            constexpr bool TL = decltype(tail)::value;
+            tile(t, x0, x1, vq[0], wx1, wx0, wt0, wt1, wr0, wr1, tail);
+            if (TL && t + 1 >= T) return;
+            tile(t + 1, x1, x0, vq[1], wx0, wx1, wt1, wt0, wr1, wr0, tail);
+            if (TL && t + 2 >= T) return;
+            tile(t + 2, x0, x1, vq[2], wx1, wx0, wt0, wt1, wr0, wr1, tail);
+            if (TL && t + 3 >= T) return;
+            tile(t + 3, x1, x0, vq[3], wx0, wx1, wt1, wt0, wr1, wr0, tail);
+        };
+        // trips whose tiles t .. t + 4 all lie before the last tile need no masks
         int t = 0;
-        for (; t + 3 < T - 1; t += 2) trip(t, FULL);
-        for (; t < T; t += 2) trip(t, TAIL);
+        for (; t + 4 < T - 1; t += 4) trip(t, FULL);
+        for (; t < T; t += 4) trip(t, TAIL);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -337,7 +349,7 @@ __device__ inline void body(const FitDesc &a, int n_first) {
     int bad = 0;
     f4 wx[MT];
     float wt_unused[4][MT];
-    f4 wr[4];
+    RV wr[4];
     load_wx(0, wx);
     f4 x = model_ops(0, wx, TAIL);
     f4 v0 = load_v(0);
