@@ -55,9 +55,9 @@ FIT_SOURCES = {
     "mfma": ("fit_body.h", "fit_launch.h", "fit_f32.hip"),
 }
 TRAFFIC = {
-    # FETCH_SIZE 697.0 KiB x 2.0 + WRITE_SIZE 552.0 KiB x 1.0 per b=128 launch
+    # FETCH_SIZE 713.0 KiB x 2.0 + WRITE_SIZE 558.5 KiB x 1.0 per b=128 launch
     # (profiles/fit_valu_F513_K50_b128_pmc.md)
-    ("fit_valu_kernel<7,9>", "b47b7c84d1bd7c19210ea3ed5356d8d044f07670"): (697.0 * 2.0 + 552.0) * 1024,
+    ("fit_valu_kernel<7,9>", "6f97083ad08ec38c886dc31404157a459e2ea1dd"): (713.0 * 2.0 + 558.5) * 1024,
 }
 
 
