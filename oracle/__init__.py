@@ -62,6 +62,20 @@ def _load():
     lib.isnmf_ref_batch_cycle.restype = ctypes.c_int
     lib.isnmf_ref_batch_cycle.argtypes = [ctypes.c_int] * 3 + [_dp, ctypes.c_long] * 3 + [
         ctypes.c_double, ctypes.c_int, _dp]
+    lib.isnmf_ref_pen_objective_h.restype = ctypes.c_double
+    lib.isnmf_ref_pen_objective_h.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_long,
+                                              _dp, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double]
+    lib.isnmf_ref_fit_h_pen.restype = ctypes.c_int
+    lib.isnmf_ref_fit_h_pen.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_long, _dp,
+                                        ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, _dp]
+    lib.isnmf_ref_online_step_pen.restype = ctypes.c_int
+    lib.isnmf_ref_online_step_pen.argtypes = [
+        ctypes.c_int, ctypes.c_int, ctypes.c_int,
+        _dp, ctypes.c_long, _dp, ctypes.c_long, _dp, _dp, _dp, ctypes.c_long,
+        ctypes.c_int, ctypes.c_double, ctypes.c_double,
+        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp]
     lib.isnmf_ref_set_threads.restype = None
     lib.isnmf_ref_set_threads.argtypes = [ctypes.c_int]
     lib.isnmf_ref_get_threads.restype = ctypes.c_int
@@ -127,6 +141,30 @@ def fit_h(v, W, h0=None, iters: int = 20, eps: float = 1e-12):
     return h, int(fl)
 
 
+def pen_objective_h(v, W, h, lam: float, a: float, eps: float = 1e-12) -> float:
+    """sum_f d_IS(eps + v_f, eps + (W h)_f) + lam * log(a + sum_k h_k): the inner
+    objective with the log penalty on H (section 2.2, Extensions)."""
+    v = np.ascontiguousarray(np.ravel(v), dtype=np.float64)
+    W = _f64(W)
+    F, K = W.shape
+    h = np.ascontiguousarray(np.ravel(h), dtype=np.float64)
+    return float(_load().isnmf_ref_pen_objective_h(F, K, _p(v), _p(W), F, _p(h), float(eps),
+                                                   float(lam), float(a)))
+
+
+def fit_h_pen(v, W, lam: float, a: float, h0=None, iters: int = 20, eps: float = 1e-12):
+    """Inner fit with the log penalty on H (section 2.2, Extensions).
+    Returns (h, flags)."""
+    v = np.ascontiguousarray(np.ravel(v), dtype=np.float64)
+    W = _f64(W)
+    F, K = W.shape
+    h = np.ones(K) if h0 is None else np.array(h0, dtype=np.float64).ravel().copy()
+    scratch = np.zeros(F + K)
+    fl = _load().isnmf_ref_fit_h_pen(F, K, _p(v), _p(W), F, _p(h), int(iters), float(eps),
+                                     float(lam), float(a), _p(scratch))
+    return h, int(fl)
+
+
 class OnlineState:
     """(W, A, B, t) of Algorithm 1, FP64, with one-minibatch steps."""
 
@@ -152,11 +190,12 @@ class OnlineState:
         return s
 
     def step(self, Vb, iters: int = 20, eps: float = 1e-12, rho: float = 1.0,
-             normalize: bool = True, H=None, update_w: bool = True):
+             normalize: bool = True, H=None, update_w: bool = True, psi=None):
         """One online step on the minibatch Vb (F x b).
 
         H: None for fresh restarts (h = 1), else a K x b warm start (updated
-        copy returned).  Returns (H_b, dW_fro, flags)."""
+        copy returned).  psi: None, or (lambda, a) of the log penalty on H
+        (section 2.2, Extensions).  Returns (H_b, dW_fro, flags)."""
         Vb = _f64(Vb)
         F, b = Vb.shape
         if F != self.F:
@@ -165,10 +204,17 @@ class OnlineState:
         Hb = np.ones((self.K, b), order="F") if H is None else _f64(H, (self.K, b)).copy(order="F")
         loss = ctypes.c_double(0.0)
         dw = ctypes.c_double(0.0)
-        fl = _load().isnmf_ref_online_step(
-            F, self.K, b, _p(Vb), F, _p(self.W), F, _p(self.A), _p(self.B), _p(Hb), self.K,
-            int(iters), float(eps), float(rho), int(bool(normalize)), int(warm), int(bool(update_w)),
-            ctypes.byref(loss), ctypes.byref(dw))
+        if psi is not None:
+            fl = _load().isnmf_ref_online_step_pen(
+                F, self.K, b, _p(Vb), F, _p(self.W), F, _p(self.A), _p(self.B), _p(Hb), self.K,
+                int(iters), float(eps), float(rho), int(bool(normalize)), int(warm),
+                int(bool(update_w)), float(psi[0]), float(psi[1]), ctypes.byref(loss),
+                ctypes.byref(dw))
+        else:
+            fl = _load().isnmf_ref_online_step(
+                F, self.K, b, _p(Vb), F, _p(self.W), F, _p(self.A), _p(self.B), _p(Hb), self.K,
+                int(iters), float(eps), float(rho), int(bool(normalize)), int(warm),
+                int(bool(update_w)), ctypes.byref(loss), ctypes.byref(dw))
         if fl < 0:
             raise MemoryError("oracle allocation failed")
         self.t += b

@@ -27,7 +27,9 @@
  *    (section 2.3, scaling past data; identical to Algorithm 1 at rho = 1);
  *  - column rescaling uses the L1 sum s_k = sum_f W_fk (Algorithm 1);
  *  - 0/0 guards: when a denominator is zero the old value is kept and the
- *    event is counted in the returned flag count.
+ *    event is counted in the returned flag count;
+ *  - penalty on H (section 2.2, Extensions): psi(s) = lambda log(a + s) of
+ *    the column sum, entering the h update through its tangent.
  *
  * Parity pins: see tests/test_oracle_pins.py.  Every function below is
  * pinned there by a closed form, an invariant or a stated property of the
@@ -403,4 +405,126 @@ int isnmf_ref_batch_cycle(int F, int K, int N,
         *obj = isnmf_ref_objective(F, K, N, V, ldv, W, ldw, H, ldh, eps);
     free(X); free(A); free(B); free(G);
     return flags;
+}
+
+/* ------------------------------------------------------------------------
+ * Penalty on H (section 2.2, Extensions): a decomposable penalty
+ * Psi(H) = sum_n psi(sum_k H_kn) with psi concave and increasing.  The paper
+ * names the family, not a psi; the reading here is the log penalty
+ *   psi(s) = lambda * log(a + s),   lambda >= 0, a > 0
+ * (lambda = 0 is the plain method).  The inner problem of a frame becomes
+ *   min_h  d_IS(eps + v, eps + W h) + psi(sum_k h_k).
+ * A concave psi lies below its tangent, so at the current h (s = sum_k h_k)
+ *   psi(sum_k h'_k) <= psi(s) + psi'(s) (sum_k h'_k - s),
+ * a term linear in h'.  Added to the IS auxiliary function of h (the
+ * majorizer behind the update of section 2.1), whose h'_k-part is
+ * num_k h_k^2 / h'_k + den_k h'_k, it moves psi'(s) into den_k:
+ *   h_k <- h_k * sqrt(num_k / (den_k + psi'(s))),  psi'(s) = lambda / (a + s),
+ * still a descent step of the penalized inner objective.
+ * ------------------------------------------------------------------------ */
+
+/* The penalized inner objective of one frame:
+ *   sum_f d_IS(eps + v_f, eps + (W h)_f) + lambda * log(a + sum_k h_k).  */
+double isnmf_ref_pen_objective_h(int F, int K, const double *v, const double *W, long ldw,
+                                 const double *h, double eps, double lambda, double a)
+{
+    double total = 0.0, s = 0.0;
+    for (int f = 0; f < F; ++f) {
+        double x = eps;
+        for (int k = 0; k < K; ++k)
+            x += W[IX(f, k, ldw)] * h[k];
+        total += isnmf_ref_dis_term(eps + v[f], x);
+    }
+    for (int k = 0; k < K; ++k)
+        s += h[k];
+    return total + lambda * log(a + s);
+}
+
+/* The penalized inner fit: as isnmf_ref_fit_h with psi'(s) added to every
+ * den_k, s the sum of h at the start of the update.  Returns the number of
+ * guarded 0/0 events. */
+int isnmf_ref_fit_h_pen(int F, int K, const double *v, const double *W, long ldw,
+                        double *h, int iters, double eps, double lambda, double a, double *x)
+{
+    int flags = 0;
+    for (int it = 0; it < iters; ++it) {
+        double s = 0.0;
+        for (int k = 0; k < K; ++k)
+            s += h[k];
+        const double dpsi = lambda / (a + s);
+        for (int f = 0; f < F; ++f) {
+            double t = eps;
+            for (int k = 0; k < K; ++k)
+                t += W[IX(f, k, ldw)] * h[k];
+            x[f] = t;
+        }
+        for (int k = 0; k < K; ++k) {
+            double num = 0.0, den = 0.0;
+            for (int f = 0; f < F; ++f) {
+                double wf = W[IX(f, k, ldw)];
+                num += wf * (eps + v[f]) / (x[f] * x[f]);
+                den += wf / x[f];
+            }
+            den += dpsi;
+            if (den > 0.0 && num >= 0.0)
+                x[F + k] = sqrt(num / den);
+            else {
+                x[F + k] = 1.0;
+                ++flags;
+            }
+        }
+        for (int k = 0; k < K; ++k)
+            h[k] *= x[F + k];
+    }
+    return flags;
+}
+
+/*
+ * One online step with the penalty on H: isnmf_ref_online_step with the
+ * penalized inner fit.  The statistics a, b of eq. (4), the fold, the
+ * dictionary update and the rescale are those of Algorithm 1 (the penalty
+ * involves H only, so the auxiliary function of W is unchanged); the frame
+ * losses added to *loss_sum are the d_IS terms alone.
+ */
+int isnmf_ref_online_step_pen(int F, int K, int b,
+                              const double *V, long ldv,
+                              double *W, long ldw,
+                              double *A, double *B,
+                              double *H, long ldh,
+                              int iters, double eps, double rho,
+                              int normalize, int warm, int update_w,
+                              double lambda, double a_psi,
+                              double *loss_sum, double *dw_norm)
+{
+    /* the fit of every frame first, then the unpenalized step from those h
+     * with no further updates (iters = 0, warm) */
+    int flags = 0;
+    double *Hfit = (double *)malloc(sizeof(double) * (size_t)K * (b > 0 ? b : 1));
+    if (!Hfit)
+        return -1;
+#pragma omp parallel for schedule(static) num_threads(g_threads) reduction(+ : flags)
+    for (int n = 0; n < b; ++n) {
+        double *h = Hfit + (size_t)n * K;
+        double *scratch = (double *)malloc(sizeof(double) * (size_t)(F + K));
+        for (int k = 0; k < K; ++k)
+            h[k] = warm ? H[IX(k, n, ldh)] : 1.0;
+        flags += isnmf_ref_fit_h_pen(F, K, V + (size_t)n * ldv, W, ldw, h, iters, eps, lambda,
+                                     a_psi, scratch);
+        free(scratch);
+    }
+    for (int n = 0; n < b; ++n)
+        for (int k = 0; k < K; ++k)
+            H[IX(k, n, ldh)] = Hfit[IX(k, n, K)];
+    /* warm = 1 keeps the fitted h as the starting point of zero updates; the
+     * rescale then compensates H, which only warm restarts ask for */
+    const int f2 = isnmf_ref_online_step(F, K, b, V, ldv, W, ldw, A, B, H, ldh, 0, eps, rho,
+                                         normalize, 1, update_w, loss_sum, dw_norm);
+    if (!warm)
+        for (int n = 0; n < b; ++n)
+            for (int k = 0; k < K; ++k)
+                H[IX(k, n, ldh)] = Hfit[IX(k, n, K)];
+    free(Hfit);
+    if (f2 < 0)
+        return f2;
+    return flags + f2;
 }

@@ -416,6 +416,148 @@ def test_multipass_visits_keep_each_frames_own_h():
     assert _relerr(H2[:, swap], H) < 1e-14
 
 
+# ---------------------------------------------------------------- penalty on H (section 2.2, Extensions)
+# Reading: psi(s) = lam * log(a + s), a concave increasing function of the
+# column sum s = sum_k h_k; the inner update moves psi'(s) = lam / (a + s) into
+# every den_k.
+
+def _pen_root_K1(F, m, lam, a):
+    """K = 1, eps = 0: the penalized inner objective F (m / h + log h) + lam log(a + h)
+    (up to constants) is stationary where g(h) = F h + lam h^2 / (a + h) - F m = 0;
+    g rises strictly in h > 0, so bisection finds the one root."""
+    lo, hi = 0.0, m
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if F * mid + lam * mid * mid / (a + mid) - F * m > 0.0:
+            hi = mid
+        else:
+            lo = mid
+    return 0.5 * (lo + hi)
+
+
+def test_pen_lambda_zero_is_the_plain_fit():
+    V, W, _ = _rand_problem(23, 4, 2, seed=30)
+    for n in range(2):
+        for a in (0.5, 3.0):
+            hp, fp = oracle.fit_h_pen(V[:, n], W, 0.0, a, iters=9)
+            h0, f0 = oracle.fit_h(V[:, n], W, iters=9)
+            assert np.array_equal(hp, h0) and fp == f0 == 0
+
+
+@pytest.mark.parametrize("lam,a", [(1.0, 0.5), (10.0, 2.0), (40.0, 0.01), (0.3, 30.0)])
+def test_pen_K1_fixed_point_is_the_stationary_point(lam, a):
+    """K = 1, eps = 0: the update is h <- h sqrt((F m / h^2) / (F / h + lam / (a + h))),
+    whose fixed point solves F m = F h + lam h^2 / (a + h), the stationary point of
+    the penalized objective.  A dropped a, a wrong power of (a + s) or psi' taken
+    after the update moves the limit."""
+    rng = np.random.default_rng(31)
+    F = 29
+    w = rng.uniform(0.1, 2.0, size=(F, 1))
+    v = rng.gamma(0.5, 3.0, size=F) + 1e-3
+    m = float(np.mean(v / w[:, 0]))
+    h, fl = oracle.fit_h_pen(v, w, lam, a, iters=400, eps=0.0)
+    assert fl == 0
+    want = _pen_root_K1(F, m, lam, a)
+    assert want < m
+    assert abs(h[0] - want) <= 1e-12 * want
+
+
+@pytest.mark.parametrize("lam,a", [(2.0, 1.0), (50.0, 0.1)])
+def test_pen_fit_monotone_descent(lam, a):
+    """The tangent of the concave psi majorizes it, so the penalized update is a
+    majorize-minimize step: d_IS + psi never rises."""
+    V, W, _ = _rand_problem(40, 6, 3, seed=32)
+    eps = 1e-12
+    for n in range(3):
+        prev = np.inf
+        for it in range(0, 60):
+            h, _ = oracle.fit_h_pen(V[:, n], W, lam, a, iters=it, eps=eps)
+            obj = oracle.pen_objective_h(V[:, n], W, h, lam, a, eps)
+            want = oracle.dis(V[:, n], W @ h, eps) + lam * math.log(a + h.sum())
+            assert abs(obj - want) <= 1e-13 * abs(want)
+            assert obj <= prev * (1 + 1e-13) + 1e-300
+            prev = obj
+
+
+def test_pen_fit_converges_to_stationary_point():
+    """Large I: num_k = den_k + lam / (a + sum h) wherever h_k stays positive,
+    num_k <= den_k + lam / (a + sum h) where it does not."""
+    V, W, _ = _rand_problem(30, 3, 1, seed=33)
+    v = V[:, 0]
+    lam, a = 5.0, 0.7
+    h, _ = oracle.fit_h_pen(v, W, lam, a, iters=6000, eps=0.0)
+    x = W @ h
+    num = W.T @ (v / x ** 2)
+    den = W.T @ (1.0 / x) + lam / (a + h.sum())
+    act = h > 1e-6 * h.max()
+    assert act.any()
+    assert np.all(np.abs(num[act] / den[act] - 1.0) < 1e-9)
+    assert np.all(num[~act] <= den[~act] * (1 + 1e-9))
+
+
+def test_pen_fit_matches_bruteforce_minimum():
+    """Tiny K = 2: the penalized MU limit reaches the minimum of d_IS + lam log(a + s)
+    found by a derivative-free search, and the penalty shrinks sum h below the
+    unpenalized minimizer's (psi increasing)."""
+    scipy_opt = pytest.importorskip("scipy.optimize")
+    rng = np.random.default_rng(34)
+    F = 8
+    W = rng.uniform(0.2, 1.0, size=(F, 2))
+    v = (W @ np.array([1.7, 0.4])) * rng.exponential(1.0, size=F) + 1e-3
+    lam, a = 3.0, 0.5
+
+    def obj(z):
+        hh = np.exp(z)
+        x = W @ hh
+        return float(np.sum(v / x - np.log(v / x) - 1)) + lam * math.log(a + hh.sum())
+
+    best = min((scipy_opt.minimize(obj, np.log(s), method="Nelder-Mead",
+                                   options=dict(xatol=1e-12, fatol=1e-15, maxiter=20000))
+                for s in ([1.0, 1.0], [0.1, 3.0], [3.0, 0.1])), key=lambda r: r.fun)
+    h, _ = oracle.fit_h_pen(v, W, lam, a, iters=20000, eps=0.0)
+    assert oracle.pen_objective_h(v, W, h, lam, a, 0.0) <= best.fun + 1e-10
+    assert np.allclose(h, np.exp(best.x), rtol=2e-4)
+    h0, _ = oracle.fit_h(v, W, iters=20000, eps=0.0)
+    assert h.sum() < h0.sum()
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_pen_step_statistics_are_eq3_at_the_penalized_h(warm):
+    """The penalty involves H only: a penalized step with W frozen, rho = 1 and
+    A0 = B0 = 0 leaves the statistics of eq. (3) at (W0, H) with H the penalized
+    inner fit of each frame, and the loss is the d_IS part alone."""
+    V, W0, H0 = _rand_problem(19, 4, 9, seed=35)
+    eps, lam, a = 1e-12, 4.0, 0.3
+    st = oracle.OnlineState(W0)
+    Hb, _, fl = st.step(V, iters=11, eps=eps, update_w=False, psi=(lam, a),
+                        H=H0 if warm else None)
+    assert fl == 0
+    for n in range(9):
+        hn, _ = oracle.fit_h_pen(V[:, n], W0, lam, a, h0=H0[:, n] if warm else None,
+                                 iters=11, eps=eps)
+        assert np.array_equal(Hb[:, n], hn)
+    A, B = oracle.batch_stats(V, W0, Hb, eps)
+    assert _relerr(st.A, A) < 1e-14
+    assert _relerr(st.B, B) < 1e-14
+    assert abs(st.loss_sum - oracle.objective(V, W0, Hb, eps) * 9) <= 1e-12 * st.loss_sum
+
+
+def test_pen_step_with_w_update_rescales_warm_h():
+    """With the W update and the L1 rescale, a warm penalized step returns H scaled
+    by the column sums of sqrt(A/B), as the plain step does (W H unchanged)."""
+    V, W0, H0 = _rand_problem(15, 3, 6, seed=36)
+    eps, lam, a = 1e-12, 2.0, 1.0
+    st = oracle.OnlineState(W0)
+    Hb, _, _ = st.step(V, iters=5, eps=eps, psi=(lam, a), H=H0)
+    hf = np.stack([oracle.fit_h_pen(V[:, n], W0, lam, a, h0=H0[:, n], iters=5, eps=eps)[0]
+                   for n in range(6)], axis=1)
+    A, B = oracle.batch_stats(V, W0, hf, eps)
+    Wn = np.sqrt(A / B)
+    s = Wn.sum(axis=0)
+    assert _relerr(st.W, Wn / s) < 1e-14
+    assert _relerr(Hb, hf * s[:, None]) < 1e-14
+
+
 # ---------------------------------------------------------------- generator statistics
 
 def test_objective_at_true_factors_is_euler_gamma():
