@@ -74,7 +74,19 @@ typedef enum {
 
 /* Parameters of Algorithm 1.  Defaults (isnmf_params_default):
  * eps 1e-12, inner_iters 20, rho 1, normalize 1, h_init ONES, precision
- * FP32, kernel AUTO, update_w 1. */
+ * FP32, kernel AUTO, update_w 1, psi_lambda 0, psi_a 1.
+ *
+ * Penalty on H (section 2.2, Extensions: a concave increasing psi of each
+ * column sum).  With psi_lambda > 0 every inner fit minimizes
+ *   d_IS(eps + v, eps + W h) + psi_lambda * log(psi_a + sum_k h_k)
+ * by the majorize-minimize update with the penalty's tangent:
+ *   h_k <- h_k * sqrt(num_k / (den_k + psi_lambda / (psi_a + sum_j h_j))),
+ * the sum taken at the start of the update.  The statistics, the fold and
+ * the W update are unchanged (the penalty involves H only), and the frame
+ * losses stay the d_IS terms.  Supported by FP64 and FP32 handles (FP32 runs
+ * the VALU fit variant when the shape has one, F <= 1088 and K <= 64, else
+ * the plain path); BF16/FP16 handles, isnmf_batch_mu, the batched and the
+ * served forms return ISNMF_EUNSUPPORTED for psi_lambda > 0. */
 typedef struct {
     double eps;        /* eps >= 0: shift of the small-amplitude remedy (section 2.3)     */
     int inner_iters;   /* >= 0: multiplicative updates of h per frame                     */
@@ -84,6 +96,8 @@ typedef struct {
     int precision;     /* isnmf_precision                                                 */
     int kernel;        /* isnmf_kernel                                                    */
     int update_w;      /* 1: W <- sqrt(A/B); 0: W frozen, statistics still accumulate     */
+    double psi_lambda; /* >= 0: weight of the penalty on H above; 0: none                 */
+    double psi_a;      /* > 0: offset a of psi(s) = psi_lambda * log(a + s)               */
 } isnmf_params;
 
 typedef struct isnmf_online isnmf_online;   /* opaque handle */

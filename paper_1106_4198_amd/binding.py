@@ -30,7 +30,8 @@ KERNEL_NAME = {v: k for k, v in KERNEL.items()}
 class Params(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("inner_iters", ctypes.c_int), ("rho", ctypes.c_double),
                 ("normalize", ctypes.c_int), ("h_init", ctypes.c_int), ("precision", ctypes.c_int),
-                ("kernel", ctypes.c_int), ("update_w", ctypes.c_int)]
+                ("kernel", ctypes.c_int), ("update_w", ctypes.c_int),
+                ("psi_lambda", ctypes.c_double), ("psi_a", ctypes.c_double)]
 
 
 class IsnmfError(RuntimeError):
@@ -158,9 +159,13 @@ def forgetting_rho(r: float, beta: int, n_frames: int) -> float:
 
 
 def make_params(eps=1e-12, inner_iters=20, rho=1.0, normalize=True, warm=False,
-                precision="fp32", kernel="auto", update_w=True) -> Params:
+                precision="fp32", kernel="auto", update_w=True, psi=None) -> Params:
+    """psi: None, or (lambda, a) of the penalty lambda log(a + sum_k h_k) on H."""
     p = Params()
     _lib.isnmf_params_default(ctypes.byref(p))
+    if psi is not None:
+        p.psi_lambda = float(psi[0])
+        p.psi_a = float(psi[1])
     p.eps = float(eps)
     p.inner_iters = int(inner_iters)
     p.rho = float(rho)
@@ -203,12 +208,12 @@ class OnlineISNMF:
 
     def __init__(self, W0: torch.Tensor, b_max: int, *, eps=1e-12, inner_iters=20, rho=1.0,
                  normalize=True, warm=False, precision="fp32", kernel="auto", update_w=True,
-                 A0=None, B0=None, stream=None):
+                 A0=None, B0=None, stream=None, psi=None):
         _req(W0, torch.float32, name="W0")
         K, F = W0.shape
         self.F, self.K, self.b_max = int(F), int(K), int(b_max)
         self.params = make_params(eps, inner_iters, rho, normalize, warm, precision, kernel,
-                                  update_w)
+                                  update_w, psi)
         self.warm = bool(warm)
         nbytes = _lib.isnmf_online_workspace_size(self.F, self.K, self.b_max,
                                                   ctypes.byref(self.params))

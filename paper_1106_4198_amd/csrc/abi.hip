@@ -40,6 +40,8 @@ bool params_ok(const isnmf_params &p) {
     if (p.h_init != ISNMF_H_ONES && p.h_init != ISNMF_H_WARM) return false;
     if (p.precision < ISNMF_FP32 || p.precision > ISNMF_FP64) return false;
     if (p.kernel < ISNMF_KERNEL_AUTO || p.kernel > ISNMF_KERNEL_FUSED) return false;
+    if (!(p.psi_lambda >= 0.0) || !isfinite(p.psi_lambda)) return false;
+    if (!(p.psi_a > 0.0) || !isfinite(p.psi_a)) return false;
     return true;
 }
 
@@ -92,7 +94,9 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
     t.R1 = take((size_t)b_max * FR * es);
     t.R2 = take((size_t)b_max * FR * es);
     t.Hi = take((size_t)b_max * KP * es);
-    t.Xt = nullptr;
+    t.psi_lambda = p.psi_lambda;
+    t.psi_a = p.psi_a;
+    t.hsum = p.psi_lambda > 0.0 ? take((size_t)b_max * es) : nullptr;
     t.lossel = with_lossel ? (double *)take((size_t)b_max * FR * 8) : nullptr;
     const size_t pb = fold_partial_bytes(F, K, b_max);
     t.part = pb ? (float *)take(pb) : nullptr;
@@ -103,9 +107,13 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
     return off;
 }
 
+bool penalized(const isnmf_params &p) { return p.psi_lambda > 0.0; }
+
+// With the penalty on H the fused fit is the VALU variant (FP32 only).
 int use_fused(const isnmf_params &p, int F, int K) {
     if (p.precision == ISNMF_FP64) return 0;
     if (p.kernel == ISNMF_KERNEL_PLAIN) return 0;
+    if (penalized(p)) return p.precision == ISNMF_FP32 && valu_class(F, K).ok ? 1 : 0;
     return fused_supported(F, K, prec_code(p)) ? 1 : 0;
 }
 
@@ -193,6 +201,8 @@ void isnmf_params_default(isnmf_params *p) {
     p->precision = ISNMF_FP32;
     p->kernel = ISNMF_KERNEL_AUTO;
     p->update_w = 1;
+    p->psi_lambda = 0.0;
+    p->psi_a = 1.0;
 }
 
 const char *isnmf_strerror(int status) {
@@ -234,6 +244,7 @@ int isnmf_online_init(isnmf_online **out, int F, int K, int b_max, const isnmf_p
     if ((p.kernel == ISNMF_KERNEL_FUSED || is16(p)) && !use_fused(p, F, K))
         return ISNMF_EUNSUPPORTED;
     if (is16(p) && p.kernel == ISNMF_KERNEL_PLAIN) return ISNMF_EUNSUPPORTED;
+    if (is16(p) && penalized(p)) return ISNMF_EUNSUPPORTED;
     const size_t need = carve_online(F, K, b_max, p, true, nullptr, nullptr);
     if (ws_bytes < need) return ISNMF_ENOMEM;
     isnmf_online *h = new (std::nothrow) isnmf_online;
@@ -243,7 +254,7 @@ int isnmf_online_init(isnmf_online **out, int F, int K, int b_max, const isnmf_p
     h->t = 0;
     h->last = (hipStream_t)stream;
     h->kernel_used = use_fused(p, F, K) ? ISNMF_KERNEL_FUSED : ISNMF_KERNEL_PLAIN;
-    h->cls = tuned_class(F, K, prec_code(p), b_max);
+    h->cls = penalized(p) ? valu_class(F, K) : tuned_class(F, K, prec_code(p), b_max);
     h->d.w16_rows = h->cls.cpw != -1;   // the 16-frame tile variant reads only W16c
     hipStream_t s = (hipStream_t)stream;
     const size_t fk8 = sizeof(double) * (size_t)F * K;
@@ -499,6 +510,7 @@ int isnmf_batch_mu(const float *V, int ldv, int F, int N, float *W, int ldw, flo
     if (((uintptr_t)workspace & 255) != 0) return ISNMF_EINVAL;
     if (is16(p) && (p.kernel == ISNMF_KERNEL_PLAIN || !use_fused(p, F, K)))
         return ISNMF_EUNSUPPORTED;
+    if (penalized(p)) return ISNMF_EUNSUPPORTED;
     if (ws_bytes < isnmf_batch_workspace_size(F, K, N, &p)) return ISNMF_ENOMEM;
     // an online handle over the whole set: beta = N, rho = 0, warm restarts,
     // one h update per cycle (section 2.3, overview).

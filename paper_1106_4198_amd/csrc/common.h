@@ -67,7 +67,10 @@ struct OnlineDev {
     double *lossf;       // b_max: per-frame loss of the current minibatch
     void *R1, *R2;       // b_max x FR (float, or double in FP64 mode): 1/x and (eps+v)/x^2
     void *Hi;            // b_max x KP (float or double): fitted h of the minibatch
-    void *Xt;            // plain path scratch: b_max x FR model values / loss terms
+    void *hsum;          // plain path with the penalty on H: b_max column sums of H
+                         // (float, or double in FP64 mode), else null
+    double psi_lambda;   // penalty on H: psi(s) = psi_lambda log(psi_a + s) of each
+    double psi_a;        // column sum (psi_lambda = 0: none)
     double *lossel;      // plain path: b_max x FR per-element loss terms
     float *part;         // fold slice partials (b_max > 512) or null
     float *Vg, *Hg;      // warm multi-pass: gathered minibatch frames (b_max x F) and h
@@ -84,6 +87,7 @@ struct FitDesc {
     int tail;          // rows after them on the VALU (<= TAIL_MAX)
     int FR, KP;
     float eps, wscale, hscale;
+    float psi_lambda, psi_a;   // penalty on H (VALU variant only; 0 elsewhere)
     double epsd;
     const float *V;            // frame 0 of the minibatch
     const float *W;            // F x K, ld F (FP32 working copy)

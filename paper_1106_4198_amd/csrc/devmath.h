@@ -81,6 +81,14 @@ __device__ inline double wave_sum_f64(double v) {
     return join_f64(l32[0], h32[0]) + join_f64(l32[1], h32[1]);
 }
 
+// Sum over the wave in a fixed order (same value in every lane): the xor
+// butterfly over lane bits 0..5.
+__device__ inline float wave_sum_f32(float v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
 // Sum over the 16 lanes that share (lane & 3): xor butterfly over lane bits
 // 2..5.  Every lane of the group ends with the same, order-independent value.
 __device__ inline double sum_over_quads(double v) {

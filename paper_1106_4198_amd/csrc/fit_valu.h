@@ -179,11 +179,17 @@ __device__ inline void body(const FitDesc &a, int fr) {
             }
         }
         __syncthreads();
+        // penalty on H (section 2.2, Extensions): psi'(s) = lambda / (a + s) of
+        // the column sum before the update joins every den_k.  K <= 64, so the
+        // lanes t < K are wave 0's, which reads hsh before it writes it.
+        float dpsi = 0.f;
+        if (a.psi_lambda > 0.f && w == 0)
+            dpsi = a.psi_lambda / (a.psi_a + wave_sum_f32(lane < K ? hsh[lane] : 0.f));
         if (t < K) {
             const float4 *pk = red4 + t * (KS / 4);
             const float4 n0 = pk[0], n1 = pk[1], d0 = pk[2], d1 = pk[3];
             const float N = ((n0.x + n0.y) + (n0.z + n0.w)) + ((n1.x + n1.y) + (n1.z + n1.w));
-            const float D = ((d0.x + d0.y) + (d0.z + d0.w)) + ((d1.x + d1.y) + (d1.z + d1.w));
+            const float D = ((d0.x + d0.y) + (d0.z + d0.w)) + ((d1.x + d1.y) + (d1.z + d1.w)) + dpsi;
             float h = hsh[t];
             if (D > 0.f && N >= 0.f)
                 h *= __builtin_amdgcn_sqrtf(N * __builtin_amdgcn_rcpf(D));

@@ -125,6 +125,8 @@ FitDesc make_fit_desc(const OnlineDev &d, const float *V, int ldv, int b, int it
     a.FR = d.FR;
     a.KP = d.KP;
     a.eps = float(eps);
+    a.psi_lambda = float(d.psi_lambda);
+    a.psi_a = float(d.psi_a);
     a.epsd = eps;
     a.wscale = ldexpf(1.f, d.wexp);
     a.hscale = ldexpf(1.f, -d.wexp);
@@ -148,6 +150,7 @@ hipError_t launch_fused_fit(const OnlineDev &d, const FitClass &c, const float *
     if (!c.ok) return hipErrorNotSupported;
     const FitDesc a = make_fit_desc(d, V, ldv, b, iters, eps, warm, Hb, ldh);
     if (c.cpw == 0) return prec == 0 ? launch_fit_valu(a, c, b, s) : hipErrorNotSupported;
+    if (d.psi_lambda > 0.0) return hipErrorNotSupported;   // penalty: VALU variant only
     if (c.cpw == -1) return prec == 1 ? launch_fit_tile(a, c, b, s) : hipErrorNotSupported;
     if (c.cpw == -2) return prec == 1 ? launch_fit_stile(a, c, b, s) : hipErrorNotSupported;
     if (c.cpw == -3) return prec == 0 ? launch_fit_t32(a, c, b, s) : hipErrorNotSupported;

@@ -314,6 +314,7 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         if (ldv[s] < d.F || b[s] > d.b_max) return ISNMF_EINVAL;
         if (p.h_init == ISNMF_H_WARM) return ISNMF_EINVAL;            // fresh restarts only
         if (isnmf_handle_kernel(handles[s]) != ISNMF_KERNEL_FUSED) return ISNMF_EUNSUPPORTED;
+        if (p.psi_lambda > 0.0) return ISNMF_EUNSUPPORTED;            // no penalty on H
         if (b[s] > 512) return ISNMF_EUNSUPPORTED;                   // single fold slice
         if (isnmf_handle_class(handles[s])->cpw == 0 && !d.Wv) return ISNMF_EUNSUPPORTED;
         for (int r = 0; r < s; ++r)

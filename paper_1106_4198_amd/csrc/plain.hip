@@ -6,6 +6,9 @@
 // Algorithm 1, inner argmin with the eps shift of section 2.3):
 //   x_f = eps + sum_k W_fk h_k,  r1_f = 1/x_f,  r2_f = (eps + v_f) r1_f^2
 //   h_k <- h_k sqrt( sum_f W_fk r2_f / sum_f W_fk r1_f )
+// With the penalty on H (section 2.2, Extensions; psi(s) = lambda log(a + s)
+// of the column sum s = sum_k h_k), lambda / (a + s) joins the denominator,
+// s taken before the update.
 #include <type_traits>
 
 #include "common.h"
@@ -46,11 +49,23 @@ __global__ void plain_model(int F, int K, int b, const float *__restrict__ V, in
     if (lossel) lossel[(size_t)n * FR + f] = dis_term(double(eps) + double(vin), double(x));
 }
 
-// num/den and the multiplicative update of h.  Thread per (k, n).
+// Column sums of H in index order (penalty on H).  Thread per frame.
+template <typename T>
+__global__ void plain_hsum(int K, int b, int KP, const T *__restrict__ H, T *__restrict__ S) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= b) return;
+    T s = T(0);
+    for (int k = 0; k < K; ++k) s += H[(size_t)n * KP + k];
+    S[n] = s;
+}
+
+// num/den and the multiplicative update of h.  Thread per (k, n).  S: null,
+// or the column sums for the penalty term lambda / (a + S[n]).
 template <typename T>
 __global__ void plain_numden(int F, int K, int b, const T *__restrict__ W,
                              const T *__restrict__ R1, const T *__restrict__ R2, int FR,
-                             T *__restrict__ H, int KP, int *__restrict__ flags) {
+                             T *__restrict__ H, int KP, const T *__restrict__ S, T lam, T pa,
+                             int *__restrict__ flags) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = blockIdx.y;
     if (k >= K || n >= b) return;
@@ -62,6 +77,7 @@ __global__ void plain_numden(int F, int K, int b, const T *__restrict__ W,
         num += wk[f] * r2[f];
         den += wk[f] * r1[f];
     }
+    if (S) den += lam / (pa + S[n]);
     T hk = H[(size_t)n * KP + k];
     if (den > T(0) && num >= T(0))
         hk *= sqrt(num / den);
@@ -105,12 +121,16 @@ hipError_t launch_plain_fit(const OnlineDev &d, const float *V, int ldv, int b, 
     T *R1 = (T *)d.R1;
     T *R2 = (T *)d.R2;
     const T e = T(eps);
+    T *S = d.psi_lambda > 0.0 ? (T *)d.hsum : nullptr;
+    if (d.psi_lambda > 0.0 && !S) return hipErrorInvalidValue;
     dim3 gk((d.KP + 63) / 64, b), gf((d.F + 255) / 256, b), gkk((d.K + 63) / 64, b);
     plain_hinit<T><<<gk, 64, 0, s>>>(d.K, b, d.KP, warm, Hb, ldh, H);
     for (int it = 0; it < iters; ++it) {
         plain_model<T><<<gf, 256, 0, s>>>(d.F, d.K, b, V, ldv, W, H, d.KP, e, R1, R2, d.FR,
                                           nullptr, d.flags);
-        plain_numden<T><<<gkk, 64, 0, s>>>(d.F, d.K, b, W, R1, R2, d.FR, H, d.KP, d.flags);
+        if (S) plain_hsum<T><<<(b + 63) / 64, 64, 0, s>>>(d.K, b, d.KP, H, S);
+        plain_numden<T><<<gkk, 64, 0, s>>>(d.F, d.K, b, W, R1, R2, d.FR, H, d.KP, S,
+                                           T(d.psi_lambda), T(d.psi_a), d.flags);
     }
     plain_model<T><<<gf, 256, 0, s>>>(d.F, d.K, b, V, ldv, W, H, d.KP, e, R1, R2, d.FR,
                                       d.lossel, d.flags);

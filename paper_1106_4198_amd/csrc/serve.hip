@@ -521,6 +521,7 @@ int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *s
     const isnmf_params &p = *isnmf_handle_params(h);
     if (p.h_init == ISNMF_H_WARM) return ISNMF_EINVAL;
     if (isnmf_handle_kernel(h) != ISNMF_KERNEL_FUSED) return ISNMF_EUNSUPPORTED;
+    if (p.psi_lambda > 0.0) return ISNMF_EUNSUPPORTED;   // no penalty on H
     const OnlineDev &d = *isnmf_handle_dev(h);
     const FitClass &c = *isnmf_handle_class(h);
     const bool tile16 = ((c.cpw == -1 || c.cpw == -2) && prec_of(p) == 1) ||

@@ -54,6 +54,14 @@ def test_defaults_and_strerror():
     assert bd.strerror(-99) == "unknown status"
 
 
+def test_params_default_has_no_penalty():
+    from paper_1106_4198_amd import binding as bd
+    p = bd.make_params()
+    assert p.psi_lambda == 0.0 and p.psi_a == 1.0
+    q = bd.make_params(psi=(2.5, 0.25))
+    assert q.psi_lambda == 2.5 and q.psi_a == 0.25
+
+
 def test_workspace_sizes_are_host_only_and_grow():
     from paper_1106_4198_amd import binding as bd
     L = bd.lib()
@@ -85,6 +93,18 @@ def test_einval_before_any_device_work():
     assert L.isnmf_online_init(ctypes.byref(h), 10, 2, 4, ctypes.byref(bad), fake, 10, None, None, fake, 1 << 20, None) == bd.EINVAL
     bad = bd.make_params(inner_iters=-1)
     assert L.isnmf_online_init(ctypes.byref(h), 10, 2, 4, ctypes.byref(bad), fake, 10, None, None, fake, 1 << 20, None) == bd.EINVAL
+    # penalty on H: lambda >= 0 and a > 0, finite
+    for psi in ((-1.0, 1.0), (1.0, 0.0), (1.0, -2.0), (float("nan"), 1.0), (1.0, float("inf"))):
+        bad = bd.make_params(psi=psi)
+        assert L.isnmf_online_init(ctypes.byref(h), 10, 2, 4, ctypes.byref(bad), fake, 10, None, None, fake, 1 << 20, None) == bd.EINVAL, psi
+    # the penalty is refused by the 16-bit forms and by the batch MU
+    for prec in ("bf16", "fp16"):
+        pen = bd.make_params(precision=prec, psi=(1.0, 1.0))
+        assert L.isnmf_online_init(ctypes.byref(h), 64, 8, 4, ctypes.byref(pen), fake, 64, None, None, fake, 1 << 30, None) == bd.EUNSUPPORTED
+    pen = bd.make_params(kernel="fused", psi=(1.0, 1.0))       # no VALU variant at K = 65
+    assert L.isnmf_online_init(ctypes.byref(h), 10, 65, 4, ctypes.byref(pen), fake, 10, None, None, fake, 1 << 30, None) == bd.EUNSUPPORTED
+    pen = bd.make_params(psi=(1.0, 1.0))
+    assert L.isnmf_batch_mu(fake, 10, 10, 5, fake, 10, fake, 2, 2, 1, ctypes.byref(pen), None, fake, 1 << 30, None) == bd.EUNSUPPORTED
     # misaligned workspace
     assert L.isnmf_online_init(ctypes.byref(h), 10, 2, 4, ctypes.byref(p), fake, 10, None, None, ctypes.c_void_p(260), 1 << 20, None) == bd.EINVAL
     # too small workspace

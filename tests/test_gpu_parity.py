@@ -64,9 +64,9 @@ def run_step(g, Vb_fn, H0=None):
 
 
 def compare_step(F, K, b, iters, precision, kernel, seed, tol, warm=False, rho=1.0,
-                 normalize=True, update_w=True, steps_before=2, b_max=None):
+                 normalize=True, update_w=True, steps_before=2, b_max=None, psi=None):
     say(f"step F={F} K={K} b={b} I={iters} {precision}/{kernel} warm={warm} rho={rho} "
-        f"norm={normalize} upd={update_w} seed={seed}")
+        f"norm={normalize} upd={update_w} seed={seed} psi={psi}")
     st = make_state(F, K, seed, steps_before)
     Vb = synth.frames(F, K, b, seed + 1000)
     H0 = None
@@ -75,13 +75,13 @@ def compare_step(F, K, b, iters, precision, kernel, seed, tol, warm=False, rho=1
         H0 = H0.astype(np.float32).astype(np.float64)
     g = gpu_from_state(st, b_max or b, eps=1e-12, inner_iters=iters, rho=rho,
                        normalize=normalize, warm=warm, precision=precision, kernel=kernel,
-                       update_w=update_w)
+                       update_w=update_w, psi=psi)
     if kernel == "fused":
         assert g.kernel_used == "fused"
     Hg, lg, dwg = run_step(g, Vb, H0)
     ref = st.copy()
     Hr, dwr, fl = ref.step(Vb.astype(np.float64), iters=iters, rho=rho, normalize=normalize,
-                           H=H0, update_w=update_w)
+                           H=H0, update_w=update_w, psi=psi)
     assert fl == 0
     W64 = from_gpu_kf(g.get_w64())
     Wg, Ag, Bg, t = g.get()
