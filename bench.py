@@ -147,11 +147,12 @@ def cpu_baseline(V, W0, target_s: float, snaps=None, accuracy_steps: int = 0):
 PEAK_BF16_MFMA = 2500e12        # MI355X dense BF16 matrix peak, FLOP/s
 
 
-def form_accuracy(bd, torch, np, Vt, Wt, snaps, fp32_variant):
+def form_accuracy(bd, torch, np, Vt, Wt, snaps, fp32_variant, form_variants=None):
     """Relative error (Frobenius) of W, A, B and of the online loss sum against
     the FP64 oracle's snapshots, per form, at the checkpoints the oracle
     reached: each form runs the same stream prefix from W(0).  The FP32 fused
-    form runs fp32_variant (nw, cpw, wg), the fit variant of the timed pass."""
+    form runs fp32_variant (nw, cpw, wg), the fit variant of the timed pass,
+    and the 16-bit forms the variants they were timed on (form_variants)."""
     cps = sorted(snaps)
     out = {"checkpoints": cps, "reference": "FP64 oracle, same stream prefix from W(0)",
            "measure": "||x - x_oracle||_F / ||x_oracle||_F; loss: |sum - sum_oracle| / sum_oracle"}
@@ -162,6 +163,8 @@ def form_accuracy(bd, torch, np, Vt, Wt, snaps, fp32_variant):
         return float(np.linalg.norm(x - y) / np.linalg.norm(y))
 
     bd.tune_set(F, K, "fp32", *fp32_variant)
+    for p, v in (form_variants or {}).items():
+        bd.tune_set(F, K, p, *v)
     for name, kw in (("fp32", {}), ("bf16", {"precision": "bf16"}), ("fp16", {"precision": "fp16"}),
                      ("fp32_plain", {"kernel": "plain"})):
         g = bd.OnlineISNMF(Wt, B, inner_iters=ITERS, **kw)
@@ -585,8 +588,13 @@ def main() -> int:
         roofline["peak_unpacked_fp32"] = PEAK_FP32_VALU_UNPACKED / 1e12
         roofline["cus_used"] = min(B, 256)
 
-    # precision forms: BF16 / FP16 products, same stream prefix
+    # precision forms: BF16 / FP16 products, same stream prefix, each on the fit
+    # variant the autotuner picks for one minibatch
+    form_variants = {}
+
     def time_form(precision, nsteps):
+        bd.autotune(F, K, B, precision=precision, inner_iters=ITERS, trials=10)
+        form_variants[precision] = bd.tune_get(F, K, precision)
         gw = bd.OnlineISNMF(Wt, B, inner_iters=ITERS, precision=precision)
         gw.run_pass(Vt[:B * 4], B)
         gw.close()
@@ -608,6 +616,8 @@ def main() -> int:
     f_steps = max(1, min(args.form_steps, steps))
     forms = {p: {"value": time_form(p, f_steps), "unit": "frames/s", "steps": f_steps}
              for p in ("bf16", "fp16") if want(p)}
+    for p in forms:
+        forms[p]["variant"] = list(form_variants[p])
 
     # the plain FP32 path (one op per launch) over a prefix, same shapes
     plain_fps = None
@@ -695,7 +705,8 @@ def main() -> int:
     if not args.no_cpu:
         snaps = {}
         out["cpu_baseline"] = cpu_baseline(V, W0, args.cpu_seconds, snaps, args.accuracy_steps)
-        out["accuracy"] = form_accuracy(bd, torch, np, Vt, Wt, snaps, (nw, cpw, wg))
+        out["accuracy"] = form_accuracy(bd, torch, np, Vt, Wt, snaps, (nw, cpw, wg),
+                                       form_variants)
         print(f"[bench] accuracy vs the FP64 oracle: {out['accuracy']}", file=sys.stderr,
               flush=True)
     print(json.dumps(out), flush=True)

@@ -81,8 +81,8 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
     t.w16_kind = prec_code(p);
     t.w16_rows = 1;
     t.wexp = (int)lrint(log2((double)F));
-    // register-order copy for the VALU fit variant (FP32 shapes it covers)
-    const bool wv = p.precision == ISNMF_FP32 && valu_class(F, K).ok;
+    // register-order copy for the VALU fit variant (FP32 and BF16 shapes it covers)
+    const bool wv = (p.precision == ISNMF_FP32 || p.precision == ISNMF_BF16) && valu_class(F, K).ok;
     t.Wv = wv ? (float *)take(wv_floats(F, K) * 4) : nullptr;
     t.wv_ck = (K + 7) / 8;
     t.A = (double *)take(fk * 8);

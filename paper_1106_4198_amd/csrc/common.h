@@ -114,7 +114,7 @@ struct ServeWork {
 // fit_body.h (cpw >= 1: NW waves x CPW chunks of 64 rows, NF frames per
 // workgroup), the VALU variant of fit_valu.h (cpw = 0: one frame per
 // workgroup of nw = 8 waves, rf row sets and kmax / 8 components per
-// thread), the 16-frame tile variant of fit_tile.h (cpw = -1: BF16
+// thread; cpw = -4 is its BF16 form), the 16-frame tile variant of fit_tile.h (cpw = -1: BF16
 // products, nw = 8 waves of 16 frames each, rf = ceil(F / 32) contraction
 // steps of 32 rows, kmax = 32 ceil(K / 32)), its streamed form of
 // fit_stile.h (cpw = -2), or the FP32 16-frame tile variant of fit_t32.h
@@ -129,6 +129,9 @@ struct FitClass {
 FitClass fit_class(int F, int K, int prec);
 // The VALU variant for (F, K) with FP32 products, or ok = 0.
 FitClass valu_class(int F, int K);
+// The VALU variant with bf16 products on v_dot2c_f32_bf16 (cpw = -4; the
+// same shapes as valu_class), or ok = 0.
+FitClass vbf_class(int F, int K);
 // The 16-frame tile variant for (F, K) with BF16 products, or ok = 0.
 FitClass tile_class(int F, int K);
 FitClass stile_class(int F, int K);
@@ -161,6 +164,8 @@ bool fused_supported(int F, int K, int prec);
 // VALU variant launches (class from valu_class): b frames, or the frames of
 // n batched items of NF frames each.
 hipError_t launch_fit_valu(const FitDesc &a, const FitClass &c, int b, hipStream_t s);
+hipError_t launch_fit_valu_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
+                                int max_b, hipStream_t s);
 hipError_t launch_fit_valu_multi(const FitClass &c, const FitDesc *d, const int2 *items, int n,
                                  const long long *cur, const int *beff, hipStream_t s);
 // 16-frame tile variant launches: b frames, or n batched items (stream, tile of 16 frames).
@@ -182,8 +187,11 @@ hipError_t launch_fit_t32_multi(const FitClass &c, const FitDesc *d, const int2 
                                 const long long *cur, const int *beff, hipStream_t s);
 hipError_t launch_fit_t32_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
                                int tiles, hipStream_t s);
-// 16-frame tile variants (cpw -1 resident W, -2 streamed W, -3 FP32): 128 frames per item
-inline int frames_per_item(const FitClass &c) { return c.cpw < 0 ? 128 : NF; }
+// Frames per batched item: 128 for the 16-frame tile variants (8 waves of
+// 16), NF (the workgroups of one item) for the MFMA tile and VALU variants.
+inline int frames_per_item(const FitClass &c) {
+    return c.cpw == -1 || c.cpw == -2 || c.cpw == -3 ? 128 : NF;
+}
 // Every fit variant valid for the shape (the default first); returns the count.
 int fit_candidates(int F, int K, int prec, FitClass *out, int max_out);
 // The variant the autotuner chose for (F, K, prec, b), or the default.

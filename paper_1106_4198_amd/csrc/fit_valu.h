@@ -20,6 +20,15 @@
 //                  waves by the lane owning k (8 + 8 values from LDS).
 // Two workgroup barriers per update.  Every sum has a fixed order, so results
 // are bitwise repeatable and independent of the other frames of a launch.
+//
+// BF16 form (BF = true, the precision form's single-stream variant): the
+// products W h, W^T r2 and W^T r1 take bf16 operands two at a time on
+// v_dot2c_f32_bf16 (FP32 accumulation), with everything else (x, the ratios,
+// the reductions, h) in FP32 as above.  The thread keeps W twice as packed
+// bf16 pairs: pairs of components (c, c + 1) of one row for W h, and pairs of
+// row sets (r, r + 1) of one component for the transposed products, so each
+// product takes half the instructions.  bf16 has FP32's exponent range, so no
+// operand is scaled.
 #pragma once
 
 #include "common.h"
@@ -44,6 +53,20 @@ __device__ inline float sum8(float v) {
     return v;
 }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+// (a, b) rounded to bf16 (nearest even) in one word, a in the low half
+__device__ inline uint32_t pack_bf2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){a, b}, bf16x2));
+}
+
+// c + a.lo * b.lo + a.hi * b.hi with bf16 operands
+__device__ inline float dot2(uint32_t a, uint32_t b, float c) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a),
+                                           __builtin_bit_cast(bf16x2, b), c, false);
+}
+
 // a, b -> rows (a0+a1, b0+b1, a2+a3, b2+b3) of 16 lanes each
 __device__ inline float swap16_add(float a, float b) {
     auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
@@ -56,9 +79,11 @@ __device__ inline float swap32_add(float a, float b) {
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-template <int CK, int RF>
+template <int CK, int RF, bool BF>
 __device__ inline void body(const FitDesc &a, int fr) {
     constexpr int NV = 2 * CK;              // num/den values per thread
+    constexpr int CH = (CK + 1) / 2;        // BF16: component pairs per row set
+    constexpr int RH = (RF + 1) / 2;        // BF16: row-set pairs per component
     constexpr int NG = (CK + 1) / 2;        // registers after the in-wave reduction
     const int t = threadIdx.x;
     const int lane = t & 63;
@@ -94,6 +119,20 @@ __device__ inline void body(const FitDesc &a, int fr) {
                 if (4 * g + j < NE) wr[(4 * g + j) / CK][(4 * g + j) % CK] = e4[j];
         }
     }
+    // BF16: W as pairs of components (model) and pairs of row sets (W^T)
+    uint32_t wkp[BF ? RF : 1][BF ? CH : 1], wfp[BF ? RH : 1][BF ? CK : 1];
+    if constexpr (BF) {
+#pragma unroll
+        for (int r = 0; r < RF; ++r)
+#pragma unroll
+            for (int i = 0; i < CH; ++i)
+                wkp[r][i] = pack_bf2(wr[r][2 * i], 2 * i + 1 < CK ? wr[r][2 * i + 1] : 0.f);
+#pragma unroll
+        for (int j = 0; j < RH; ++j)
+#pragma unroll
+            for (int c = 0; c < CK; ++c)
+                wfp[j][c] = pack_bf2(wr[2 * j][c], 2 * j + 1 < RF ? wr[2 * j + 1][c] : 0.f);
+    }
     float ve[RF];   // eps + v (0 past F)
     int bad = 0;
 #pragma unroll
@@ -110,26 +149,37 @@ __device__ inline void body(const FitDesc &a, int fr) {
         hsh[t] = t < K ? (a.warm ? a.Hb[(size_t)fr * a.ldh + t] : 1.f) : 0.f;
     __syncthreads();
     float hk[CK];
+    uint32_t hkp[CH];   // BF16: h as pairs of components
+    auto load_h = [&]() {
 #pragma unroll
-    for (int c = 0; c < CK; ++c) hk[c] = hsh[q + 8 * c];
+        for (int c = 0; c < CK; ++c) hk[c] = hsh[q + 8 * c];
+        if constexpr (BF) {
+#pragma unroll
+            for (int i = 0; i < CH; ++i) hkp[i] = pack_bf2(hk[2 * i], 2 * i + 1 < CK ? hk[2 * i + 1] : 0.f);
+        }
+    };
+    load_h();
 
     // eps enters the sum once, in the q = 0 lane of each row
     const float s0 = q == 0 ? eps : 0.f;
     float x[RF];
-    auto model = [&]() {
+    auto row_model = [&](int r) {
+        float s = s0;
+        if constexpr (BF) {
 #pragma unroll
-        for (int r = 0; r < RL; ++r) {
-            float s = s0;
+            for (int i = 0; i < CH; ++i) s = dot2(wkp[r][i], hkp[i], s);
+        } else {
 #pragma unroll
             for (int c = 0; c < CK; ++c) s = fmaf(wr[r][c], hk[c], s);
-            x[r] = sum8(s);
         }
+        return sum8(s);
+    };
+    auto model = [&]() {
+#pragma unroll
+        for (int r = 0; r < RL; ++r) x[r] = row_model(r);
         x[RL] = 1.f;
         if (last_live) {
-            float s = s0;
-#pragma unroll
-            for (int c = 0; c < CK; ++c) s = fmaf(wr[RL][c], hk[c], s);
-            s = sum8(s);
+            const float s = row_model(RL);
             x[RL] = last_ok ? s : 1.f;   // rows past F: W = 0 and v' = 0, any x > 0
         }
     };
@@ -140,23 +190,47 @@ __device__ inline void body(const FitDesc &a, int fr) {
         float nd[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) nd[i] = 0.f;
+        if constexpr (BF) {
+            // ratios of the row sets in pairs; the last pair's second row set
+            // (RF odd) and the dead last row set of a wave give r1 = r2 = 0
+            // against W = 0 there
+            float r1v[2 * RH], r2v[2 * RH];
 #pragma unroll
-        for (int r = 0; r < RL; ++r) {
-            const float r1 = __builtin_amdgcn_rcpf(x[r]);
-            const float r2 = ve[r] * r1 * r1;
-#pragma unroll
-            for (int c = 0; c < CK; ++c) {
-                nd[2 * c] = fmaf(wr[r][c], r2, nd[2 * c]);
-                nd[2 * c + 1] = fmaf(wr[r][c], r1, nd[2 * c + 1]);
+            for (int r = 0; r < 2 * RH; ++r) {
+                const bool live = r < RL || (r == RL && last_live);
+                const float r1 = live ? __builtin_amdgcn_rcpf(x[r < RF ? r : 0]) : 0.f;
+                r1v[r] = r1;
+                r2v[r] = live ? ve[r < RF ? r : 0] * r1 * r1 : 0.f;
             }
-        }
-        if (last_live) {
-            const float r1 = __builtin_amdgcn_rcpf(x[RL]);
-            const float r2 = ve[RL] * r1 * r1;
 #pragma unroll
-            for (int c = 0; c < CK; ++c) {
-                nd[2 * c] = fmaf(wr[RL][c], r2, nd[2 * c]);
-                nd[2 * c + 1] = fmaf(wr[RL][c], r1, nd[2 * c + 1]);
+            for (int j = 0; j < RH; ++j) {
+                const uint32_t p1 = pack_bf2(r1v[2 * j], r1v[2 * j + 1]);
+                const uint32_t p2 = pack_bf2(r2v[2 * j], r2v[2 * j + 1]);
+#pragma unroll
+                for (int c = 0; c < CK; ++c) {
+                    nd[2 * c] = dot2(wfp[j][c], p2, nd[2 * c]);
+                    nd[2 * c + 1] = dot2(wfp[j][c], p1, nd[2 * c + 1]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const float r1 = __builtin_amdgcn_rcpf(x[r]);
+                const float r2 = ve[r] * r1 * r1;
+#pragma unroll
+                for (int c = 0; c < CK; ++c) {
+                    nd[2 * c] = fmaf(wr[r][c], r2, nd[2 * c]);
+                    nd[2 * c + 1] = fmaf(wr[r][c], r1, nd[2 * c + 1]);
+                }
+            }
+            if (last_live) {
+                const float r1 = __builtin_amdgcn_rcpf(x[RL]);
+                const float r2 = ve[RL] * r1 * r1;
+#pragma unroll
+                for (int c = 0; c < CK; ++c) {
+                    nd[2 * c] = fmaf(wr[RL][c], r2, nd[2 * c]);
+                    nd[2 * c + 1] = fmaf(wr[RL][c], r1, nd[2 * c + 1]);
+                }
             }
         }
         // over the wave: lanes 8 apart, then rows 0+1 / 2+3, then halves
@@ -183,7 +257,7 @@ __device__ inline void body(const FitDesc &a, int fr) {
         // the column sum before the update joins every den_k.  K <= 64, so the
         // lanes t < K are wave 0's, which reads hsh before it writes it.
         float dpsi = 0.f;
-        if (a.psi_lambda > 0.f && w == 0)
+        if (!BF && a.psi_lambda > 0.f && w == 0)
             dpsi = a.psi_lambda / (a.psi_a + wave_sum_f32(lane < K ? hsh[lane] : 0.f));
         if (t < K) {
             const float4 *pk = red4 + t * (KS / 4);
@@ -198,8 +272,7 @@ __device__ inline void body(const FitDesc &a, int fr) {
             hsh[t] = h;
         }
         __syncthreads();
-#pragma unroll
-        for (int c = 0; c < CK; ++c) hk[c] = hsh[q + 8 * c];
+        load_h();
     }
     if (guard) atomicOr(a.flags, FLAG_GUARD_H);
 
@@ -243,14 +316,14 @@ __device__ inline void body(const FitDesc &a, int fr) {
     }
 }
 
-template <int CK, int RF>
+template <int CK, int RF, bool BF>
 __global__ __launch_bounds__(VT) void fit_valu_kernel(FitDesc a) {
-    body<CK, RF>(a, blockIdx.x);
+    body<CK, RF, BF>(a, blockIdx.x);
 }
 
 // Batched form: item = (stream, tile of NF frames); workgroup NF*i + j fits
 // frame j of item i; frames past the stream's minibatch of this step exit.
-template <int CK, int RF>
+template <int CK, int RF, bool BF>
 __global__ __launch_bounds__(VT) void fit_valu_multi_kernel(const FitDesc *__restrict__ descs,
                                                             const int2 *__restrict__ items,
                                                             const long long *__restrict__ cursor,
@@ -264,22 +337,40 @@ __global__ __launch_bounds__(VT) void fit_valu_multi_kernel(const FitDesc *__res
     a.b = b;
     a.V += c * a.ldv;
     if (a.Hb) a.Hb += c * a.ldh;
-    body<CK, RF>(a, fr);
+    body<CK, RF, BF>(a, fr);
 }
 
-// Launch of the (CK, rf) instance, rf = 1..17: b frames of *a (d = nullptr),
-// or the frames of n batched items of d.  Explicitly instantiated per CK in
+// Served form: grid (frame j, chunk i) over a step's work list (the frame
+// index in x, whose range is the larger); frames past the chunk exit.
+template <int CK, int RF, bool BF>
+__global__ __launch_bounds__(VT) void fit_valu_work_kernel(const FitDesc *__restrict__ tab,
+                                                           const ServeWork *__restrict__ work) {
+    const ServeWork wk = work[blockIdx.y];
+    if ((int)blockIdx.x >= wk.b) return;   // uniform per workgroup
+    FitDesc a = tab[wk.sess];
+    a.b = wk.b;
+    a.V = wk.V;
+    a.ldv = wk.ldv;
+    body<CK, RF, BF>(a, blockIdx.x);
+}
+
+// Launch of the (CK, rf, BF) instance, rf = 1..17: b frames of *a (d and tab
+// null), the frames of n batched items of d, or the frames of n served chunks
+// of tab (at most max_b frames each).  Explicitly instantiated per CK in
 // fit_valu_ck*.hip, so the instances build in parallel.
-template <int CK>
+template <int CK, bool BF>
 hipError_t launch_any(const FitDesc *a, int rf, int b, const FitDesc *d, const int2 *items, int n,
-                      const long long *cur, const int *beff, hipStream_t s) {
+                      const long long *cur, const int *beff, const FitDesc *tab,
+                      const ServeWork *work, int max_b, hipStream_t s) {
     switch (rf) {
-#define ISNMF_VALU_RF(RF)                                                             \
-    case RF:                                                                          \
-        if (d)                                                                        \
-            fit_valu_multi_kernel<CK, RF><<<n * NF, VT, 0, s>>>(d, items, cur, beff); \
-        else                                                                          \
-            fit_valu_kernel<CK, RF><<<b, VT, 0, s>>>(*a);                             \
+#define ISNMF_VALU_RF(RF)                                                                    \
+    case RF:                                                                                 \
+        if (tab)                                                                             \
+            fit_valu_work_kernel<CK, RF, BF><<<dim3(max_b, n), VT, 0, s>>>(tab, work);        \
+        else if (d)                                                                          \
+            fit_valu_multi_kernel<CK, RF, BF><<<n * NF, VT, 0, s>>>(d, items, cur, beff);     \
+        else                                                                                 \
+            fit_valu_kernel<CK, RF, BF><<<b, VT, 0, s>>>(*a);                                 \
         break;
         ISNMF_VALU_RF(1) ISNMF_VALU_RF(2) ISNMF_VALU_RF(3) ISNMF_VALU_RF(4)
         ISNMF_VALU_RF(5) ISNMF_VALU_RF(6) ISNMF_VALU_RF(7) ISNMF_VALU_RF(8)
@@ -293,14 +384,13 @@ hipError_t launch_any(const FitDesc *a, int rf, int b, const FitDesc *d, const i
     return hipGetLastError();
 }
 
-#define ISNMF_VALU_EXTERN(CKV)                                                                  \
-    extern template hipError_t launch_any<CKV>(const FitDesc *, int, int, const FitDesc *,     \
-                                               const int2 *, int, const long long *, const int *, \
-                                               hipStream_t);
-#define ISNMF_VALU_INSTANTIATE(CKV)                                                      \
-    template hipError_t launch_any<CKV>(const FitDesc *, int, int, const FitDesc *,     \
-                                        const int2 *, int, const long long *, const int *, \
-                                        hipStream_t);
+#define ISNMF_VALU_SIG(CKV, BFV)                                                               \
+    hipError_t launch_any<CKV, BFV>(const FitDesc *, int, int, const FitDesc *, const int2 *,  \
+                                    int, const long long *, const int *, const FitDesc *,      \
+                                    const ServeWork *, int, hipStream_t);
+#define ISNMF_VALU_EXTERN(CKV) \
+    extern template ISNMF_VALU_SIG(CKV, false) extern template ISNMF_VALU_SIG(CKV, true)
+#define ISNMF_VALU_INSTANTIATE(CKV) template ISNMF_VALU_SIG(CKV, false) template ISNMF_VALU_SIG(CKV, true)
 
 }  // namespace valu
 }  // namespace isnmf

@@ -18,18 +18,22 @@ namespace {
 constexpr int VALU_RF_MAX = 17;   // F <= 1088
 constexpr int VALU_CK_MAX = 8;    // K <= 64
 
+// cpw 0: FP32 products; cpw -4: bf16 products on v_dot2c_f32_bf16.
 hipError_t launch(const FitClass &c, const FitDesc *a, int b, const FitDesc *d, const int2 *items,
-                  int n, const long long *cur, const int *beff, hipStream_t s) {
-    if (!c.ok || c.cpw != 0 || c.kmax % 8 != 0) return hipErrorNotSupported;
+                  int n, const long long *cur, const int *beff, const FitDesc *tab,
+                  const ServeWork *work, int max_b, hipStream_t s) {
+    if (!c.ok || (c.cpw != 0 && c.cpw != -4) || c.kmax % 8 != 0) return hipErrorNotSupported;
+    const bool bf = c.cpw == -4;
     switch (c.kmax / 8) {
-        case 1: return valu::launch_any<1>(a, c.rf, b, d, items, n, cur, beff, s);
-        case 2: return valu::launch_any<2>(a, c.rf, b, d, items, n, cur, beff, s);
-        case 3: return valu::launch_any<3>(a, c.rf, b, d, items, n, cur, beff, s);
-        case 4: return valu::launch_any<4>(a, c.rf, b, d, items, n, cur, beff, s);
-        case 5: return valu::launch_any<5>(a, c.rf, b, d, items, n, cur, beff, s);
-        case 6: return valu::launch_any<6>(a, c.rf, b, d, items, n, cur, beff, s);
-        case 7: return valu::launch_any<7>(a, c.rf, b, d, items, n, cur, beff, s);
-        case 8: return valu::launch_any<8>(a, c.rf, b, d, items, n, cur, beff, s);
+#define ISNMF_VALU_CK(CKV)                                                                     \
+    case CKV:                                                                                  \
+        return bf ? valu::launch_any<CKV, true>(a, c.rf, b, d, items, n, cur, beff, tab, work, \
+                                                max_b, s)                                      \
+                  : valu::launch_any<CKV, false>(a, c.rf, b, d, items, n, cur, beff, tab, work, \
+                                                 max_b, s);
+        ISNMF_VALU_CK(1) ISNMF_VALU_CK(2) ISNMF_VALU_CK(3) ISNMF_VALU_CK(4)
+        ISNMF_VALU_CK(5) ISNMF_VALU_CK(6) ISNMF_VALU_CK(7) ISNMF_VALU_CK(8)
+#undef ISNMF_VALU_CK
         default: return hipErrorNotSupported;
     }
 }
@@ -48,14 +52,26 @@ FitClass valu_class(int F, int K) {
     return c;
 }
 
+FitClass vbf_class(int F, int K) {
+    FitClass c = valu_class(F, K);
+    if (c.ok) c.cpw = -4;
+    return c;
+}
+
 hipError_t launch_fit_valu(const FitDesc &a, const FitClass &c, int b, hipStream_t s) {
     if (c.rf != (a.F + 63) / 64 || c.kmax < a.K || !a.Wv) return hipErrorInvalidValue;
-    return launch(c, &a, b, nullptr, nullptr, 0, nullptr, nullptr, s);
+    return launch(c, &a, b, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, s);
 }
 
 hipError_t launch_fit_valu_multi(const FitClass &c, const FitDesc *d, const int2 *items, int n,
                                  const long long *cur, const int *beff, hipStream_t s) {
-    return launch(c, nullptr, 0, d, items, n, cur, beff, s);
+    return launch(c, nullptr, 0, d, items, n, cur, beff, nullptr, nullptr, 0, s);
+}
+
+hipError_t launch_fit_valu_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
+                                int max_b, hipStream_t s) {
+    if (n < 1 || max_b < 1) return hipSuccess;
+    return launch(c, nullptr, 0, nullptr, nullptr, n, nullptr, nullptr, tab, work, max_b, s);
 }
 
 }  // namespace isnmf

@@ -13,6 +13,9 @@
 //                             elsewhere
 //   BF16, F <= 640, K <= 64:  the 16-frame tile variant, a tuning candidate
 //                             (throughput over many frames)
+//   BF16, F <= 1088, K <= 64: the VALU variant on bf16 dot products, the
+//                             default where no MFMA tile fits and a tuning
+//                             candidate elsewhere (latency of one minibatch)
 //   FP32, K <= 64:            the FP32 16-frame tile variant (16x16x4 FP32
 //                             MFMA, W in LDS), a tuning candidate (throughput)
 #include <math.h>
@@ -61,8 +64,9 @@ FitClass fit_class(int F, int K, int prec) {
         }
         c.ok = 1;
     }
-    // FP32 beyond the register-resident MFMA tiles: one frame per workgroup
+    // FP32 and BF16 beyond the register-resident MFMA tiles: one frame per workgroup
     if (!c.ok && prec == 0) return valu_class(F, K);
+    if (!c.ok && prec == 1) return vbf_class(F, K);
     return c;
 }
 
@@ -83,6 +87,10 @@ int fit_candidates(int F, int K, int prec, FitClass *out, int max_out) {
     if (prec == 0) {                 // the FP32 16-frame tile variant (throughput)
         const FitClass t = t32_class(F, K);
         if (t.ok) add(t);
+    }
+    if (prec == 1 && d.cpw != -4) {   // the VALU variant on bf16 dot products (latency)
+        const FitClass v = vbf_class(F, K);
+        if (v.ok) add(v);
     }
     if (prec == 1) {                 // the 16-frame tile variants (BF16)
         const FitClass t = tile_class(F, K);
@@ -150,6 +158,7 @@ hipError_t launch_fused_fit(const OnlineDev &d, const FitClass &c, const float *
     if (!c.ok) return hipErrorNotSupported;
     const FitDesc a = make_fit_desc(d, V, ldv, b, iters, eps, warm, Hb, ldh);
     if (c.cpw == 0) return prec == 0 ? launch_fit_valu(a, c, b, s) : hipErrorNotSupported;
+    if (c.cpw == -4) return prec == 1 ? launch_fit_valu(a, c, b, s) : hipErrorNotSupported;
     if (d.psi_lambda > 0.0) return hipErrorNotSupported;   // penalty: VALU variant only
     if (c.cpw == -1) return prec == 1 ? launch_fit_tile(a, c, b, s) : hipErrorNotSupported;
     if (c.cpw == -2) return prec == 1 ? launch_fit_stile(a, c, b, s) : hipErrorNotSupported;

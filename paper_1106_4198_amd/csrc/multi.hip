@@ -228,7 +228,7 @@ hipError_t enqueue_step(isnmf_multi *m, hipStream_t s) {
     for (const auto &g : m->groups) {
         hipError_t e;
         const hipStream_t gs = g.lane ? m->side[g.lane - 1] : s;
-        if (g.c.cpw == 0)
+        if (g.c.cpw == 0 || g.c.cpw == -4)
             e = launch_fit_valu_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else if (g.c.cpw == -1)
             e = launch_fit_tile_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
@@ -316,7 +316,8 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         if (isnmf_handle_kernel(handles[s]) != ISNMF_KERNEL_FUSED) return ISNMF_EUNSUPPORTED;
         if (p.psi_lambda > 0.0) return ISNMF_EUNSUPPORTED;            // no penalty on H
         if (b[s] > 512) return ISNMF_EUNSUPPORTED;                   // single fold slice
-        if (isnmf_handle_class(handles[s])->cpw == 0 && !d.Wv) return ISNMF_EUNSUPPORTED;
+        const int cpw = isnmf_handle_class(handles[s])->cpw;
+        if ((cpw == 0 || cpw == -4) && !d.Wv) return ISNMF_EUNSUPPORTED;
         for (int r = 0; r < s; ++r)
             if (handles[r] == handles[s]) return ISNMF_EINVAL;        // one entry per stream
     }

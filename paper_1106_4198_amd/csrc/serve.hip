@@ -133,6 +133,9 @@ hipError_t serve_fit_any(int prec, const FitClass &c, const FitDesc *tab, const 
     if (c.cpw == -3)
         return prec == 0 ? launch_fit_t32_work(c, tab, work, n, (max_b + 127) / 128, s)
                          : hipErrorNotSupported;
+    if (c.cpw == 0 || c.cpw == -4)   // VALU variants: one workgroup per frame
+        return prec == (c.cpw == 0 ? 0 : 1) ? launch_fit_valu_work(c, tab, work, n, max_b, s)
+                                            : hipErrorNotSupported;
     if (prec == 1) return serve_fit<1>(c, tab, work, n, tiles, s);
     if (prec == 2) return serve_fit<2>(c, tab, work, n, tiles, s);
     return serve_fit<0>(c, tab, work, n, tiles, s);
@@ -524,9 +527,11 @@ int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *s
     if (p.psi_lambda > 0.0) return ISNMF_EUNSUPPORTED;   // no penalty on H
     const OnlineDev &d = *isnmf_handle_dev(h);
     const FitClass &c = *isnmf_handle_class(h);
-    const bool tile16 = ((c.cpw == -1 || c.cpw == -2) && prec_of(p) == 1) ||
-                        (c.cpw == -3 && prec_of(p) == 0);
-    if (!tile16 && (c.wg || c.cpw != 1 || (c.nw != 4 && c.nw != 8) || c.kmax > 64))
+    // variants with a served kernel of their own: the 16-frame tiles and the VALU forms
+    const bool own = ((c.cpw == -1 || c.cpw == -2 || c.cpw == -4) && prec_of(p) == 1) ||
+                     ((c.cpw == -3 || c.cpw == 0) && prec_of(p) == 0);
+    if ((c.cpw == 0 || c.cpw == -4) && !d.Wv) return ISNMF_EUNSUPPORTED;
+    if (!own && (c.wg || c.cpw != 1 || (c.nw != 4 && c.nw != 8) || c.kmax > 64))
         return ISNMF_EUNSUPPORTED;
     if (footprint > s->budget) return ISNMF_ENOMEM;   // could never be admitted
     for (const auto &o : s->sess)

@@ -311,16 +311,18 @@ def test_batched_streamed_tile_streams_equal_alone_bitwise():
         bd.tune_clear()
 
 
-def test_fp32_tile_batched_equals_alone_bitwise():
-    """FP32 16-frame tile variant in the batched form: streams of one shape and
-    of mixed shapes (several groups of the variant, 128-frame items and ragged
-    last minibatches) give the bits of the same streams run alone."""
+@pytest.mark.parametrize("precision,cpw", [("fp32", -3), ("fp32", 0), ("bf16", -4)])
+def test_fp32_tile_and_valu_batched_equal_alone_bitwise(precision, cpw):
+    """The FP32 16-frame tile variant (cpw -3) and the VALU variant in FP32 (0)
+    and BF16 (-4) in the batched form: streams of one shape and of mixed
+    shapes (several groups of the variant, ragged last minibatches) give the
+    bits of the same streams run alone."""
     shapes = [(513, 50, 128, 300), (513, 50, 128, 256), (257, 64, 64, 200), (129, 8, 200, 390),
               (592, 64, 33, 70), (1025, 32, 128, 130)]
-    say("fp32 tile batched vs alone")
+    say(f"{precision} cpw={cpw} batched vs alone")
     bd.tune_clear()
     for F, K, _, _ in shapes:
-        bd.tune_set(F, K, "fp32", 8, -3, 0)
+        bd.tune_set(F, K, precision, 8, cpw, 0)
     try:
         data = []
         for i, (F, K, b, N) in enumerate(shapes):
@@ -330,7 +332,7 @@ def test_fp32_tile_batched_equals_alone_bitwise():
         steps = 3
         alone, loss_alone = [], []
         for W0, V, b in data:
-            g = bd.OnlineISNMF(W0, b)
+            g = bd.OnlineISNMF(W0, b, precision=precision)
             ls = torch.zeros((), dtype=torch.float64, device=DEV)
             for s in range(steps):
                 lo, hi = s * b, min((s + 1) * b, V.shape[0])
@@ -338,7 +340,7 @@ def test_fp32_tile_batched_equals_alone_bitwise():
                     g.step(V[lo:hi], None, ls)
             alone.append(g)
             loss_alone.append(ls)
-        mixed = [bd.OnlineISNMF(W0, b) for W0, _, b in data]
+        mixed = [bd.OnlineISNMF(W0, b, precision=precision) for W0, _, b in data]
         m = bd.MultiISNMF(mixed, [d[1] for d in data], [d[2] for d in data])
         m.run(1, graph=False)
         m.run(steps - 1, graph=True)

@@ -61,7 +61,8 @@ def test_one_step_error_is_small(precision, F, K, b):
 
 def tile_variant(F, K, cpw=-1):
     """Make handles of shape (F, K) in BF16 use a 16-frame tile variant: W
-    resident in LDS (cpw -1) or streamed through it (cpw -2)."""
+    resident in LDS (cpw -1) or streamed through it (cpw -2); or the VALU
+    variant on bf16 dot products (cpw -4)."""
     bd.tune_clear()
     bd.tune_set(F, K, "bf16", 8, cpw, 0)
     assert bd.tune_get(F, K, "bf16") == (8, cpw, 0)
@@ -74,7 +75,14 @@ STILE_SHAPES = TILE_SHAPES + [(1025, 128, 128), (1025, 100, 37), (1025, 40, 130)
                               (700, 65, 9), (257, 128, 64), (1025, 72, 1)]
 
 
-@pytest.mark.parametrize("cpw,F,K,b", [(-1,) + s for s in TILE_SHAPES] + [(-2,) + s for s in STILE_SHAPES])
+# the VALU variant: F <= 1088, K <= 64, one frame per workgroup
+VBF_SHAPES = [(513, 50, 128), (129, 8, 16), (257, 64, 33), (70, 5, 6), (513, 33, 7), (640, 64, 20),
+              (16, 1, 3), (200, 40, 17), (257, 16, 1), (1025, 40, 130), (1088, 64, 5), (700, 57, 10),
+              (1025, 1, 3), (577, 24, 4), (3, 2, 5), (66, 64, 5), (128, 9, 2)]
+
+
+@pytest.mark.parametrize("cpw,F,K,b", [(-1,) + s for s in TILE_SHAPES] + [(-2,) + s for s in STILE_SHAPES]
+                         + [(-4,) + s for s in VBF_SHAPES])
 def test_tile_variant_one_step(cpw, F, K, b):
     """BF16 16-frame tile variants (16x16x32 MFMA; W resident in LDS, or
     streamed through it one 32-row step at a time) against the FP64 oracle at
@@ -111,13 +119,17 @@ def test_tile_variant_one_step(cpw, F, K, b):
         bd.tune_clear()
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp16", "fp32"])
+@pytest.mark.parametrize("precision", ["bf16", "fp16", "fp32", "bf16_valu"])
 def test_pass_accuracy_matches_stated_tolerance(precision):
     """F=513, K=50, b=128, I=20 over 24 minibatches (a prefix of the benchmark
     stream), with checkpoints of the relative error of W, A, B and the online
-    loss against the FP64 oracle."""
+    loss against the FP64 oracle.  bf16_valu: BF16 on the VALU variant."""
     F, K, b, I, steps = 513, 50, 128, 20, 24
     say(f"precision pass {precision}")
+    bd.tune_clear()
+    if precision == "bf16_valu":
+        precision = "bf16"
+        bd.tune_set(F, K, "bf16", 8, -4, 0)
     V, W0 = synth.problem(F, K, steps * b, seed=2011)
     st = oracle.OnlineState(W0.astype(np.float64))
     oracle.set_threads(8)
@@ -147,9 +159,10 @@ def test_pass_accuracy_matches_stated_tolerance(precision):
     orf = oracle.objective(V[:, ::97].astype(np.float64), st.W, Hr)
     print(f"[precision] {precision} final objective rel {abs(og - orf) / orf:.2e}")
     assert abs(og - orf) <= 1e-3 * orf
+    bd.tune_clear()
 
 
-@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+@pytest.mark.parametrize("precision", ["fp16", "bf16", "bf16_valu"])
 @pytest.mark.parametrize("scale_exp", [-20, 20])
 def test_step_is_amplitude_invariant(precision, scale_exp):
     """IS-NMF's fitted h scales with the frames' amplitude (section 2.1: the
@@ -165,8 +178,12 @@ def test_step_is_amplitude_invariant(precision, scale_exp):
     st.step(V[:, :b].astype(np.float64), iters=20)
     st.step(V[:, b:2 * b].astype(np.float64), iters=20)
     bd.tune_clear()
+    if precision == "bf16_valu":
+        precision = "bf16"
+        bd.tune_set(F, K, "bf16", 8, -4, 0)
     g = bd.OnlineISNMF(to_gpu_kf(st.W, np.float32, torch), b, precision=precision,
                        A0=to_gpu_kf(st.A, np.float64, torch), B0=to_gpu_kf(st.B, np.float64, torch))
+    bd.tune_clear()
     assert g.kernel_used == "fused"
     g.set_w64(to_gpu_kf(st.W, np.float64, torch))
     Vb = V[:, 2 * b:3 * b]

@@ -290,17 +290,31 @@ def test_server_keeps_chunks_and_loss_targets_alive():
     srv.close()
 
 
-def test_served_form_rejects_the_valu_variant():
-    """The served form runs MFMA tile variants only; a handle whose fit is the
-    one-frame-per-workgroup VALU variant is refused, not silently rerouted."""
-    say("serve rejects VALU")
+def test_served_form_runs_the_valu_variant_at_wide_f():
+    """At F = 1025 no FP32 MFMA tile holds W, so FP32 handles fit on the VALU
+    variant by default (BF16 handles here by a tuning entry); the served form
+    runs them on its kernel of its own (one workgroup per frame) and gives
+    the bits of the sessions alone."""
+    say("serve VALU at F = 1025")
+    bd.tune_clear()
+    bd.tune_set(1025, 40, "bf16", 8, -4, 0)
     W0 = torch.rand((40, 1025), device=DEV) + 0.5
-    g = bd.OnlineISNMF(W0, 16)   # FP32, F = 1025: the VALU variant
-    srv = bd.Server(max_sessions=2, max_per_step=2, max_frames=64)
-    with pytest.raises(bd.IsnmfError) as ei:
-        srv.open(g)
-    assert ei.value.code == bd.EUNSUPPORTED
-    srv.close()
+    V = torch.rand((200, 1025), device=DEV) + 1e-3
+    for prec in ("fp32", "bf16"):
+        ga = bd.OnlineISNMF(W0, 128, precision=prec)
+        assert bd.tune_get(1025, 40, prec)[1] == (0 if prec == "fp32" else -4)
+        ga.step(V[:120])
+        ga.step(V[120:])
+        gs = bd.OnlineISNMF(W0, 128, precision=prec)
+        srv = bd.Server(max_sessions=2, max_per_step=2, max_frames=256)
+        sid = srv.open(gs)
+        srv.submit(sid, V[:120])
+        srv.submit(sid, V[120:])
+        srv.drain()
+        torch.cuda.synchronize()
+        assert torch.equal(ga.get_w64(), gs.get_w64()), prec
+        srv.close()
+    bd.tune_clear()
 
 
 @pytest.mark.parametrize("cpw", [-1, -2])
@@ -353,12 +367,15 @@ def test_served_tile_sessions_equal_alone_bitwise(cpw):
         bd.tune_clear()
 
 
-def test_served_fp32_tile_sessions_equal_alone_bitwise():
-    """Sessions on the FP32 16-frame tile variant in the served form."""
-    say("served fp32 tile")
+@pytest.mark.parametrize("precision,cpw", [("fp32", -3), ("fp32", 0), ("bf16", -4)])
+def test_served_own_kernel_sessions_equal_alone_bitwise(precision, cpw):
+    """Sessions on the variants with served kernels of their own (the FP32
+    16-frame tile, and the VALU variant in FP32 and BF16: one workgroup per
+    frame) give the bits of the same sessions run alone."""
+    say(f"served {precision} cpw={cpw}")
     bd.tune_clear()
-    bd.tune_set(513, 64, "fp32", 8, -3, 0)
-    bd.tune_set(257, 32, "fp32", 8, -3, 0)
+    bd.tune_set(513, 64, precision, 8, cpw, 0)
+    bd.tune_set(257, 32, precision, 8, cpw, 0)
     try:
         rng = np.random.default_rng(9)
         data = []
@@ -374,14 +391,14 @@ def test_served_fp32_tile_sessions_equal_alone_bitwise():
             data.append((torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), chunks))
         alone = []
         for W0, chunks in data:
-            g = bd.OnlineISNMF(W0, 512)
+            g = bd.OnlineISNMF(W0, 512, precision=precision)
             for c in chunks:
                 g.step(c)
             alone.append(g)
         srv = bd.Server(max_sessions=6, max_per_step=6, max_frames=4096, inflight=2)
         served = []
         for W0, _ in data:
-            g = bd.OnlineISNMF(W0, 512)
+            g = bd.OnlineISNMF(W0, 512, precision=precision)
             served.append((g, srv.open(g)))
         for k in range(3):
             for i, (_, chunks) in enumerate(data):
