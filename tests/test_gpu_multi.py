@@ -161,7 +161,9 @@ def test_autotune_picks_a_valid_variant_and_keeps_parity():
         v, us = bd.autotune(F, K, 64, precision=prec, trials=3)
         nw, cpw, wg = bd.tune_get(F, K, prec)
         print(f"[autotune] F={F} K={K} {prec}: variant {v} nw={nw} cpw={cpw} wg={wg} {us:.1f} us")
-        assert us > 0 and nw * cpw * 64 >= (F // 64) * 64
+        # an MFMA tile variant's waves x chunks cover the rows; the VALU (0, -4)
+        # and 16-frame tile (-1, -2, -3) variants cover any F they are offered for
+        assert us > 0 and (cpw <= 0 or nw * cpw * 64 >= (F // 64) * 64)
         V, W0 = synth.problem(F, K, 64, seed=7)
         g = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), 64, precision=prec)
         g.step(torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV))
