@@ -55,9 +55,9 @@ FIT_SOURCES = {
     "mfma": ("fit_body.h", "fit_launch.h", "fit_f32.hip"),
 }
 TRAFFIC = {
-    # FETCH_SIZE 713.0 KiB x 2.0 + WRITE_SIZE 558.5 KiB x 1.0 per b=128 launch
+    # FETCH_SIZE 716.0 KiB x 2.0 + WRITE_SIZE 558.5 KiB x 1.0 per b=128 launch
     # (profiles/fit_valu_F513_K50_b128_pmc.md)
-    ("fit_valu_kernel<7,9>", "6f97083ad08ec38c886dc31404157a459e2ea1dd"): (713.0 * 2.0 + 558.5) * 1024,
+    ("fit_valu_kernel<7,9,false>", "c31ddd00528b77f6ea79f09aac8924c20c790e12"): (716.0 * 2.0 + 558.5) * 1024,
 }
 
 
@@ -72,7 +72,7 @@ def _src_hash(kind: str) -> str:
 def fit_kernel_name(nw: int, cpw: int, kmax: int, wg: int) -> tuple:
     """(kind, kernel symbol) of the tuned FP32 fit variant for (F, K)."""
     if cpw == 0:
-        return "valu", f"fit_valu_kernel<{(K + 7) // 8},{(F + 63) // 64}>"
+        return "valu", f"fit_valu_kernel<{(K + 7) // 8},{(F + 63) // 64},false>"
     return "mfma", f"fit_single_kernel<{nw},{cpw},{kmax},0,{bool(wg)}>"
 
 
@@ -396,8 +396,8 @@ def bench_served(bd, synth, torch, np, dev, S, n_chunks, duration_s, threads, se
     """Continuous batching: S sessions (F in {257,513}, K in {32,64}, BF16
     products), chunks of U[1,512] frames.  Capacity with every chunk queued at
     once, then Poisson arrivals at 50% and 90% of it: p50/p99 chunk latency.
-    tune: kernel variants timed at one mean chunk ("latency") or at a whole
-    served step ("throughput", capacity only)."""
+    tune: kernel variants timed at four mean chunks, a lightly loaded step
+    ("latency"), or at a whole served step ("throughput", capacity only)."""
     rng = np.random.default_rng(seed0)
     Fs = rng.choice([257, 513], size=S)
     Ks = rng.choice([32, 64], size=S)
@@ -406,12 +406,14 @@ def bench_served(bd, synth, torch, np, dev, S, n_chunks, duration_s, threads, se
     for Fi in (257, 513):
         V = synth.frames(Fi, 50, pool_n, seed0 + Fi, threads=threads)
         pools[Fi] = torch.from_numpy(np.ascontiguousarray(V.T)).to(dev)
-    # kernel variant per shape, timed at one mean chunk (latency) or at a
-    # served step's size: all sessions of a shape with a mean chunk each
+    # kernel variant per shape, timed at four mean chunks (latency: one chunk
+    # alone would pick the one-frame-per-workgroup VALU variant, which halves
+    # the capacity) or at a served step's size: all sessions of a shape with a
+    # mean chunk each
     variants = {}
     for Fi in (257, 513):
         for Ki in (32, 64):
-            nb = 256 if tune == "latency" else int(np.sum((Fs == Fi) & (Ks == Ki))) * 256
+            nb = 1024 if tune == "latency" else int(np.sum((Fs == Fi) & (Ks == Ki))) * 256
             bd.autotune(Fi, Ki, max(nb, 256), precision="bf16", trials=2)
             variants[f"{Fi}x{Ki}"] = list(bd.tune_get(Fi, Ki, "bf16"))
     hs = [bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(

@@ -85,6 +85,7 @@ size_t carve_online(int F, int K, int b_max, const isnmf_params &p, bool with_lo
     const bool wv = (p.precision == ISNMF_FP32 || p.precision == ISNMF_BF16) && valu_class(F, K).ok;
     t.Wv = wv ? (float *)take(wv_floats(F, K) * 4) : nullptr;
     t.wv_ck = (K + 7) / 8;
+    t.wv_live = 1;
     t.A = (double *)take(fk * 8);
     t.B = (double *)take(fk * 8);
     t.Wn = (double *)take(fk * 8);
@@ -273,6 +274,8 @@ int isnmf_online_init(isnmf_online **out, int F, int K, int b_max, const isnmf_p
         delete h;
         return ISNMF_EDEVICE;
     }
+    // the register-order copy is written above; only the VALU variants read it later
+    h->d.wv_live = h->cls.cpw == 0 || h->cls.cpw == -4;
     *out = h;
     return ISNMF_OK;
 }

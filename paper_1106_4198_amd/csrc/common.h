@@ -59,6 +59,8 @@ struct OnlineDev {
     int wexp;            // s = round(log2 F): 16-bit copies hold W * 2^s
     float *Wv;           // W in the register order of the VALU fit (see wv_index) or null
     int wv_ck;           // ceil(K / 8): components per thread of that order
+    int wv_live;         // 1: Wv is kept current (0 when the handle's fit variant does
+                         // not read it; it then holds W(0) for the autotuner's trials)
     double *A, *B;       // F x K, ld F, stored before the last column rescale:
                          // the statistics are A[:,k] / sc[k] and B[:,k] * sc[k]
     double *sc;          // K: column scale of A and B not yet applied (1 = none)

@@ -125,7 +125,7 @@ inline W16Out w16_out(const OnlineDev &d) {
     return o;
 }
 
-inline WvOut wv_out(const OnlineDev &d) { return WvOut{d.Wv, d.wv_ck}; }
+inline WvOut wv_out(const OnlineDev &d) { return WvOut{d.wv_live ? d.Wv : nullptr, d.wv_ck}; }
 
 inline RescaleArgs rescale_args(const OnlineDev &d, int normalize, int warm, float *Hb, int ldh) {
     RescaleArgs a;
