@@ -57,7 +57,7 @@ FIT_SOURCES = {
 TRAFFIC = {
     # FETCH_SIZE 716.0 KiB x 2.0 + WRITE_SIZE 558.5 KiB x 1.0 per b=128 launch
     # (profiles/fit_valu_F513_K50_b128_pmc.md)
-    ("fit_valu_kernel<7,9,false>", "c31ddd00528b77f6ea79f09aac8924c20c790e12"): (716.0 * 2.0 + 558.5) * 1024,
+    ("fit_valu_kernel<7,9,false>", "414602e3f7c1a3fb073836c5de58ce6ba3bf7d2b"): (716.0 * 2.0 + 558.5) * 1024,
 }
 
 

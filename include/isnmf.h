@@ -206,9 +206,11 @@ int isnmf_online_fit(isnmf_online *h, const float *Vb, int ldv, int b, float *Hb
 /*
  * Not part of the method: measurement hooks.
  * Per-launch timing of the fit kernel with HIP events on the launch stream.
- * enable != 0 starts recording an event pair around every fit launch of this
- * handle (up to `capacity` launches; later launches are not timed);
- * enable == 0 stops.  isnmf_online_timing synchronizes, returns the number
+ * enable != 0 starts timing every fit launch of this handle (up to
+ * `capacity` launches; later launches are not timed); enable == 0 stops.
+ * The VALU fit variants are launched with the event pair attached to the
+ * dispatch itself (hipExtLaunchKernel), so their time is the kernel's own;
+ * the other variants record the pair around the launch.  isnmf_online_timing synchronizes, returns the number
  * of timed launches and their total duration in milliseconds, and clears
  * the record.
  */

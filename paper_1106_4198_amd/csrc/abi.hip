@@ -11,6 +11,8 @@
 
 using namespace isnmf;
 
+thread_local LaunchTiming isnmf::g_launch_timing;
+
 struct isnmf_online {
     OnlineDev d;
     isnmf_params p;
@@ -138,17 +140,24 @@ int run_fit(isnmf_online *h, const float *V, int ldv, int b, int iters, int warm
             int ldh, hipStream_t s) {
     const isnmf_params &p = h->p;
     const bool timed = h->timing && h->timed < h->ev0.size();
-    if (timed && hipEventRecord(h->ev0[h->timed], s) != hipSuccess) return ISNMF_EDEVICE;
+    // the VALU variants take the event pair on their dispatch (one launch)
+    const bool fused = p.precision != ISNMF_FP64 && h->kernel_used == ISNMF_KERNEL_FUSED;
+    const bool on_dispatch = timed && fused && (h->cls.cpw == 0 || h->cls.cpw == -4);
+    if (on_dispatch) g_launch_timing = LaunchTiming{h->ev0[h->timed], h->ev1[h->timed], true};
+    if (timed && !on_dispatch && hipEventRecord(h->ev0[h->timed], s) != hipSuccess)
+        return ISNMF_EDEVICE;
     hipError_t e;
     if (p.precision == ISNMF_FP64)
         e = launch_plain_fit<double>(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
-    else if (h->kernel_used == ISNMF_KERNEL_FUSED)
+    else if (fused)
         e = launch_fused_fit(h->d, h->cls, V, ldv, b, iters, p.eps, warm, Hb, ldh, prec_code(p), s);
     else
         e = launch_plain_fit<float>(h->d, V, ldv, b, iters, p.eps, warm, Hb, ldh, s);
-    if (e != hipSuccess) return ISNMF_EDEVICE;
+    const bool attached = on_dispatch && !g_launch_timing.pending;
+    g_launch_timing = LaunchTiming{};
+    if (e != hipSuccess || (on_dispatch && !attached)) return ISNMF_EDEVICE;
     if (timed) {
-        if (hipEventRecord(h->ev1[h->timed], s) != hipSuccess) return ISNMF_EDEVICE;
+        if (!on_dispatch && hipEventRecord(h->ev1[h->timed], s) != hipSuccess) return ISNMF_EDEVICE;
         ++h->timed;
     }
     return ISNMF_OK;

@@ -81,6 +81,15 @@ struct OnlineDev {
     unsigned *counter;   // spare device word (zeroed at init)
 };
 
+// Start/stop events for the next single-stream fit launch, set by a handle's
+// timing hook.  A launcher that attaches them to its dispatch (the VALU
+// variants, through hipExtLaunchKernel) clears `pending`.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool pending = false;
+};
+extern thread_local LaunchTiming g_launch_timing;
+
 // One stream's fit problem for the fused kernels (by value for a single
 // stream, an array in device memory for the batched form).
 struct FitDesc {

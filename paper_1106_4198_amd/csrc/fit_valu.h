@@ -31,6 +31,8 @@
 // operand is scaled.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "devmath.h"
 
@@ -354,6 +356,19 @@ __global__ __launch_bounds__(VT) void fit_valu_work_kernel(const FitDesc *__rest
     body<CK, RF, BF>(a, blockIdx.x);
 }
 
+// Single-stream launch of b frames; with the handle's timing events pending,
+// the events are attached to the dispatch (they then time the kernel alone).
+inline void launch_single(void (*k)(FitDesc), FitDesc a, int b, hipStream_t s) {
+    if (g_launch_timing.pending) {
+        void *args[] = {&a};
+        if (hipExtLaunchKernel(reinterpret_cast<const void *>(k), dim3(b), dim3(VT), args, 0, s,
+                               g_launch_timing.start, g_launch_timing.stop, 0) == hipSuccess)
+            g_launch_timing.pending = false;
+        return;
+    }
+    k<<<b, VT, 0, s>>>(a);
+}
+
 // Launch of the (CK, rf, BF) instance, rf = 1..17: b frames of *a (d and tab
 // null), the frames of n batched items of d, or the frames of n served chunks
 // of tab (at most max_b frames each).  Explicitly instantiated per CK in
@@ -370,7 +385,7 @@ hipError_t launch_any(const FitDesc *a, int rf, int b, const FitDesc *d, const i
         else if (d)                                                                          \
             fit_valu_multi_kernel<CK, RF, BF><<<n * NF, VT, 0, s>>>(d, items, cur, beff);     \
         else                                                                                 \
-            fit_valu_kernel<CK, RF, BF><<<b, VT, 0, s>>>(*a);                                 \
+            launch_single(&fit_valu_kernel<CK, RF, BF>, *a, b, s);                            \
         break;
         ISNMF_VALU_RF(1) ISNMF_VALU_RF(2) ISNMF_VALU_RF(3) ISNMF_VALU_RF(4)
         ISNMF_VALU_RF(5) ISNMF_VALU_RF(6) ISNMF_VALU_RF(7) ISNMF_VALU_RF(8)

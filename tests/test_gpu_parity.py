@@ -780,3 +780,35 @@ def test_multipass_out_of_range_index_is_flagged_not_read():
     cold = bd.OnlineISNMF(torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV), b, warm=False)
     with pytest.raises(bd.IsnmfError):   # the passes entry point needs warm restarts
         cold.run_passes(torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV), perm, b, H)
+
+
+@pytest.mark.parametrize("precision,cpw", [("fp32", 0), ("bf16", -4), ("fp32", 1)])
+def test_fit_timing_hook_counts_launches_and_keeps_the_bits(precision, cpw):
+    """The per-launch timing hook (the VALU variants time their dispatch
+    itself, the others bracket the launch) counts every fit launch, reports a
+    positive duration, and changes no result bit."""
+    F, K, b = 257, 24, 64
+    say(f"timing hook {precision} cpw={cpw}")
+    bd.tune_clear()
+    bd.tune_set(F, K, precision, 8 if cpw <= 0 else 4, cpw, 0)
+    try:
+        V, W0 = synth.problem(F, K, 5 * b, seed=77)
+        Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+        W0t = torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV)
+        plain = bd.OnlineISNMF(W0t, b, precision=precision)
+        timed = bd.OnlineISNMF(W0t, b, precision=precision)
+        timed.set_timing(True, 3)
+        for s in range(5):
+            plain.step(Vt[s * b:(s + 1) * b])
+            timed.step(Vt[s * b:(s + 1) * b])
+        n, ms = timed.timing()
+        assert n == 3 and ms > 0.0
+        assert torch.equal(plain.get_w64(), timed.get_w64())
+        timed.set_timing(True, 8)
+        timed.step(Vt[:b])
+        assert timed.timing()[0] == 1
+        assert plain.status() == 0 and timed.status() == 0
+        plain.close()
+        timed.close()
+    finally:
+        bd.tune_clear()
