@@ -57,7 +57,7 @@ FIT_SOURCES = {
 TRAFFIC = {
     # FETCH_SIZE 716.0 KiB x 2.0 + WRITE_SIZE 558.5 KiB x 1.0 per b=128 launch
     # (profiles/fit_valu_F513_K50_b128_pmc.md)
-    ("fit_valu_kernel<7,9,false>", "414602e3f7c1a3fb073836c5de58ce6ba3bf7d2b"): (716.0 * 2.0 + 558.5) * 1024,
+    ("fit_valu_kernel<7,9,false,8>", "95871bd11515f8a347fbf5913caec1f1600f0aa3"): (716.0 * 2.0 + 558.5) * 1024,
 }
 
 
@@ -72,7 +72,7 @@ def _src_hash(kind: str) -> str:
 def fit_kernel_name(nw: int, cpw: int, kmax: int, wg: int) -> tuple:
     """(kind, kernel symbol) of the tuned FP32 fit variant for (F, K)."""
     if cpw == 0:
-        return "valu", f"fit_valu_kernel<{(K + 7) // 8},{(F + 63) // 64},false>"
+        return "valu", f"fit_valu_kernel<{(K + 7) // 8},{(F + 8 * nw - 1) // (8 * nw)},false,{nw}>"
     return "mfma", f"fit_single_kernel<{nw},{cpw},{kmax},0,{bool(wg)}>"
 
 

@@ -84,8 +84,8 @@ typedef enum {
  * the sum taken at the start of the update.  The statistics, the fold and
  * the W update are unchanged (the penalty involves H only), and the frame
  * losses stay the d_IS terms.  Supported by FP64 and FP32 handles (FP32 runs
- * the VALU fit variant when the shape has one, F <= 1088 and K <= 64, else
- * the plain path); BF16/FP16 handles, isnmf_batch_mu, the batched and the
+ * the 8-wave VALU fit variant when the shape has one, F <= 1088 and K <= 64,
+ * else the plain path); BF16/FP16 handles, isnmf_batch_mu, the batched and the
  * served forms return ISNMF_EUNSUPPORTED for psi_lambda > 0. */
 typedef struct {
     double eps;        /* eps >= 0: shift of the small-amplitude remedy (section 2.3)     */
@@ -375,7 +375,9 @@ int isnmf_server_create(isnmf_server **out, int max_sessions, int max_per_step, 
  * waits (isnmf_server_session_state).  ISNMF_ENOMEM when footprint alone
  * exceeds hbm_budget (it could never be admitted); ISNMF_EINVAL when h is
  * already open on this server and not closed; ISNMF_EUNSUPPORTED for a handle
- * whose fit variant the engine does not run.  Admission enqueues the
+ * whose fit variant the engine does not run (an MFMA tile variant with wg =
+ * 1, cpw = 2, nw other than 4 or 8, or K > 64), for a penalty on H or the
+ * plain kernel (ISNMF_EINVAL for warm restarts).  Admission enqueues the
  * session's descriptors on the server's stream.
  */
 int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *session);
@@ -478,13 +480,17 @@ int isnmf_autotune(int F, int K, int b, const isnmf_params *p, int trials, int *
 /* Not part of the method: read / set / clear the tuning table (for
  * persisting it between processes):
  * nw = waves per workgroup, cpw = 64-row chunks per wave, wg = W read from
- * its 16-bit copies in memory instead of registers.  cpw = 0 denotes the
- * FP32 VALU variant (one frame per workgroup of nw = 8 waves) and cpw = -1
- * the BF16 16-frame tile variant (16 frames per wave, nw = 8 waves per
- * workgroup, on 16x16x32 MFMA); the served form runs the latter but not the
- * VALU variant (isnmf_server_open returns ISNMF_EUNSUPPORTED for it).  The autotuner times
- * the variants at the b it is given: a single stream's minibatch for
- * latency, or the frames of all streams of a batched step for throughput. */
+ * its 16-bit copies in memory instead of registers.  Non-positive cpw name
+ * the other variants: cpw = 0 the FP32 VALU variant (one frame per workgroup
+ * of nw = 8 waves, or of nw = 16 waves for 1088 < F <= 1152, where it is the
+ * FP32 default and the only VALU form), cpw = -4 its BF16 form (nw = 8),
+ * cpw = -1 the BF16 16-frame tile variant (16 frames per wave, nw = 8 waves
+ * per workgroup, on 16x16x32 MFMA), cpw = -2 its streamed form and cpw = -3
+ * the FP32 16-frame tile variant (16x16x4 FP32 MFMA).  The batched form runs
+ * all of them; the served form all but the MFMA tile variants with wg = 1,
+ * cpw = 2, nw other than 4 or 8, or K > 64.  The autotuner times the variants at the b
+ * it is given: a single stream's minibatch for latency, or the frames of all
+ * streams of a batched step for throughput. */
 int isnmf_tune_get(int F, int K, int precision, int *nw, int *cpw, int *wg);
 int isnmf_tune_set(int F, int K, int precision, int nw, int cpw, int wg);
 void isnmf_tune_clear(void);

@@ -284,7 +284,7 @@ int isnmf_online_init(isnmf_online **out, int F, int K, int b_max, const isnmf_p
         return ISNMF_EDEVICE;
     }
     // the register-order copy is written above; only the VALU variants read it later
-    h->d.wv_live = h->cls.cpw == 0 || h->cls.cpw == -4;
+    h->d.wv_live = (h->cls.cpw == 0 && h->cls.nw == 8) || h->cls.cpw == -4;
     *out = h;
     return ISNMF_OK;
 }

@@ -124,8 +124,8 @@ struct ServeWork {
 // Kernel variant of the fused fit for a shape: an MFMA tile variant of
 // fit_body.h (cpw >= 1: NW waves x CPW chunks of 64 rows, NF frames per
 // workgroup), the VALU variant of fit_valu.h (cpw = 0: one frame per
-// workgroup of nw = 8 waves, rf row sets and kmax / 8 components per
-// thread; cpw = -4 is its BF16 form), the 16-frame tile variant of fit_tile.h (cpw = -1: BF16
+// workgroup of nw = 8 or 16 waves, rf row sets of 8 nw rows and kmax / 8
+// components per thread; cpw = -4 is its BF16 form, 8 waves), the 16-frame tile variant of fit_tile.h (cpw = -1: BF16
 // products, nw = 8 waves of 16 frames each, rf = ceil(F / 32) contraction
 // steps of 32 rows, kmax = 32 ceil(K / 32)), its streamed form of
 // fit_stile.h (cpw = -2), or the FP32 16-frame tile variant of fit_t32.h
@@ -143,6 +143,10 @@ FitClass valu_class(int F, int K);
 // The VALU variant with bf16 products on v_dot2c_f32_bf16 (cpw = -4; the
 // same shapes as valu_class), or ok = 0.
 FitClass vbf_class(int F, int K);
+// The 16-wave form of the FP32 VALU variant for the rows past the 8-wave
+// form (cpw = 0, nw = 16, 1088 < F <= 1152, rf = 9, K <= 64; W read from the
+// FP32 working copy), or ok = 0.
+FitClass valu16_class(int F, int K);
 // The 16-frame tile variant for (F, K) with BF16 products, or ok = 0.
 FitClass tile_class(int F, int K);
 FitClass stile_class(int F, int K);

@@ -21,6 +21,14 @@
 // Two workgroup barriers per update.  Every sum has a fixed order, so results
 // are bitwise repeatable and independent of the other frames of a launch.
 //
+// 16-wave form (NW = 16, FP32): 1024 threads = 128 row groups x 8 component
+// groups, rows p + 128 r, W read from the column-major FP32 copy, the
+// partials of 16 waves summed per component.  It extends the variant past the
+// 8-wave form's 17 row sets (F <= 1088) to F <= 1152 (9 row sets of 128 rows
+// within the 128 registers of four waves per SIMD); where both forms fit, the
+// 8-wave form is the faster (the per-wave reductions and the barrier grow with
+// the wave count), so only RF = 9 is built.
+//
 // BF16 form (BF = true, the precision form's single-stream variant): the
 // products W h, W^T r2 and W^T r1 take bf16 operands two at a time on
 // v_dot2c_f32_bf16 (FP32 accumulation), with everything else (x, the ratios,
@@ -39,8 +47,7 @@
 namespace isnmf {
 namespace valu {
 
-constexpr int VT = 512;   // threads per workgroup
-constexpr int KS = 20;    // LDS floats per component: 8 N + 8 D partials, padded
+constexpr int VT = 512;   // threads per workgroup (8-wave form)
 
 template <int CTRL>
 __device__ inline float dpp(float v) {
@@ -81,8 +88,11 @@ __device__ inline float swap32_add(float a, float b) {
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-template <int CK, int RF, bool BF>
+template <int CK, int RF, bool BF, int NW = 8>
 __device__ inline void body(const FitDesc &a, int fr) {
+    static_assert(NW == 8 || (NW == 16 && !BF), "8 waves, or 16 waves in FP32");
+    constexpr int PR = 8 * NW;              // row groups: rows p + PR r
+    constexpr int KSW = 2 * NW + 4;         // LDS floats per component: N, D partials, pad
     constexpr int NV = 2 * CK;              // num/den values per thread
     constexpr int CH = (CK + 1) / 2;        // BF16: component pairs per row set
     constexpr int RH = (RF + 1) / 2;        // BF16: row-set pairs per component
@@ -95,22 +105,23 @@ __device__ inline void body(const FitDesc &a, int fr) {
     const int F = a.F, K = a.K;
     const float eps = a.eps;
 
-    __shared__ float4 red4[8 * CK * KS / 4];   // [k][N 0..7 | D 0..7 | pad] per wave w
+    __shared__ float4 red4[8 * CK * KSW / 4];   // [k][N 0..NW-1 | D 0..NW-1 | pad] per wave w
     __shared__ float hsh[8 * CK];
-    __shared__ double lred[8];
+    __shared__ double lred[NW];
     float *red = reinterpret_cast<float *>(red4);
 
-    // the last row set holds rows p + 64 (RF-1); it has rows below F in wave w
-    // iff 8w + 64 (RF-1) < F (uniform per wave)
+    // the last row set holds rows p + PR (RF-1); it has rows below F in wave w
+    // iff 8w + PR (RF-1) < F (uniform per wave)
     constexpr int RL = RF - 1;
-    const bool last_live = 8 * w + 64 * RL < F;
-    const bool last_ok = p + 64 * RL < F;
+    const bool last_live = 8 * w + PR * RL < F;
+    const bool last_ok = p + PR * RL < F;
 
-    // W from its register-order copy: one float4 per thread per 4 elements,
-    // contiguous over the workgroup (zero past F and K)
+    // W: 8 waves read its register-order copy, one float4 per thread per 4
+    // elements, contiguous over the workgroup (zero past F and K); 16 waves
+    // read the column-major FP32 copy
     constexpr int NE = RF * CK;
     float wr[RF][CK];
-    {
+    if constexpr (NW == 8) {
         const float4 *wv = reinterpret_cast<const float4 *>(a.Wv);
 #pragma unroll
         for (int g = 0; g < (NE + 3) / 4; ++g) {
@@ -120,6 +131,14 @@ __device__ inline void body(const FitDesc &a, int fr) {
             for (int j = 0; j < 4; ++j)
                 if (4 * g + j < NE) wr[(4 * g + j) / CK][(4 * g + j) % CK] = e4[j];
         }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RF; ++r)
+#pragma unroll
+            for (int c = 0; c < CK; ++c) {
+                const int f = p + PR * r, k = q + 8 * c;
+                wr[r][c] = (f < F && k < K) ? a.W[(size_t)k * F + f] : 0.f;
+            }
     }
     // BF16: W as pairs of components (model) and pairs of row sets (W^T)
     uint32_t wkp[BF ? RF : 1][BF ? CH : 1], wfp[BF ? RH : 1][BF ? CK : 1];
@@ -139,7 +158,7 @@ __device__ inline void body(const FitDesc &a, int fr) {
     int bad = 0;
 #pragma unroll
     for (int r = 0; r < RF; ++r) {
-        const int f = p + 64 * r;
+        const int f = p + PR * r;
         const bool ok = r < RL || last_ok;
         const float v = ok ? a.V[(size_t)fr * a.ldv + f] : 0.f;
         bad |= !isfinite(v);
@@ -251,7 +270,7 @@ __device__ inline void body(const FitDesc &a, int fr) {
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
                 const int c = 2 * g + (j >> 1);
-                if (c < CK) red[(q + 8 * c) * KS + (j & 1) * 8 + w] = g4[g];
+                if (c < CK) red[(q + 8 * c) * KSW + (j & 1) * NW + w] = g4[g];
             }
         }
         __syncthreads();
@@ -262,10 +281,16 @@ __device__ inline void body(const FitDesc &a, int fr) {
         if (!BF && a.psi_lambda > 0.f && w == 0)
             dpsi = a.psi_lambda / (a.psi_a + wave_sum_f32(lane < K ? hsh[lane] : 0.f));
         if (t < K) {
-            const float4 *pk = red4 + t * (KS / 4);
-            const float4 n0 = pk[0], n1 = pk[1], d0 = pk[2], d1 = pk[3];
-            const float N = ((n0.x + n0.y) + (n0.z + n0.w)) + ((n1.x + n1.y) + (n1.z + n1.w));
-            const float D = ((d0.x + d0.y) + (d0.z + d0.w)) + ((d1.x + d1.y) + (d1.z + d1.w)) + dpsi;
+            const float4 *pk = red4 + t * (KSW / 4);
+            auto sum4 = [](float4 v) { return (v.x + v.y) + (v.z + v.w); };
+            float N, D;
+            if constexpr (NW == 8) {
+                N = sum4(pk[0]) + sum4(pk[1]);
+                D = (sum4(pk[2]) + sum4(pk[3])) + dpsi;
+            } else {
+                N = (sum4(pk[0]) + sum4(pk[1])) + (sum4(pk[2]) + sum4(pk[3]));
+                D = ((sum4(pk[4]) + sum4(pk[5])) + (sum4(pk[6]) + sum4(pk[7]))) + dpsi;
+            }
             float h = hsh[t];
             if (D > 0.f && N >= 0.f)
                 h *= __builtin_amdgcn_sqrtf(N * __builtin_amdgcn_rcpf(D));
@@ -292,7 +317,7 @@ __device__ inline void body(const FitDesc &a, int fr) {
                 es = ve[r];
             }
         const int r = base + q;
-        const int f = p + 64 * r;
+        const int f = p + PR * r;
         if (r < RL || (r == RL && last_ok)) {
             const float ir = __builtin_amdgcn_rcpf(xs);
             a.R1[(size_t)fr * a.FR + f] = ir;
@@ -309,7 +334,7 @@ __device__ inline void body(const FitDesc &a, int fr) {
     if (t == 0) {
         double s = 0.0;
 #pragma unroll
-        for (int v = 0; v < 8; ++v) s += lred[v];
+        for (int v = 0; v < NW; ++v) s += lred[v];
         a.lossf[fr] = s;
     }
     if (t < K) {
@@ -318,18 +343,18 @@ __device__ inline void body(const FitDesc &a, int fr) {
     }
 }
 
-template <int CK, int RF, bool BF>
-__global__ __launch_bounds__(VT) void fit_valu_kernel(FitDesc a) {
-    body<CK, RF, BF>(a, blockIdx.x);
+template <int CK, int RF, bool BF, int NW>
+__global__ __launch_bounds__(64 * NW) void fit_valu_kernel(FitDesc a) {
+    body<CK, RF, BF, NW>(a, blockIdx.x);
 }
 
 // Batched form: item = (stream, tile of NF frames); workgroup NF*i + j fits
 // frame j of item i; frames past the stream's minibatch of this step exit.
-template <int CK, int RF, bool BF>
-__global__ __launch_bounds__(VT) void fit_valu_multi_kernel(const FitDesc *__restrict__ descs,
-                                                            const int2 *__restrict__ items,
-                                                            const long long *__restrict__ cursor,
-                                                            const int *__restrict__ beff) {
+template <int CK, int RF, bool BF, int NW>
+__global__ __launch_bounds__(64 * NW) void fit_valu_multi_kernel(const FitDesc *__restrict__ descs,
+                                                                 const int2 *__restrict__ items,
+                                                                 const long long *__restrict__ cursor,
+                                                                 const int *__restrict__ beff) {
     const int2 it = items[blockIdx.x / NF];
     const int fr = it.y * NF + (int)(blockIdx.x % NF);
     const int b = beff[it.x];
@@ -339,53 +364,60 @@ __global__ __launch_bounds__(VT) void fit_valu_multi_kernel(const FitDesc *__res
     a.b = b;
     a.V += c * a.ldv;
     if (a.Hb) a.Hb += c * a.ldh;
-    body<CK, RF, BF>(a, fr);
+    body<CK, RF, BF, NW>(a, fr);
 }
 
 // Served form: grid (frame j, chunk i) over a step's work list (the frame
 // index in x, whose range is the larger); frames past the chunk exit.
-template <int CK, int RF, bool BF>
-__global__ __launch_bounds__(VT) void fit_valu_work_kernel(const FitDesc *__restrict__ tab,
-                                                           const ServeWork *__restrict__ work) {
+template <int CK, int RF, bool BF, int NW>
+__global__ __launch_bounds__(64 * NW) void fit_valu_work_kernel(const FitDesc *__restrict__ tab,
+                                                                const ServeWork *__restrict__ work) {
     const ServeWork wk = work[blockIdx.y];
     if ((int)blockIdx.x >= wk.b) return;   // uniform per workgroup
     FitDesc a = tab[wk.sess];
     a.b = wk.b;
     a.V = wk.V;
     a.ldv = wk.ldv;
-    body<CK, RF, BF>(a, blockIdx.x);
+    body<CK, RF, BF, NW>(a, blockIdx.x);
 }
 
-// Single-stream launch of b frames; with the handle's timing events pending,
-// the events are attached to the dispatch (they then time the kernel alone).
-inline void launch_single(void (*k)(FitDesc), FitDesc a, int b, hipStream_t s) {
+// Single-stream launch of b frames of nt threads; with the handle's timing
+// events pending, the events are attached to the dispatch (they then time the
+// kernel alone).
+inline void launch_single(void (*k)(FitDesc), FitDesc a, int b, int nt, hipStream_t s) {
     if (g_launch_timing.pending) {
         void *args[] = {&a};
-        if (hipExtLaunchKernel(reinterpret_cast<const void *>(k), dim3(b), dim3(VT), args, 0, s,
+        if (hipExtLaunchKernel(reinterpret_cast<const void *>(k), dim3(b), dim3(nt), args, 0, s,
                                g_launch_timing.start, g_launch_timing.stop, 0) == hipSuccess)
             g_launch_timing.pending = false;
         return;
     }
-    k<<<b, VT, 0, s>>>(a);
+    k<<<b, nt, 0, s>>>(a);
 }
 
-// Launch of the (CK, rf, BF) instance, rf = 1..17: b frames of *a (d and tab
-// null), the frames of n batched items of d, or the frames of n served chunks
-// of tab (at most max_b frames each).  Explicitly instantiated per CK in
-// fit_valu_ck*.hip, so the instances build in parallel.
-template <int CK, bool BF>
+// Launch of the (CK, rf, BF, NW) instance (rf = 1..17 with 8 waves, 9 with
+// 16): b frames of *a (d and tab null), the frames of n batched items of d,
+// or the frames of n served chunks of tab (at most max_b frames each).
+// Explicitly instantiated per CK in fit_valu_ck*.hip, so the instances build
+// in parallel.
+template <int CK, bool BF, int NW>
 hipError_t launch_any(const FitDesc *a, int rf, int b, const FitDesc *d, const int2 *items, int n,
                       const long long *cur, const int *beff, const FitDesc *tab,
                       const ServeWork *work, int max_b, hipStream_t s) {
+    constexpr int nt = 64 * NW;
+    constexpr int rf_min = NW == 8 ? 1 : 9, rf_max = NW == 8 ? 17 : 9;
+    if (rf < rf_min || rf > rf_max) return hipErrorNotSupported;
     switch (rf) {
-#define ISNMF_VALU_RF(RF)                                                                    \
-    case RF:                                                                                 \
-        if (tab)                                                                             \
-            fit_valu_work_kernel<CK, RF, BF><<<dim3(max_b, n), VT, 0, s>>>(tab, work);        \
-        else if (d)                                                                          \
-            fit_valu_multi_kernel<CK, RF, BF><<<n * NF, VT, 0, s>>>(d, items, cur, beff);     \
-        else                                                                                 \
-            launch_single(&fit_valu_kernel<CK, RF, BF>, *a, b, s);                            \
+#define ISNMF_VALU_RF(RF)                                                                        \
+    case RF:                                                                                     \
+        if constexpr (RF >= rf_min && RF <= rf_max) {                                            \
+            if (tab)                                                                             \
+                fit_valu_work_kernel<CK, RF, BF, NW><<<dim3(max_b, n), nt, 0, s>>>(tab, work);    \
+            else if (d)                                                                          \
+                fit_valu_multi_kernel<CK, RF, BF, NW><<<n * NF, nt, 0, s>>>(d, items, cur, beff); \
+            else                                                                                 \
+                launch_single(&fit_valu_kernel<CK, RF, BF, NW>, *a, b, nt, s);                    \
+        }                                                                                        \
         break;
         ISNMF_VALU_RF(1) ISNMF_VALU_RF(2) ISNMF_VALU_RF(3) ISNMF_VALU_RF(4)
         ISNMF_VALU_RF(5) ISNMF_VALU_RF(6) ISNMF_VALU_RF(7) ISNMF_VALU_RF(8)
@@ -399,13 +431,16 @@ hipError_t launch_any(const FitDesc *a, int rf, int b, const FitDesc *d, const i
     return hipGetLastError();
 }
 
-#define ISNMF_VALU_SIG(CKV, BFV)                                                               \
-    hipError_t launch_any<CKV, BFV>(const FitDesc *, int, int, const FitDesc *, const int2 *,  \
-                                    int, const long long *, const int *, const FitDesc *,      \
-                                    const ServeWork *, int, hipStream_t);
-#define ISNMF_VALU_EXTERN(CKV) \
-    extern template ISNMF_VALU_SIG(CKV, false) extern template ISNMF_VALU_SIG(CKV, true)
-#define ISNMF_VALU_INSTANTIATE(CKV) template ISNMF_VALU_SIG(CKV, false) template ISNMF_VALU_SIG(CKV, true)
+#define ISNMF_VALU_SIG(CKV, BFV, NWV)                                                           \
+    hipError_t launch_any<CKV, BFV, NWV>(const FitDesc *, int, int, const FitDesc *, const int2 *, \
+                                         int, const long long *, const int *, const FitDesc *,     \
+                                         const ServeWork *, int, hipStream_t);
+#define ISNMF_VALU_EXTERN(CKV)                                                      \
+    extern template ISNMF_VALU_SIG(CKV, false, 8) extern template ISNMF_VALU_SIG(CKV, true, 8) \
+    extern template ISNMF_VALU_SIG(CKV, false, 16)
+#define ISNMF_VALU_INSTANTIATE(CKV)                                            \
+    template ISNMF_VALU_SIG(CKV, false, 8) template ISNMF_VALU_SIG(CKV, true, 8) \
+    template ISNMF_VALU_SIG(CKV, false, 16)
 
 }  // namespace valu
 }  // namespace isnmf

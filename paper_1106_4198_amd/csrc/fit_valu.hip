@@ -15,22 +15,30 @@ ISNMF_VALU_EXTERN(8)
 }  // namespace valu
 
 namespace {
-constexpr int VALU_RF_MAX = 17;   // F <= 1088
-constexpr int VALU_CK_MAX = 8;    // K <= 64
+constexpr int VALU_RF_MAX = 17;     // F <= 1088 (8 waves)
+constexpr int VALU16_RF_MAX = 9;    // 1088 < F <= 1152 (16 waves)
+constexpr int VALU_CK_MAX = 8;      // K <= 64
 
-// cpw 0: FP32 products; cpw -4: bf16 products on v_dot2c_f32_bf16.
+// rows per row set of the class's workgroup
+int rows_per_set(const FitClass &c) { return 8 * c.nw; }
+
+// cpw 0: FP32 products (8 or 16 waves); cpw -4: bf16 products on
+// v_dot2c_f32_bf16 (8 waves).
 hipError_t launch(const FitClass &c, const FitDesc *a, int b, const FitDesc *d, const int2 *items,
                   int n, const long long *cur, const int *beff, const FitDesc *tab,
                   const ServeWork *work, int max_b, hipStream_t s) {
     if (!c.ok || (c.cpw != 0 && c.cpw != -4) || c.kmax % 8 != 0) return hipErrorNotSupported;
-    const bool bf = c.cpw == -4;
+    if (c.nw != 8 && !(c.nw == 16 && c.cpw == 0)) return hipErrorNotSupported;
+    const bool bf = c.cpw == -4, w16 = c.nw == 16;
     switch (c.kmax / 8) {
-#define ISNMF_VALU_CK(CKV)                                                                     \
-    case CKV:                                                                                  \
-        return bf ? valu::launch_any<CKV, true>(a, c.rf, b, d, items, n, cur, beff, tab, work, \
-                                                max_b, s)                                      \
-                  : valu::launch_any<CKV, false>(a, c.rf, b, d, items, n, cur, beff, tab, work, \
-                                                 max_b, s);
+#define ISNMF_VALU_CK(CKV)                                                                          \
+    case CKV:                                                                                       \
+        return bf    ? valu::launch_any<CKV, true, 8>(a, c.rf, b, d, items, n, cur, beff, tab, work, \
+                                                      max_b, s)                                     \
+               : w16 ? valu::launch_any<CKV, false, 16>(a, c.rf, b, d, items, n, cur, beff, tab,    \
+                                                        work, max_b, s)                             \
+                     : valu::launch_any<CKV, false, 8>(a, c.rf, b, d, items, n, cur, beff, tab,     \
+                                                       work, max_b, s);
         ISNMF_VALU_CK(1) ISNMF_VALU_CK(2) ISNMF_VALU_CK(3) ISNMF_VALU_CK(4)
         ISNMF_VALU_CK(5) ISNMF_VALU_CK(6) ISNMF_VALU_CK(7) ISNMF_VALU_CK(8)
 #undef ISNMF_VALU_CK
@@ -52,6 +60,19 @@ FitClass valu_class(int F, int K) {
     return c;
 }
 
+FitClass valu16_class(int F, int K) {
+    FitClass c = {};
+    const int rf = (F + 127) / 128, ck = (K + 7) / 8;
+    if (F <= 64 * VALU_RF_MAX || K < 1 || rf > VALU16_RF_MAX || ck > VALU_CK_MAX) return c;
+    c.ok = 1;
+    c.nw = 16;
+    c.cpw = 0;
+    c.kmax = 8 * ck;
+    c.wg = 0;
+    c.rf = rf;
+    return c;
+}
+
 FitClass vbf_class(int F, int K) {
     FitClass c = valu_class(F, K);
     if (c.ok) c.cpw = -4;
@@ -59,7 +80,9 @@ FitClass vbf_class(int F, int K) {
 }
 
 hipError_t launch_fit_valu(const FitDesc &a, const FitClass &c, int b, hipStream_t s) {
-    if (c.rf != (a.F + 63) / 64 || c.kmax < a.K || !a.Wv) return hipErrorInvalidValue;
+    const int pr = rows_per_set(c);
+    if (c.rf != (a.F + pr - 1) / pr || c.kmax < a.K || (c.nw == 8 && !a.Wv))
+        return hipErrorInvalidValue;
     return launch(c, &a, b, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, s);
 }
 

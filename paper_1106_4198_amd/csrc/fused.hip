@@ -64,8 +64,9 @@ FitClass fit_class(int F, int K, int prec) {
         }
         c.ok = 1;
     }
-    // FP32 and BF16 beyond the register-resident MFMA tiles: one frame per workgroup
-    if (!c.ok && prec == 0) return valu_class(F, K);
+    // FP32 and BF16 beyond the register-resident MFMA tiles: one frame per
+    // workgroup (FP32 past the 8-wave form's rows: its 16-wave form)
+    if (!c.ok && prec == 0) return valu_class(F, K).ok ? valu_class(F, K) : valu16_class(F, K);
     if (!c.ok && prec == 1) return vbf_class(F, K);
     return c;
 }

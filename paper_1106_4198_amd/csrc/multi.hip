@@ -316,8 +316,8 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         if (isnmf_handle_kernel(handles[s]) != ISNMF_KERNEL_FUSED) return ISNMF_EUNSUPPORTED;
         if (p.psi_lambda > 0.0) return ISNMF_EUNSUPPORTED;            // no penalty on H
         if (b[s] > 512) return ISNMF_EUNSUPPORTED;                   // single fold slice
-        const int cpw = isnmf_handle_class(handles[s])->cpw;
-        if ((cpw == 0 || cpw == -4) && !d.Wv) return ISNMF_EUNSUPPORTED;
+        const FitClass &c = *isnmf_handle_class(handles[s]);
+        if (((c.cpw == 0 && c.nw == 8) || c.cpw == -4) && !d.Wv) return ISNMF_EUNSUPPORTED;
         for (int r = 0; r < s; ++r)
             if (handles[r] == handles[s]) return ISNMF_EINVAL;        // one entry per stream
     }

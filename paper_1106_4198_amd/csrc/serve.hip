@@ -530,7 +530,7 @@ int isnmf_server_open(isnmf_server *s, isnmf_online *h, size_t footprint, int *s
     // variants with a served kernel of their own: the 16-frame tiles and the VALU forms
     const bool own = ((c.cpw == -1 || c.cpw == -2 || c.cpw == -4) && prec_of(p) == 1) ||
                      ((c.cpw == -3 || c.cpw == 0) && prec_of(p) == 0);
-    if ((c.cpw == 0 || c.cpw == -4) && !d.Wv) return ISNMF_EUNSUPPORTED;
+    if (((c.cpw == 0 && c.nw == 8) || c.cpw == -4) && !d.Wv) return ISNMF_EUNSUPPORTED;
     if (!own && (c.wg || c.cpw != 1 || (c.nw != 4 && c.nw != 8) || c.kmax > 64))
         return ISNMF_EUNSUPPORTED;
     if (footprint > s->budget) return ISNMF_ENOMEM;   // could never be admitted

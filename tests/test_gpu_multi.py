@@ -321,10 +321,13 @@ def test_fp32_tile_and_valu_batched_equal_alone_bitwise(precision, cpw):
     bits of the same streams run alone."""
     shapes = [(513, 50, 128, 300), (513, 50, 128, 256), (257, 64, 64, 200), (129, 8, 200, 390),
               (592, 64, 33, 70), (1025, 32, 128, 130)]
+    if cpw == 0:   # and the 16-wave form past F = 1088 (the default there)
+        shapes += [(1100, 40, 64, 130), (1152, 64, 17, 40)]
     say(f"{precision} cpw={cpw} batched vs alone")
     bd.tune_clear()
     for F, K, _, _ in shapes:
-        bd.tune_set(F, K, precision, 8, cpw, 0)
+        if F <= 1088:
+            bd.tune_set(F, K, precision, 8, cpw, 0)
     try:
         data = []
         for i, (F, K, b, N) in enumerate(shapes):

@@ -156,6 +156,27 @@ def test_step_fp32_valu(F, K, b):
         compare_step(F, K, b, 20, "fp32", "fused", seed=27, tol=1e-5)
 
 
+# the 16-wave form of the VALU variant: the FP32 default past the 8-wave form's
+# rows (1088 < F <= 1152), 9 row sets of 128 rows with a ragged last set, K
+# across the component groups of 8 (1..8, ragged)
+@pytest.mark.parametrize("F,K,b", [(1089, 40, 3), (1152, 64, 5), (1100, 57, 33), (1120, 1, 4),
+                                   (1150, 24, 9), (1130, 8, 1), (1097, 33, 130)])
+def test_step_fp32_valu16(F, K, b):
+    bd.tune_clear()
+    assert bd.tune_get(F, K, "fp32") == (16, 0, 0)
+    compare_step(F, K, b, 20, "fp32", "fused", seed=27, tol=1e-5)
+
+
+def test_step_fp32_valu16_variants():
+    bd.tune_clear()
+    compare_step(1100, 10, 11, 6, "fp32", "fused", seed=22, tol=1e-5, warm=True)
+    compare_step(1100, 10, 11, 6, "fp32", "fused", seed=23, tol=1e-5, rho=0.7)
+    compare_step(1100, 10, 11, 6, "fp32", "fused", seed=24, tol=1e-5, normalize=False)
+    compare_step(1100, 10, 11, 6, "fp32", "fused", seed=25, tol=1e-5, update_w=False)
+    compare_step(1100, 10, 5, 6, "fp32", "fused", seed=26, tol=1e-5, b_max=16)
+    compare_step(1100, 10, 5, 0, "fp32", "fused", seed=28, tol=1e-5)
+
+
 def test_step_fp32_valu_variants():
     with valu_variant(130, 10):
         compare_step(130, 10, 11, 6, "fp32", "fused", seed=22, tol=1e-5, warm=True)
@@ -235,6 +256,9 @@ def test_fp32_wide_F_uses_the_valu_variant():
     assert g.kernel_used == "fused"
     assert bd.tune_get(1025, 40, "fp32") == (8, 0, 0)
     W0 = torch.rand((40, 1089), dtype=torch.float32, device=DEV) + 0.5
+    assert bd.OnlineISNMF(W0, 4, kernel="auto").kernel_used == "fused"
+    assert bd.tune_get(1089, 40, "fp32") == (16, 0, 0)   # past the 8-wave form's rows
+    W0 = torch.rand((40, 1153), dtype=torch.float32, device=DEV) + 0.5
     assert bd.OnlineISNMF(W0, 4, kernel="auto").kernel_used == "plain"
 
 

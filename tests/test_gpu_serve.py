@@ -367,20 +367,25 @@ def test_served_tile_sessions_equal_alone_bitwise(cpw):
         bd.tune_clear()
 
 
-@pytest.mark.parametrize("precision,cpw", [("fp32", -3), ("fp32", 0), ("bf16", -4)])
+@pytest.mark.parametrize("precision,cpw", [("fp32", -3), ("fp32", 0), ("bf16", -4), ("fp32", None)])
 def test_served_own_kernel_sessions_equal_alone_bitwise(precision, cpw):
     """Sessions on the variants with served kernels of their own (the FP32
     16-frame tile, and the VALU variant in FP32 and BF16: one workgroup per
-    frame) give the bits of the same sessions run alone."""
+    frame; cpw None: the VALU variant's 16-wave form, the FP32 default past
+    F = 1088) give the bits of the same sessions run alone."""
     say(f"served {precision} cpw={cpw}")
     bd.tune_clear()
-    bd.tune_set(513, 64, precision, 8, cpw, 0)
-    bd.tune_set(257, 32, precision, 8, cpw, 0)
+    shapes = [(513, 64), (257, 32)] if cpw is not None else [(1100, 64), (1130, 32)]
+    for F, K in shapes:
+        if cpw is not None:
+            bd.tune_set(F, K, precision, 8, cpw, 0)
+        else:
+            assert bd.tune_get(F, K, precision) == (16, 0, 0)
     try:
         rng = np.random.default_rng(9)
         data = []
         for i in range(6):
-            F, K = [(513, 64), (257, 32)][i % 2]
+            F, K = shapes[i % 2]
             lens = rng.integers(1, 300, size=3)
             V, W0 = synth.problem(F, K, int(lens.sum()), seed=700 + i)
             Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
