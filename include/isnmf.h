@@ -266,7 +266,8 @@ int isnmf_online_destroy(isnmf_online *h);
  * minibatch of every stream that has frames left (fresh restarts), folds it
  * into that stream's A and B and updates its W -- exactly
  * isnmf_online_step on each handle, with one fit launch per kernel variant
- * in use and one fold and one rescale launch for all streams.  The frame
+ * in use and one fold (see isnmf_multi_launches) and one rescale launch for
+ * all streams.  The frame
  * cursors live on the device, so a step can be captured into a hipGraph and
  * replayed (isnmf_multi_run with use_graph).
  *
@@ -304,6 +305,13 @@ int isnmf_multi_run(isnmf_multi *m, int steps, int use_graph, void *stream);
 /* Not part of the method: largest number of frames any stream has left
  * (host bookkeeping). */
 int isnmf_multi_frames_left(const isnmf_multi *m, long long *host_max_left);
+
+/* Not part of the method: the launches of one step of the plan.
+ * *fit_launches: one per group of streams on one kernel variant;
+ * *fold_launches: 1, or 0 when every stream is on the 16-frame tile variant
+ * with b[s] <= 128, so that each fit launch folds its streams' minibatches
+ * itself (the same bits as the fold launch). */
+int isnmf_multi_launches(const isnmf_multi *m, int *fit_launches, int *fold_launches);
 
 /* Not part of the method: wait for the plan's streams and free it (not the
  * handles, not the workspace). */

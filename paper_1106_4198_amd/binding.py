@@ -74,6 +74,7 @@ def _load():
         "isnmf_multi_step": (i, [vp, vp]),
         "isnmf_multi_run": (i, [vp, i, i, vp]),
         "isnmf_multi_frames_left": (i, [vp, ctypes.POINTER(ctypes.c_longlong)]),
+        "isnmf_multi_launches": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "isnmf_multi_destroy": (i, [vp]),
         "isnmf_autotune_workspace_size": (sz, [i, i, i, P]),
         "isnmf_autotune": (i, [i, i, i, P, i, ctypes.POINTER(i), ctypes.POINTER(d), vp, sz, vp]),
@@ -119,7 +120,7 @@ EXPORTED = ("isnmf_params_default", "isnmf_strerror", "isnmf_forgetting_rho",
             "isnmf_online_destroy", "isnmf_online_pass", "isnmf_online_passes", "isnmf_online_fit",
             "isnmf_online_set_timing", "isnmf_online_timing",
             "isnmf_multi_workspace_size", "isnmf_multi_create", "isnmf_multi_step",
-            "isnmf_multi_run", "isnmf_multi_frames_left", "isnmf_multi_destroy",
+            "isnmf_multi_run", "isnmf_multi_frames_left", "isnmf_multi_launches", "isnmf_multi_destroy",
             "isnmf_autotune_workspace_size", "isnmf_autotune", "isnmf_tune_get", "isnmf_tune_set",
             "isnmf_tune_clear",
             "isnmf_server_workspace_size", "isnmf_server_create", "isnmf_server_open",
@@ -194,13 +195,17 @@ def _req(t, dtype, shape=None, name="tensor"):
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
-    if t.dim() == 2 and t.stride(1) != 1:
+    if t.dim() == 2 and t.shape[1] > 1 and t.stride(1) != 1:
         raise ValueError(f"{name} rows must be contiguous")
     return t
 
 
 def _ld(t):
-    return t.stride(0) if t.dim() == 2 else t.shape[-1]
+    """Row stride in elements; a single row's stride is arbitrary (numpy and
+    torch leave it so), and its row length serves."""
+    if t.dim() != 2:
+        return t.shape[-1]
+    return t.stride(0) if t.shape[0] > 1 else t.shape[1]
 
 
 class OnlineISNMF:
@@ -385,6 +390,13 @@ class MultiISNMF:
         n = ctypes.c_longlong()
         _check(_lib.isnmf_multi_frames_left(self._m, ctypes.byref(n)), "frames_left")
         return n.value
+
+    def launches(self) -> tuple:
+        """(fit launches, fold launches) of one step; 0 fold launches when every
+        fit launch folds its streams itself."""
+        f, g = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.isnmf_multi_launches(self._m, ctypes.byref(f), ctypes.byref(g)), "launches")
+        return f.value, g.value
 
     def close(self):
         if getattr(self, "_m", None):

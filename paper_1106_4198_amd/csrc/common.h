@@ -90,6 +90,8 @@ struct LaunchTiming {
 };
 extern thread_local LaunchTiming g_launch_timing;
 
+struct FoldArgs;   // fold_body.h
+
 // One stream's fit problem for the fused kernels (by value for a single
 // stream, an array in device memory for the batched form).
 struct FitDesc {
@@ -110,6 +112,10 @@ struct FitDesc {
     float *R1, *R2;            // b x FR
     double *lossf;             // b
     int *flags;
+    // The stream's fold (device memory) when the fit launch folds the minibatch
+    // itself (the batched form's 16-frame tile streams of at most 128 frames),
+    // else null: the fit then writes R1, R2 for a separate fold.
+    const FoldArgs *fold;
 };
 
 // One chunk of a served step: session (index in the server's device tables),
@@ -185,8 +191,13 @@ hipError_t launch_fit_valu_multi(const FitClass &c, const FitDesc *d, const int2
                                  const long long *cur, const int *beff, hipStream_t s);
 // 16-frame tile variant launches: b frames, or n batched items (stream, tile of 16 frames).
 hipError_t launch_fit_tile(const FitDesc &a, const FitClass &c, int b, hipStream_t s);
+// fold: the launch folds each minibatch itself (every descriptor's fold is set;
+// tile_fold_fits(c) holds).
 hipError_t launch_fit_tile_multi(const FitClass &c, const FitDesc *d, const int2 *items, int n,
-                                 const long long *cur, const int *beff, hipStream_t s);
+                                 const long long *cur, const int *beff, bool fold, hipStream_t s);
+// The 16-frame tile variant of class c can fold in its launch (its LDS holds the
+// fold's staging beside the X operands).
+bool tile_fold_fits(const FitClass &c);
 // ... and over a served step's work list: n chunks, `tiles` tiles of 128 frames each.
 hipError_t launch_fit_tile_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
                                 int tiles, hipStream_t s);

@@ -28,6 +28,7 @@
 
 #include "common.h"
 #include "devmath.h"
+#include "fold_body.h"
 
 namespace isnmf {
 namespace tile {
@@ -74,8 +75,23 @@ __host__ __device__ constexpr size_t lds_bytes(int S, int KS) {
     return (size_t)(2 * S * KS + S * 2 * KS) * 64 * 16;
 }
 
+// The folding final pass (FOLD) keeps the X operands and, past them, over the
+// W^T operands: the ratios of two row tiles for all 128 frames in two buffers
+// ([buffer][tile][r2, r1][frame][16 rows] floats; buffer 1 first carries h of
+// every frame), a per-wave slab pair for the epilogue, the 128 frame losses.
+constexpr size_t FOLD_STAGE = (size_t)2 * 2 * 2 * FPW * 16 * 4;
+constexpr size_t FOLD_EXTRA = FOLD_STAGE + (size_t)NWT * 2 * RSLAB * 4 + (size_t)FPW * 8;
+constexpr size_t LDS_MAX = 160 * 1024;
+__host__ __device__ constexpr size_t lds_fold_bytes(int S, int KS) {
+    return lds_bytes(S, KS) > (size_t)2 * S * KS * 64 * 16 + FOLD_EXTRA
+               ? lds_bytes(S, KS)
+               : (size_t)2 * S * KS * 64 * 16 + FOLD_EXTRA;
+}
+
 // S = ceil(F / 32) contraction steps, KS = ceil(K / 32) component steps.
-template <int S, int KS>
+// FOLD: the workgroup holds the stream's whole minibatch (b <= 128, n_first =
+// 0) and folds it (a.fold) instead of writing R1 and R2.
+template <int S, int KS, bool FOLD>
 __device__ inline void body(const FitDesc &a, int n_first) {
     constexpr int T = 2 * S;        // 16-row tiles (the last may be past F)
     constexpr int MT = 2 * KS;      // 16-component m-tiles
@@ -304,16 +320,159 @@ __device__ inline void body(const FitDesc &a, int n_first) {
     }
     if (guard) atomicOr(a.flags, FLAG_GUARD_H);
 
-    // ---- final model: R1, R2 for the fold (FP32) and the frame loss.  v (FP32)
-    // is read FPD row tiles ahead of its use, so that the loads are in flight
-    // during the tiles before (the update loop's registers are free here).
+    // ---- final model: R1, R2 for the fold (FP32), or the fold itself, and the
+    // frame loss.
+    double ls = 0.0;
+    if constexpr (FOLD) {
+        // The fold of the minibatch (Algorithm 1's statistics update and W =
+        // sqrt(A/B)) in this workgroup.  Round r takes row tiles 2r and 2r + 1:
+        // every wave forms its frames' ratios there and stages them in LDS,
+        // then wave w folds row tile 2r + (w & 1) over component tile w >> 1
+        // for all frames, with the separate fold's MFMA chains (frames with
+        // (n / 4) mod 4 = v in increasing n), chain sums and epilogue
+        // (fold_rows_body), so the bits are those of the fit followed by that
+        // fold.  The ratio buffers alternate, one barrier per round.
+        const FoldArgs &fa0 = *a.fold;
+        FoldArgs fa = fa0;
+        fa.b = a.b;
+        constexpr int CW = 32 * KS;                  // LDS floats per frame of h
+        constexpr int RB = 2 * FPW * 16;             // floats per staged row tile (r2, r1)
+        float *stg = reinterpret_cast<float *>(wl + 2 * S * KS * 64);
+        float *slab = stg + 4 * RB + w * 2 * RSLAB;
+        const int KT = (K + 15) / 16;
+        const int kt = w >> 1, uw = w & 1;
+        const bool kact = kt < KT;   // uniform per wave
+        // h of every frame through buffer 1 (zero past the minibatch and past
+        // K, as the separate fold stages it); wave w keeps the column of its
+        // component tile for all 128 frames.  The barrier first: the W^T
+        // operands under the buffers may still be read by the last update.
+        __syncthreads();
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            f4 hv;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) hv[j] = (fok && 16 * mt + 4 * g + j < K) ? hq[mt][j] : 0.f;
+            *reinterpret_cast<f4 *>(stg + 2 * RB + (WF * w + n) * CW + 16 * mt + 4 * g) = hv;
+        }
+        __syncthreads();
+        float hh[32];
+#pragma unroll
+        for (int m = 0; m < 32; ++m) hh[m] = kact ? stg[2 * RB + (4 * m + g) * CW + 16 * kt + n] : 0.f;
+        // v (FP32) of a round's two row tiles and the epilogue operands of the
+        // wave's fold tile (element (16 tf + n, 16 kt + 4 g + j) in pass j: W,
+        // A, B), read one round ahead; the pending column scales of its columns
+        float vc[2][4], vn[2][4];
+        double eo[3][4], en[3][4];   // [W, A, B][j]
+        double scq[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int kc = 16 * kt + 4 * g + j;
+            scq[j] = kact && kc < K ? fa.sc[kc] : 1.0;
+        }
+        auto load_eo = [&](int r, double (&o)[3][4]) {
+            const int tf = 2 * r + uw, fe = 16 * tf + n;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int kc = 16 * kt + 4 * g + j;
+                const bool ok = kact && fe < F && kc < K;
+                const size_t e = ok ? (size_t)fe + (size_t)kc * F : 0;
+                o[0][j] = ok ? fa.W64[e] : 0.0;
+                o[1][j] = ok ? fa.A[e] : 0.0;
+                o[2][j] = ok ? fa.B[e] : 0.0;
+            }
+        };
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) vc[u][j] = load_v(u, j);
+        load_eo(0, eo);
+#pragma unroll 1
+        for (int r = 0; r < S; ++r) {
+            float *sb0 = stg + (r & 1) * 2 * RB;
+            const int tf = 2 * r + uw;                 // this wave's fold row tile
+            const bool fact = kact && 16 * tf < F;     // uniform per wave
+            const int fe = 16 * tf + n;
+            if (r + 1 < S) load_eo(r + 1, en);
+            if (r + 1 < S) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) vn[u][j] = load_v(2 * r + 2 + u, j);
+            }
+            // ratios of row tiles 2r and 2r + 1 of this wave's frames (zero for
+            // frames past the minibatch) and the frame loss terms
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int t = 2 * r + u;
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+                const f4 x = model(t);
+                const int row0 = 16 * t + 4 * g;
+                f4 r1, r2;
+                float l = 0.f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float rr = __builtin_amdgcn_rcpf(x[j]);
+                    const float ve = vprime(t, j, vc[u][j]);
+                    r1[j] = fok ? rr : 0.f;
+                    r2[j] = fok ? ve * rr * rr : 0.f;
+                    if (row0 + j < F) l += dis_term32(ve, rr);
+                }
+                ls += double(l);
+                float *sr = sb0 + u * RB;
+                *reinterpret_cast<f4 *>(sr + (WF * w + n) * 16 + 4 * g) = r2;
+                *reinterpret_cast<f4 *>(sr + FPW * 16 + (WF * w + n) * 16 + 4 * g) = r1;
+            }
+            __syncthreads();
+            if (fact) {
+                const float *sr2 = sb0 + uw * RB, *sr1 = sr2 + FPW * 16;
+                floatx4 ca[4], cb[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    ca[v] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    cb[v] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+#pragma unroll
+                for (int m = 0; m < 32; ++m) {
+                    if (4 * m < fa.b) {   // groups of 4 frames that start in the minibatch
+                        const int nl = 4 * m + g;
+                        ca[m & 3] = mfma16(sr2[nl * 16 + n], hh[m], ca[m & 3]);
+                        cb[m & 3] = mfma16(sr1[nl * 16 + n], hh[m], cb[m & 3]);
+                    }
+                }
+                const floatx4 sa = ((ca[0] + ca[1]) + ca[2]) + ca[3];
+                const floatx4 sb = ((cb[0] + cb[1]) + cb[2]) + cb[3];
+                reinterpret_cast<floatx4 *>(slab)[red_pos(lane)] = sa;
+                reinterpret_cast<floatx4 *>(slab + RSLAB)[red_pos(lane)] = sb;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int cl = 4 * g + j;
+                    const float ea = red_elem(slab, n, cl);
+                    const float eb = red_elem(slab + RSLAB, n, cl);
+                    const int kc = 16 * kt + cl;
+                    if (fe < F && kc < K)
+                        epilogue(fa, fe, kc, double(ea), double(eb), eo[0][j], eo[1][j] / scq[j],
+                                 eo[2][j] * scq[j]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) vc[u][j] = vn[u][j];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) eo[i][j] = en[i][j];
+        }
+    } else {
+    // v (FP32) is read FPD row tiles ahead of its use, so that the loads are in
+    // flight during the tiles before (the update loop's registers are free here)
     constexpr int FPD = 8;
     float vf[T][4];
 #pragma unroll
     for (int t = 0; t < FPD && t < T; ++t)
 #pragma unroll
         for (int j = 0; j < 4; ++j) vf[t][j] = load_v(t, j);
-    double ls = 0.0;
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         asm volatile("" ::: "memory");
@@ -340,11 +499,29 @@ __device__ inline void body(const FitDesc &a, int n_first) {
             *reinterpret_cast<f4 *>(a.R2 + (size_t)fr * a.FR + row0) = r2;
         }
     }
+    }
     // frame n's loss: lanes n, n + 16, n + 32, n + 48, in that order
     const double l1 = __shfl_xor(ls, 16, 64);
     const double l2 = __shfl_xor(ls, 32, 64);
     const double l3 = __shfl_xor(ls, 48, 64);
-    if (g == 0 && fok) a.lossf[fr] = ((ls + l1) + l2) + l3;
+    const double lframe = ((ls + l1) + l2) + l3;
+    if (g == 0 && fok) a.lossf[fr] = lframe;
+    if constexpr (FOLD) {
+        // the minibatch loss as the separate fold adds it: wave 1, lane l sums
+        // frames l, l + 64 in order, then a fixed xor butterfly over the lanes
+        double *lsh = reinterpret_cast<double *>(reinterpret_cast<char *>(wl) + 2 * S * KS * 64 * 16 +
+                                                 FOLD_STAGE + NWT * 2 * RSLAB * 4);
+        if (g == 0) lsh[WF * w + n] = lframe;
+        __syncthreads();
+        const FoldArgs *fa = a.fold;
+        if (fa->d_loss_sum && w == 1) {
+            double sl = 0.0;
+            for (int m = lane; m < a.b; m += 64) sl += lsh[m];
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) sl += __shfl_xor(sl, m, 64);
+            if (lane == 0) *fa->d_loss_sum += sl;
+        }
+    }
     if (fok) {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -361,12 +538,13 @@ __device__ inline void body(const FitDesc &a, int n_first) {
 
 template <int S, int KS>
 __global__ __launch_bounds__(NWT * 64) void fit_tile_kernel(FitDesc a) {
-    body<S, KS>(a, blockIdx.x * FPW);
+    body<S, KS, false>(a, blockIdx.x * FPW);
 }
 
 // Batched form: item = (stream, tile of 128 frames); tiles past the stream's
-// minibatch of this step exit.
-template <int S, int KS>
+// minibatch of this step exit.  FOLD: every stream of the launch has one tile
+// (b <= 128) and a fold descriptor.
+template <int S, int KS, bool FOLD>
 __global__ __launch_bounds__(NWT * 64) void fit_tile_multi_kernel(const FitDesc *__restrict__ descs,
                                                                   const int2 *__restrict__ items,
                                                                   const long long *__restrict__ cursor,
@@ -379,7 +557,7 @@ __global__ __launch_bounds__(NWT * 64) void fit_tile_multi_kernel(const FitDesc 
     a.b = b;
     a.V += c * a.ldv;
     if (a.Hb) a.Hb += c * a.ldh;
-    body<S, KS>(a, it.y * FPW);
+    body<S, KS, FOLD>(a, it.y * FPW);
 }
 
 // Served form: grid (chunk i, 128-frame tile j) over a step's work list.
@@ -392,7 +570,7 @@ __global__ __launch_bounds__(NWT * 64) void fit_tile_work_kernel(const FitDesc *
     a.b = wk.b;
     a.V = wk.V;
     a.ldv = wk.ldv;
-    body<S, KS>(a, blockIdx.y * FPW);
+    body<S, KS, false>(a, blockIdx.y * FPW);
 }
 
 template <int S, int KS>
@@ -409,14 +587,25 @@ hipError_t launch_work_one(const FitDesc *tab, const ServeWork *work, int n, int
 
 template <int S, int KS>
 hipError_t launch_one(const FitDesc *a, int b, const FitDesc *d, const int2 *items, int n,
-                      const long long *cur, const int *beff, hipStream_t s) {
+                      const long long *cur, const int *beff, bool fold, hipStream_t s) {
     constexpr size_t lds = lds_bytes(S, KS);
-    if (d) {
+    if (d && fold) {
+        constexpr size_t lf = lds_fold_bytes(S, KS);
+        if constexpr (lf <= LDS_MAX) {
+            static const hipError_t attr = hipFuncSetAttribute(
+                reinterpret_cast<const void *>(&fit_tile_multi_kernel<S, KS, true>),
+                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lf);
+            if (attr != hipSuccess) return attr;
+            fit_tile_multi_kernel<S, KS, true><<<n, NWT * 64, lf, s>>>(d, items, cur, beff);
+        } else {
+            return hipErrorNotSupported;
+        }
+    } else if (d) {
         static const hipError_t attr = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&fit_tile_multi_kernel<S, KS>),
+            reinterpret_cast<const void *>(&fit_tile_multi_kernel<S, KS, false>),
             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (attr != hipSuccess) return attr;
-        fit_tile_multi_kernel<S, KS><<<n, NWT * 64, lds, s>>>(d, items, cur, beff);
+        fit_tile_multi_kernel<S, KS, false><<<n, NWT * 64, lds, s>>>(d, items, cur, beff);
     } else {
         static const hipError_t attr = hipFuncSetAttribute(
             reinterpret_cast<const void *>(&fit_tile_kernel<S, KS>),
@@ -439,10 +628,10 @@ constexpr int S_MAX = 20;   // F <= 640
 // KS in fit_tile_k*.hip so the instances build in parallel.
 template <int KS>
 hipError_t launch_ks(int S, const FitDesc *a, int b, const FitDesc *d, const int2 *items, int n,
-                     const long long *cur, const int *beff, hipStream_t st) {
+                     const long long *cur, const int *beff, bool fold, hipStream_t st) {
     switch (S) {
 #define ISNMF_TILE_S(SV) \
-    case SV: return launch_one<SV, KS>(a, b, d, items, n, cur, beff, st);
+    case SV: return launch_one<SV, KS>(a, b, d, items, n, cur, beff, fold, st);
         ISNMF_TILE_S(1) ISNMF_TILE_S(2) ISNMF_TILE_S(3) ISNMF_TILE_S(4) ISNMF_TILE_S(5)
         ISNMF_TILE_S(6) ISNMF_TILE_S(7) ISNMF_TILE_S(8) ISNMF_TILE_S(9) ISNMF_TILE_S(10)
         ISNMF_TILE_S(11) ISNMF_TILE_S(12) ISNMF_TILE_S(13) ISNMF_TILE_S(14) ISNMF_TILE_S(15)
@@ -470,13 +659,13 @@ hipError_t launch_work_ks(int S, const FitDesc *tab, const ServeWork *work, int 
 #define ISNMF_TILE_EXTERN(KSV)                                                                   \
     extern template hipError_t launch_ks<KSV>(int, const FitDesc *, int, const FitDesc *,       \
                                               const int2 *, int, const long long *, const int *, \
-                                              hipStream_t);                                      \
+                                              bool, hipStream_t);                                \
     extern template hipError_t launch_work_ks<KSV>(int, const FitDesc *, const ServeWork *, int, \
                                                    int, hipStream_t);
 #define ISNMF_TILE_INSTANTIATE(KSV)                                                       \
     template hipError_t launch_ks<KSV>(int, const FitDesc *, int, const FitDesc *,       \
                                        const int2 *, int, const long long *, const int *, \
-                                       hipStream_t);                                      \
+                                       bool, hipStream_t);                                \
     template hipError_t launch_work_ks<KSV>(int, const FitDesc *, const ServeWork *, int, \
                                             int, hipStream_t);
 

@@ -150,6 +150,7 @@ FitDesc make_fit_desc(const OnlineDev &d, const float *V, int ldv, int b, int it
     a.R2 = (float *)d.R2;
     a.lossf = d.lossf;
     a.flags = d.flags;
+    a.fold = nullptr;
     return a;
 }
 

@@ -110,6 +110,7 @@ struct isnmf_multi {
     struct Group {
         FitClass c;
         int prec, off, n;
+        bool fold;     // the fit launch folds its streams' minibatches itself
         double cost;   // frames x F x K over its items (for the lane balance)
         int lane;      // 0: the step's stream; i > 0: side[i - 1]
     };
@@ -231,7 +232,8 @@ hipError_t enqueue_step(isnmf_multi *m, hipStream_t s) {
         if (g.c.cpw == 0 || g.c.cpw == -4)
             e = launch_fit_valu_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else if (g.c.cpw == -1)
-            e = launch_fit_tile_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
+            e = launch_fit_tile_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff,
+                                      g.fold, gs);
         else if (g.c.cpw == -2)
             e = launch_fit_stile_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else if (g.c.cpw == -3)
@@ -351,18 +353,31 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
     std::vector<long long> zero(S, 0);
     std::vector<int2> items;
     items.reserve(nitems);
-    // fit items grouped by (variant, precision)
-    std::vector<std::pair<std::tuple<int, int, int, int, int, int>, std::vector<int2>>> groups;
+    // fit items grouped by (variant, precision, fold in the fit).  When every
+    // stream is on the 16-frame tile variant with a minibatch that fits one
+    // workgroup, each fit launch folds its streams itself (the same bits as the
+    // separate fold) and the step has no fold launch.  With any other stream
+    // the fold launch stays, and moving work from it into the fit lanes (the
+    // step's critical path) only lengthens them, so then no stream is folded
+    // in its fit.
+    std::vector<std::pair<std::tuple<int, int, int, int, int, int, int>, std::vector<int2>>> groups;
+    bool fold_in_fit = true;
+    for (int s = 0; s < S && fold_in_fit; ++s) {
+        const FitClass &c = *isnmf_handle_class(handles[s]);
+        fold_in_fit = c.cpw == -1 && b[s] <= frames_per_item(c) && tile_fold_fits(c);
+    }
+    std::vector<char> folded(S, fold_in_fit ? 1 : 0);
     for (int s = 0; s < S; ++s) {
         const OnlineDev &d = *isnmf_handle_dev(handles[s]);
         const isnmf_params &p = *isnmf_handle_params(handles[s]);
         const FitClass &c = *isnmf_handle_class(handles[s]);
         fit[s] = make_fit_desc(d, V[s], ldv[s], b[s], p.inner_iters, p.eps, 0, nullptr, d.K);
         fold[s] = fold_args(d, b[s], p.rho, p.update_w, nullptr, d_loss ? d_loss + s : nullptr);
+        if (folded[s]) fit[s].fold = m->d_fold + s;
         rs[s] = rescale_args(d, p.normalize, 0, nullptr, d.K);
         rs[s].dwpart = nullptr;   // the batched step reports no dW
         upd[s] = p.update_w;
-        const auto key = std::make_tuple(c.nw, c.cpw, c.kmax, c.wg, c.rf, prec_of(p));
+        const auto key = std::make_tuple(c.nw, c.cpw, c.kmax, c.wg, c.rf, prec_of(p), (int)folded[s]);
         size_t gi = 0;
         while (gi < groups.size() && groups[gi].first != key) ++gi;
         if (gi == groups.size()) groups.push_back({key, {}});
@@ -373,6 +388,7 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         isnmf_multi::Group G;
         G.c = *isnmf_handle_class(handles[g.second.front().x]);
         G.prec = std::get<5>(g.first);
+        G.fold = std::get<6>(g.first) != 0;
         G.off = (int)items.size();
         G.n = (int)g.second.size();
         G.cost = 0.0;
@@ -410,6 +426,7 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
     std::vector<int2> list;
     m->fold_off = (int)items.size();
     for (int s = 0; s < S; ++s) {
+        if (folded[s]) continue;
         const int nt = fold_tiles(*isnmf_handle_dev(handles[s]));
         m->fold_ktm = std::max(m->fold_ktm, fold_ktm(isnmf_handle_dev(handles[s])->K));
         for (int t = 0; t < nt; ++t) list.push_back(int2{s, t});
@@ -503,6 +520,13 @@ int isnmf_multi_frames_left(const isnmf_multi *m, long long *host_max_left) {
         if (left > mx) mx = left;
     }
     *host_max_left = mx;
+    return ISNMF_OK;
+}
+
+int isnmf_multi_launches(const isnmf_multi *m, int *fit_launches, int *fold_launches) {
+    if (!m || !fit_launches || !fold_launches) return ISNMF_EINVAL;
+    *fit_launches = (int)m->groups.size();
+    *fold_launches = m->fold_n > 0 ? 1 : 0;
     return ISNMF_OK;
 }
 

@@ -227,3 +227,18 @@ def test_forgetting_rho_is_a_library_call():
     assert L.isnmf_forgetting_rho(0.5, 0, 10, ctypes.byref(r)) == bd.EINVAL
     assert L.isnmf_forgetting_rho(0.5, 1, 10, None) == bd.EINVAL
     assert bd.forgetting_rho(0.25, 2, 4) == 0.5
+
+
+def test_single_row_tensors_get_their_row_length_as_stride():
+    """A one-row matrix (K = 1 as K x F, or one frame) may carry any row stride
+    (numpy's relaxed strides give 1 for np.ascontiguousarray of a transposed
+    F x 1 array); the binding passes its row length as the leading dimension."""
+    import numpy as np
+    import torch
+    from paper_1106_4198_amd import binding as bd
+    t = torch.from_numpy(np.ascontiguousarray(np.zeros((64, 1), dtype=np.float32).T))
+    assert t.shape == (1, 64)
+    assert bd._ld(t) == 64
+    u = torch.zeros((5, 64), dtype=torch.float32)
+    assert bd._ld(u) == 64 and bd._ld(u[:, :10]) == 64 and bd._ld(u[2:3]) == 64
+    assert bd._ld(torch.zeros((3, 1))[:, :]) == 1

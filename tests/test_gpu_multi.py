@@ -226,16 +226,31 @@ def test_autotune_offers_the_valu_variant_for_fp32():
     bd.tune_clear()
 
 
-def test_batched_tile_streams_equal_alone_bitwise():
+TILE_FOLD_MIX = [(513, 50, 128, "bf16", 300), (257, 64, 40, "bf16", 100), (129, 8, 16, "bf16", 40),
+                 (200, 33, 37, "bf16", 100), (608, 64, 128, "bf16", 260), (64, 1, 5, "bf16", 12),
+                 (33, 20, 100, "bf16", 250)]
+
+
+@pytest.mark.parametrize("fold_in_fit", [False, True])
+def test_batched_tile_streams_equal_alone_bitwise(fold_in_fit):
     """BF16 streams on the 16-frame tile variant (ragged minibatches included)
-    share launches with other variants and match their runs alone."""
-    mix = [(513, 50, 128, "bf16", 300), (257, 64, 40, "bf16", 100), (129, 8, 16, "bf16", 40),
-           (513, 50, 64, "fp32", 200), (1025, 40, 32, "bf16", 90)]
-    say("batched tile vs alone")
+    match their runs alone.  Mixed with other variants, they share the step's
+    fold launch; alone in the step with at most 128 frames each, every fit
+    launch folds its streams itself (no fold launch), while alone they run the
+    separate fold: W, A, B and the running loss must agree bit for bit either
+    way.  The fold-in-fit set has K = 33 (an idle fold wave), K = 1, F = 200
+    and 33 (row tiles past F), F = 608 (19 contraction steps) and b = 5."""
+    if fold_in_fit:
+        mix = TILE_FOLD_MIX
+    else:
+        mix = [(513, 50, 128, "bf16", 300), (257, 64, 40, "bf16", 100), (129, 8, 16, "bf16", 40),
+               (513, 50, 64, "fp32", 200), (1025, 40, 32, "bf16", 90), (200, 33, 37, "bf16", 100),
+               (513, 50, 256, "bf16", 600)]
+    say(f"batched tile vs alone, fold in fit {fold_in_fit}")
     bd.tune_clear()
-    bd.tune_set(513, 50, "bf16", 8, -1, 0)
-    bd.tune_set(257, 64, "bf16", 8, -1, 0)
-    bd.tune_set(129, 8, "bf16", 8, -1, 0)
+    for F, K, _, prec, _ in mix:
+        if prec == "bf16" and F <= 640 and K <= 64:
+            bd.tune_set(F, K, "bf16", 8, -1, 0)
     try:
         data = []
         for i, (F, K, b, prec, N) in enumerate(mix):
@@ -244,20 +259,26 @@ def test_batched_tile_streams_equal_alone_bitwise():
                          torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV), b, prec))
         steps = 3
         alone = handles(data)
+        loss_alone = []
         for g, (W0, V, b, prec) in zip(alone, data):
+            ls = torch.zeros((), dtype=torch.float64, device=DEV)
             for s in range(steps):
                 lo, hi = s * b, min((s + 1) * b, V.shape[0])
                 if lo < hi:
-                    g.step(V[lo:hi])
+                    g.step(V[lo:hi], None, ls)
+            loss_alone.append(ls)
         mixed = handles(data)
         m = bd.MultiISNMF(mixed, [d[1] for d in data], [d[2] for d in data])
-        m.run(steps, graph=True)
+        assert m.launches()[1] == (0 if fold_in_fit else 1)
+        m.run(1, graph=False)
+        m.run(steps - 1, graph=True)
         torch.cuda.synchronize()
         for i, (ga, gm) in enumerate(zip(alone, mixed)):
             sa, sm = state(ga), state(gm)
             assert sa[3] == sm[3], i
             for x, y in zip(sa[:3], sm[:3]):
                 assert torch.equal(x, y), f"stream {i} {mix[i]} differs alone vs batched"
+            assert torch.equal(loss_alone[i], m.loss[i]), f"stream {i} loss differs"
         W0 = data[0][0].cpu().double().numpy().T
         V = data[0][1].cpu().double().numpy().T
         st = oracle.OnlineState(W0)
