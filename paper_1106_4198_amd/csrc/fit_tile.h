@@ -35,6 +35,7 @@ namespace tile {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef const float __attribute__((address_space(1))) gfloat;
 
 constexpr int WF = 16;       // frames per wave
 constexpr int NWT = 8;       // waves per workgroup
@@ -322,6 +323,21 @@ __device__ inline void body(const FitDesc &a, int n_first) {
 
     // ---- final model: R1, R2 for the fold (FP32), or the fold itself, and the
     // frame loss.
+    // the fitted h: internal copy and the caller's H
+    auto store_h = [&]() {
+        if (fok) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = 16 * mt + 4 * g + j;
+                    if (k < K) {
+                        a.Hi[(size_t)fr * a.KP + k] = hq[mt][j];
+                        if (a.Hb) a.Hb[(size_t)fr * a.ldh + k] = hq[mt][j];
+                    }
+                }
+        }
+    };
     double ls = 0.0;
     if constexpr (FOLD) {
         // The fold of the minibatch (Algorithm 1's statistics update and W =
@@ -358,6 +374,7 @@ __device__ inline void body(const FitDesc &a, int n_first) {
         float hh[32];
 #pragma unroll
         for (int m = 0; m < 32; ++m) hh[m] = kact ? stg[2 * RB + (4 * m + g) * CW + 16 * kt + n] : 0.f;
+        store_h();
         // v (FP32) of a round's two row tiles and the epilogue operands of the
         // wave's fold tile (element (16 tf + n, 16 kt + 4 g + j) in pass j: W,
         // A, B), read one round ahead; the pending column scales of its columns
@@ -369,6 +386,16 @@ __device__ inline void body(const FitDesc &a, int n_first) {
             const int kc = 16 * kt + 4 * g + j;
             scq[j] = kact && kc < K ? fa.sc[kc] : 1.0;
         }
+        // (global-memory loads: flat ones would hold up every LDS wait of the
+        // round until they arrive)
+        const gdouble *gW = (const gdouble *)fa.W64;
+        const gdouble *gA = (const gdouble *)fa.A;
+        const gdouble *gB = (const gdouble *)fa.B;
+        const gfloat *gV = (const gfloat *)a.V;
+        auto load_vg = [&](int t, int j) {
+            const int row = 16 * t + 4 * g + j;
+            return (row < F && fok) ? gV[(size_t)fr * a.ldv + row] : 0.f;
+        };
         auto load_eo = [&](int r, double (&o)[3][4]) {
             const int tf = 2 * r + uw, fe = 16 * tf + n;
 #pragma unroll
@@ -376,15 +403,15 @@ __device__ inline void body(const FitDesc &a, int n_first) {
                 const int kc = 16 * kt + 4 * g + j;
                 const bool ok = kact && fe < F && kc < K;
                 const size_t e = ok ? (size_t)fe + (size_t)kc * F : 0;
-                o[0][j] = ok ? fa.W64[e] : 0.0;
-                o[1][j] = ok ? fa.A[e] : 0.0;
-                o[2][j] = ok ? fa.B[e] : 0.0;
+                o[0][j] = ok ? gW[e] : 0.0;
+                o[1][j] = ok ? gA[e] : 0.0;
+                o[2][j] = ok ? gB[e] : 0.0;
             }
         };
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) vc[u][j] = load_v(u, j);
+            for (int j = 0; j < 4; ++j) vc[u][j] = load_vg(u, j);
         load_eo(0, eo);
 #pragma unroll 1
         for (int r = 0; r < S; ++r) {
@@ -397,7 +424,7 @@ __device__ inline void body(const FitDesc &a, int n_first) {
 #pragma unroll
                 for (int u = 0; u < 2; ++u)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) vn[u][j] = load_v(2 * r + 2 + u, j);
+                    for (int j = 0; j < 4; ++j) vn[u][j] = load_vg(2 * r + 2 + u, j);
             }
             // ratios of row tiles 2r and 2r + 1 of this wave's frames (zero for
             // frames past the minibatch) and the frame loss terms
@@ -432,13 +459,15 @@ __device__ inline void body(const FitDesc &a, int n_first) {
                     ca[v] = floatx4{0.f, 0.f, 0.f, 0.f};
                     cb[v] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
+                // every group of 4 frames: those past the minibatch hold r = h =
+                // 0, whose products add exactly zero to the non-negative chains,
+                // as the separate fold's skipping them does
 #pragma unroll
                 for (int m = 0; m < 32; ++m) {
-                    if (4 * m < fa.b) {   // groups of 4 frames that start in the minibatch
-                        const int nl = 4 * m + g;
-                        ca[m & 3] = mfma16(sr2[nl * 16 + n], hh[m], ca[m & 3]);
-                        cb[m & 3] = mfma16(sr1[nl * 16 + n], hh[m], cb[m & 3]);
-                    }
+                    if ((m & 7) == 0) __builtin_amdgcn_sched_barrier(0);   // bounds the reads in flight
+                    const int nl = 4 * m + g;
+                    ca[m & 3] = mfma16(sr2[nl * 16 + n], hh[m], ca[m & 3]);
+                    cb[m & 3] = mfma16(sr1[nl * 16 + n], hh[m], cb[m & 3]);
                 }
                 const floatx4 sa = ((ca[0] + ca[1]) + ca[2]) + ca[3];
                 const floatx4 sb = ((cb[0] + cb[1]) + cb[2]) + cb[3];
@@ -451,8 +480,8 @@ __device__ inline void body(const FitDesc &a, int n_first) {
                     const float eb = red_elem(slab + RSLAB, n, cl);
                     const int kc = 16 * kt + cl;
                     if (fe < F && kc < K)
-                        epilogue(fa, fe, kc, double(ea), double(eb), eo[0][j], eo[1][j] / scq[j],
-                                 eo[2][j] * scq[j]);
+                        epilogue<true>(fa, fe, kc, double(ea), double(eb), eo[0][j],
+                                       eo[1][j] / scq[j], eo[2][j] * scq[j]);
                 }
             }
 #pragma unroll
@@ -522,18 +551,7 @@ __device__ inline void body(const FitDesc &a, int n_first) {
             if (lane == 0) *fa->d_loss_sum += sl;
         }
     }
-    if (fok) {
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = 16 * mt + 4 * g + j;
-                if (k < K) {
-                    a.Hi[(size_t)fr * a.KP + k] = hq[mt][j];
-                    if (a.Hb) a.Hb[(size_t)fr * a.ldh + k] = hq[mt][j];
-                }
-            }
-    }
+    if (!FOLD) store_h();   // the folding pass stores h before its rounds
 }
 
 template <int S, int KS>

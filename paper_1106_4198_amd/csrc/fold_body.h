@@ -42,23 +42,34 @@ __device__ inline float red_elem(const float *slab, int fl, int cl) {
     return slab[4 * red_pos(sl) + (fl & 3)];
 }
 
+typedef double __attribute__((address_space(1))) gdouble;
+
 // A = rho A + sum_n r2 h W^2, B = rho B + sum_n r1 h (Algorithm 1), W = sqrt(A/B);
 // w, a0, b0: the element's current W, A, B (a0, b0 with the pending column
 // scale applied).  A and B are stored as computed here, with no pending scale.
+// GLOBAL: the stores are global-memory instructions, which only the vector
+// memory counter tracks (flat stores also hold up every wait for LDS reads).
+template <bool GLOBAL = false>
 __device__ inline void epilogue(const FoldArgs &a, int f, int k, double sa, double sb, double w,
                                 double a0, double b0) {
     const size_t e = (size_t)f + (size_t)k * a.F;
     const double av = a.rho * a0 + sa * (w * w);
     const double bv = a.rho * b0 + sb;
-    a.A[e] = av;
-    a.B[e] = bv;
+    auto put = [](double *p, size_t i, double v) {
+        if constexpr (GLOBAL)
+            ((gdouble *)p)[i] = v;
+        else
+            p[i] = v;
+    };
+    put(a.A, e, av);
+    put(a.B, e, bv);
     if (a.update_w) {
         double wn = w;
         if (bv > 0.0 && av >= 0.0)
             wn = sqrt(av / bv);
         else
             atomicOr(a.flags, FLAG_GUARD_W);
-        a.Wn[e] = wn;
+        put(a.Wn, e, wn);
     }
 }
 
