@@ -236,15 +236,31 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0, pr
     # for throughput (right when a shape's launch is full), 1024 leans to
     # latency (right when a shape has few frames and one slow workgroup would
     # hold the whole step).  With several shapes, tunings at 8192 (twice: the
-    # per-shape choices are timed alone and vary from one tuning to the next)
-    # and at 1024 are each timed on the captured step itself (one warm-up and
-    # three timed replays), and the table of the fastest is restored for the
-    # timed run, so that the run measures the configuration that was chosen.
-    floors = [8192, 8192, 1024] if len(shape_set) > 1 else [8192]
+    # per-shape choices are timed alone and vary from one tuning to the next),
+    # at 1024, and a table by rule (the 16-frame tile variants wherever they
+    # fit) are each timed on the captured step itself (one warm-up and three
+    # timed replays), and the table of the fastest is restored for the timed
+    # run, so that the run measures the configuration that was chosen.
+    def by_rule(base):
+        # the 16-frame tile variant wherever it fits, else its streamed form:
+        # the throughput variants, chosen without per-shape timings
+        chosen = {}
+        bd.tune_clear()
+        for (Fi, Ki), v in base.items():
+            for cand in ((8, -1, 0), (8, -2, 0), v):
+                try:
+                    bd.tune_set(Fi, Ki, precision, *cand)
+                except bd.IsnmfError:
+                    continue
+                chosen[(Fi, Ki)] = cand
+                break
+        return chosen
+
+    floors = [8192, 8192, 1024, "rule"] if len(shape_set) > 1 else [8192]
     trial, tables = [], []
     for fl in floors:
         bd.tune_clear()
-        tables.append((fl, tune(fl)))
+        tables.append((fl, by_rule(tables[0][1]) if fl == "rule" else tune(fl)))
         if len(floors) > 1:
             hs, m = make()
             m.run(1, graph=True)
