@@ -207,10 +207,14 @@ hipError_t launch_fit_stile_multi(const FitClass &c, const FitDesc *d, const int
                                   const long long *cur, const int *beff, hipStream_t s);
 hipError_t launch_fit_stile_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
                                  int tiles, hipStream_t s);
-// FP32 16-frame tile variant launches: b frames, n batched items, or a served work list.
+// FP32 16-frame tile variant launches: b frames, n batched items (fold: as
+// for launch_fit_tile_multi), or a served work list.
 hipError_t launch_fit_t32(const FitDesc &a, const FitClass &c, int b, hipStream_t s);
 hipError_t launch_fit_t32_multi(const FitClass &c, const FitDesc *d, const int2 *items, int n,
-                                const long long *cur, const int *beff, hipStream_t s);
+                                const long long *cur, const int *beff, bool fold, hipStream_t s);
+// The FP32 16-frame tile variant of class c can fold in its launch (its LDS holds
+// the fold's staging beside W).
+bool t32_fold_fits(const FitClass &c);
 hipError_t launch_fit_t32_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
                                int tiles, hipStream_t s);
 // Frames per batched item: 128 for the 16-frame tile variants (8 waves of

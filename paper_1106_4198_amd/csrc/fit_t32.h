@@ -40,6 +40,7 @@
 
 #include "common.h"
 #include "devmath.h"
+#include "fold_body.h"
 
 namespace isnmf {
 namespace t32 {
@@ -63,6 +64,16 @@ __host__ __device__ constexpr size_t lds_bytes(int T, int MT) {
 // Row tiles the LDS holds at MT m-tiles: F <= 16 t_max(MT).
 __host__ __device__ constexpr int t_max(int MT) { return (int)(LDS_MAX / lds_bytes(1, MT)); }
 
+// The folding final pass (FOLD) keeps W and, past it, the ratios of two row
+// tiles for all 128 frames ([tile][r2, r1][frame][16 rows] floats; it first
+// carries h of every frame), a per-wave slab pair for the epilogue and the
+// 128 frame losses.
+constexpr size_t FOLD_STAGE = (size_t)2 * 2 * FPW * 16 * 4;
+constexpr size_t FOLD_EXTRA = FOLD_STAGE + (size_t)NWT * 2 * RSLAB * 4 + (size_t)FPW * 8;
+__host__ __device__ constexpr size_t lds_fold_bytes(int T, int MT) {
+    return lds_bytes(T, MT) + FOLD_EXTRA;
+}
+
 // Word 3 of a raw (unswizzled, stride 0) buffer descriptor on gfx9-family
 // chips: 32-bit data format, every out-of-range dword reads as 0.
 constexpr int BUFFER_DWORD3 = 0x00020000;
@@ -77,7 +88,9 @@ __device__ inline gfloat *gptr(const float *p) { return (gfloat *)p; }
 // components) run on the VALU, instead of a fourth m-tile of which 14 of 16
 // rows would be zero.  The remainder columns sit in the pitch padding of the
 // LDS rows, so the LDS layout is the same.
-template <int MT, int KR>
+// FOLD: the workgroup holds the stream's whole minibatch (b <= 128, n_first =
+// 0) and folds it (a.fold) instead of writing R1 and R2.
+template <int MT, int KR, bool FOLD>
 __device__ inline void body(const FitDesc &a, int n_first) {
     constexpr int P = pitch(MT);
     static_assert(KR >= 0 && KR <= 4 && 16 * MT + KR <= P, "remainder fits the pitch padding");
@@ -343,13 +356,191 @@ __device__ inline void body(const FitDesc &a, int n_first) {
     }
     if (guard) atomicOr(a.flags, FLAG_GUARD_H);
 
-    // ---- final model: R1, R2 for the fold, the frame loss (FP64 terms, as the
-    // objective), and the check of v
+    // ---- final model: R1, R2 for the fold, or the fold itself, the frame loss
+    // (FP64 terms, as the objective), and the check of v
     double ls = 0.0;
     int bad = 0;
     f4 wx[MT];
     float wt_unused[4][MT];
     RV wr[4];
+    // the fitted h: internal copy and the caller's H
+    auto store_h = [&]() {
+        if (fok) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = 16 * mt + 4 * g + j;
+                    if (k < K) {
+                        a.Hi[(size_t)fr * a.KP + k] = hq[mt][j];
+                        if (a.Hb) a.Hb[(size_t)fr * a.ldh + k] = hq[mt][j];
+                    }
+                }
+            if (g == 0) {
+#pragma unroll
+                for (int i = 0; i < KR; ++i) {
+                    const int k = 16 * MT + i;
+                    if (k < K) {
+                        a.Hi[(size_t)fr * a.KP + k] = hr[i];
+                        if (a.Hb) a.Hb[(size_t)fr * a.ldh + k] = hr[i];
+                    }
+                }
+            }
+        }
+    };
+    if constexpr (FOLD) {
+        // The fold of the minibatch (Algorithm 1's statistics update and W =
+        // sqrt(A/B)) in this workgroup, as in the BF16 tile variant's folding
+        // pass: round r takes row tiles 2r and 2r + 1, whose ratios every wave
+        // forms for its frames (the values the separate fold would read) and
+        // stores in LDS; then wave w folds row tile 2r + (w & 1) over
+        // component tile w >> 1 for all frames with the separate fold's MFMA
+        // chains, chain sums and epilogue, so the bits are those of the fit
+        // followed by that fold.  One ratio buffer, two barriers per round.
+        const FoldArgs &fa0 = *a.fold;
+        FoldArgs fa = fa0;
+        fa.b = a.b;
+        constexpr int RB = 2 * FPW * 16;             // floats per staged row tile (r2, r1)
+        float *stg = wl + 16 * T * P;
+        float *slab = stg + 2 * RB + w * 2 * RSLAB;
+        double *lsh = reinterpret_cast<double *>(stg + 2 * RB + NWT * 2 * RSLAB);
+        const int KT = (K + 15) / 16;
+        const int CW = 16 * KT;                      // LDS floats per frame of h
+        const int kt = w >> 1, uw = w & 1;
+        const bool kact = kt < KT;                   // uniform per wave
+        // h of every frame through the ratio buffer (zero past the minibatch
+        // and past K, as the separate fold stages it); wave w keeps the column
+        // of its component tile for all 128 frames
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 16 * mt + 4 * g + j;
+                if (k < CW) stg[(WF * w + n) * CW + k] = (fok && k < K) ? hq[mt][j] : 0.f;
+            }
+        if (g == 0) {
+            for (int k = 16 * MT; k < CW; ++k) {
+                const int i = k - 16 * MT;
+                float hv = 0.f;
+#pragma unroll
+                for (int q = 0; q < KR; ++q)
+                    if (q == i) hv = hr[q];
+                stg[(WF * w + n) * CW + k] = (fok && k < K) ? hv : 0.f;
+            }
+        }
+        __syncthreads();
+        float hh[32];
+#pragma unroll
+        for (int m = 0; m < 32; ++m) hh[m] = kact ? stg[(4 * m + g) * CW + 16 * kt + n] : 0.f;
+        store_h();
+        __syncthreads();   // the buffer's next use is the first round's ratios
+        const gdouble *gW = (const gdouble *)fa.W64;
+        const gdouble *gA = (const gdouble *)fa.A;
+        const gdouble *gB = (const gdouble *)fa.B;
+        double scq[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int kc = 16 * kt + 4 * g + j;
+            scq[j] = kact && kc < K ? fa.sc[kc] : 1.0;
+        }
+        const int R = (T + 1) / 2;
+        for (int r = 0; r < R; ++r) {
+            const int tf = 2 * r + uw;                 // this wave's fold row tile
+            const bool fact = kact && tf < T;          // uniform per wave
+            const int fe = 16 * tf + n;
+            // epilogue operands, element (16 tf + n, 16 kt + 4 g + j) in pass j
+            double eo[3][4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int kc = 16 * kt + 4 * g + j;
+                const bool ok = fact && fe < F && kc < K;
+                const size_t e = ok ? (size_t)fe + (size_t)kc * F : 0;
+                eo[0][j] = ok ? gW[e] : 0.0;
+                eo[1][j] = ok ? gA[e] : 0.0;
+                eo[2][j] = ok ? gB[e] : 0.0;
+            }
+            // ratios of row tiles 2r and 2r + 1 of this wave's frames (zero for
+            // frames past the minibatch and rows past F) and the loss terms
+            for (int u = 0; u < 2; ++u) {
+                const int t = 2 * r + u;
+                if (t >= T) break;   // uniform
+                load_wx(t, wx);
+                load_wt(t, wt_unused, wr);
+                const f4 xf = model_rest(model_ops(t, wx, TAIL), wr);
+                const f4 v0 = load_v(t);
+                const int r0 = 16 * t + 4 * g;
+                f4 r1, r2;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const bool ok = fok && r0 + j < F;
+                    const float v = ok ? v0[j] : 0.f;
+                    bad |= !isfinite(v);
+                    const float ve = eps + v;
+                    const float rr = __builtin_amdgcn_rcpf(xf[j]);
+                    r1[j] = ok ? rr : 0.f;
+                    r2[j] = ok ? ve * rr * rr : 0.f;
+                    if (ok) ls += dis_term(a.epsd + double(v), double(xf[j]));
+                }
+                float *sr = stg + u * RB;
+                *reinterpret_cast<f4 *>(sr + (WF * w + n) * 16 + 4 * g) = r2;
+                *reinterpret_cast<f4 *>(sr + FPW * 16 + (WF * w + n) * 16 + 4 * g) = r1;
+            }
+            __syncthreads();
+            if (fact) {
+                const float *sr2 = stg + uw * RB, *sr1 = sr2 + FPW * 16;
+                floatx4 ca[4], cb[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    ca[v] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    cb[v] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+                // every group of 4 frames: those past the minibatch hold r = h =
+                // 0, whose products add exactly zero to the non-negative chains,
+                // as the separate fold's skipping them does
+#pragma unroll
+                for (int m = 0; m < 32; ++m) {
+                    if ((m & 7) == 0) __builtin_amdgcn_sched_barrier(0);   // bounds the reads in flight
+                    const int nl = 4 * m + g;
+                    ca[m & 3] = mfma16(sr2[nl * 16 + n], hh[m], ca[m & 3]);
+                    cb[m & 3] = mfma16(sr1[nl * 16 + n], hh[m], cb[m & 3]);
+                }
+                const floatx4 sa = ((ca[0] + ca[1]) + ca[2]) + ca[3];
+                const floatx4 sb = ((cb[0] + cb[1]) + cb[2]) + cb[3];
+                reinterpret_cast<floatx4 *>(slab)[red_pos(lane)] = sa;
+                reinterpret_cast<floatx4 *>(slab + RSLAB)[red_pos(lane)] = sb;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int cl = 4 * g + j;
+                    const float ea = red_elem(slab, n, cl);
+                    const float eb = red_elem(slab + RSLAB, n, cl);
+                    const int kc = 16 * kt + cl;
+                    if (fe < F && kc < K)
+                        epilogue<true>(fa, fe, kc, double(ea), double(eb), eo[0][j],
+                                       eo[1][j] / scq[j], eo[2][j] * scq[j]);
+                }
+            }
+            __syncthreads();   // the ratio buffer is read; the next round rewrites it
+        }
+        if (bad) atomicOr(a.flags, FLAG_NONFINITE_V);
+        // frame n's loss: lanes n, n + 16, n + 32, n + 48, in that order; the
+        // minibatch loss as the separate fold adds it (wave 1, lane l sums
+        // frames l, l + 64 in order, then a fixed xor butterfly)
+        const double l1 = __shfl_xor(ls, 16, 64);
+        const double l2 = __shfl_xor(ls, 32, 64);
+        const double l3 = __shfl_xor(ls, 48, 64);
+        const double lframe = ((ls + l1) + l2) + l3;
+        if (g == 0 && fok) a.lossf[fr] = lframe;
+        if (g == 0) lsh[WF * w + n] = lframe;
+        __syncthreads();
+        if (fa.d_loss_sum && w == 1) {
+            double sl = 0.0;
+            for (int m = lane; m < a.b; m += 64) sl += lsh[m];
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) sl += __shfl_xor(sl, m, 64);
+            if (lane == 0) *fa.d_loss_sum += sl;
+        }
+        return;
+    }
     load_wx(0, wx);
     f4 x = model_ops(0, wx, TAIL);
     f4 v0 = load_v(0);
@@ -389,38 +580,18 @@ __device__ inline void body(const FitDesc &a, int n_first) {
     const double l2 = __shfl_xor(ls, 32, 64);
     const double l3 = __shfl_xor(ls, 48, 64);
     if (g == 0 && fok) a.lossf[fr] = ((ls + l1) + l2) + l3;
-    if (fok) {
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = 16 * mt + 4 * g + j;
-                if (k < K) {
-                    a.Hi[(size_t)fr * a.KP + k] = hq[mt][j];
-                    if (a.Hb) a.Hb[(size_t)fr * a.ldh + k] = hq[mt][j];
-                }
-            }
-        if (g == 0) {
-#pragma unroll
-            for (int i = 0; i < KR; ++i) {
-                const int k = 16 * MT + i;
-                if (k < K) {
-                    a.Hi[(size_t)fr * a.KP + k] = hr[i];
-                    if (a.Hb) a.Hb[(size_t)fr * a.ldh + k] = hr[i];
-                }
-            }
-        }
-    }
+    store_h();
 }
 
 template <int MT, int KR>
 __global__ __launch_bounds__(NWT * 64) void fit_t32_kernel(FitDesc a) {
-    body<MT, KR>(a, blockIdx.x * FPW);
+    body<MT, KR, false>(a, blockIdx.x * FPW);
 }
 
 // Batched form: item = (stream, tile of 128 frames); tiles past the stream's
-// minibatch of this step exit.
-template <int MT, int KR>
+// minibatch of this step exit.  FOLD: every stream of the launch has one tile
+// (b <= 128) and a fold descriptor.
+template <int MT, int KR, bool FOLD>
 __global__ __launch_bounds__(NWT * 64) void fit_t32_multi_kernel(const FitDesc *__restrict__ descs,
                                                                  const int2 *__restrict__ items,
                                                                  const long long *__restrict__ cursor,
@@ -433,7 +604,7 @@ __global__ __launch_bounds__(NWT * 64) void fit_t32_multi_kernel(const FitDesc *
     a.b = b;
     a.V += c * a.ldv;
     if (a.Hb) a.Hb += c * a.ldh;
-    body<MT, KR>(a, it.y * FPW);
+    body<MT, KR, FOLD>(a, it.y * FPW);
 }
 
 // Served form: grid (chunk i, 128-frame tile j) over a step's work list.
@@ -446,21 +617,31 @@ __global__ __launch_bounds__(NWT * 64) void fit_t32_work_kernel(const FitDesc *_
     a.b = wk.b;
     a.V = wk.V;
     a.ldv = wk.ldv;
-    body<MT, KR>(a, blockIdx.y * FPW);
+    body<MT, KR, false>(a, blockIdx.y * FPW);
 }
 
 template <int MT, int KR>
 hipError_t run(const FitDesc *a, int b, const FitDesc *d, const int2 *items, int n,
                const long long *cur, const int *beff, const FitDesc *tab, const ServeWork *work,
-               int tiles, int T, hipStream_t s) {
+               int tiles, int T, bool fold, hipStream_t s) {
     if (T < 1 || T > t_max(MT)) return hipErrorInvalidValue;
     const size_t lds = lds_bytes(T, MT);
+    if (fold) {
+        if (!d || lds_fold_bytes(T, MT) > LDS_MAX) return hipErrorNotSupported;
+        static const hipError_t a4 = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&fit_t32_multi_kernel<MT, KR, true>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+        if (a4 != hipSuccess) return a4;
+        fit_t32_multi_kernel<MT, KR, true><<<n, NWT * 64, lds_fold_bytes(T, MT), s>>>(d, items, cur,
+                                                                                     beff);
+        return hipGetLastError();
+    }
     // the largest dynamic LDS any launch of the kernel asks for, set once
     static const hipError_t a1 = hipFuncSetAttribute(
         reinterpret_cast<const void *>(&fit_t32_kernel<MT, KR>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
     static const hipError_t a2 = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&fit_t32_multi_kernel<MT, KR>),
+        reinterpret_cast<const void *>(&fit_t32_multi_kernel<MT, KR, false>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
     static const hipError_t a3 = hipFuncSetAttribute(
         reinterpret_cast<const void *>(&fit_t32_work_kernel<MT, KR>),
@@ -470,7 +651,7 @@ hipError_t run(const FitDesc *a, int b, const FitDesc *d, const int2 *items, int
         fit_t32_work_kernel<MT, KR><<<dim3(n, tiles), NWT * 64, lds, s>>>(tab, work);
     } else if (d) {
         if (a2 != hipSuccess) return a2;
-        fit_t32_multi_kernel<MT, KR><<<n, NWT * 64, lds, s>>>(d, items, cur, beff);
+        fit_t32_multi_kernel<MT, KR, false><<<n, NWT * 64, lds, s>>>(d, items, cur, beff);
     } else {
         if (a1 != hipSuccess) return a1;
         fit_t32_kernel<MT, KR><<<(b + FPW - 1) / FPW, NWT * 64, lds, s>>>(*a);
@@ -483,17 +664,17 @@ hipError_t run(const FitDesc *a, int b, const FitDesc *d, const int2 *items, int
 template <int MT>
 hipError_t launch_mt(int KR, const FitDesc *a, int b, const FitDesc *d, const int2 *items, int n,
                      const long long *cur, const int *beff, const FitDesc *tab,
-                     const ServeWork *work, int tiles, int T, hipStream_t s) {
+                     const ServeWork *work, int tiles, int T, bool fold, hipStream_t s) {
     if constexpr (MT == MT_MAX) {
         if (KR != 0) return hipErrorNotSupported;
-        return run<MT, 0>(a, b, d, items, n, cur, beff, tab, work, tiles, T, s);
+        return run<MT, 0>(a, b, d, items, n, cur, beff, tab, work, tiles, T, fold, s);
     } else {
         switch (KR) {
-            case 0: return run<MT, 0>(a, b, d, items, n, cur, beff, tab, work, tiles, T, s);
-            case 1: return run<MT, 1>(a, b, d, items, n, cur, beff, tab, work, tiles, T, s);
-            case 2: return run<MT, 2>(a, b, d, items, n, cur, beff, tab, work, tiles, T, s);
-            case 3: return run<MT, 3>(a, b, d, items, n, cur, beff, tab, work, tiles, T, s);
-            case 4: return run<MT, 4>(a, b, d, items, n, cur, beff, tab, work, tiles, T, s);
+            case 0: return run<MT, 0>(a, b, d, items, n, cur, beff, tab, work, tiles, T, fold, s);
+            case 1: return run<MT, 1>(a, b, d, items, n, cur, beff, tab, work, tiles, T, fold, s);
+            case 2: return run<MT, 2>(a, b, d, items, n, cur, beff, tab, work, tiles, T, fold, s);
+            case 3: return run<MT, 3>(a, b, d, items, n, cur, beff, tab, work, tiles, T, fold, s);
+            case 4: return run<MT, 4>(a, b, d, items, n, cur, beff, tab, work, tiles, T, fold, s);
             default: return hipErrorNotSupported;
         }
     }
@@ -502,7 +683,7 @@ hipError_t launch_mt(int KR, const FitDesc *a, int b, const FitDesc *d, const in
 #define ISNMF_T32_SIG(MTV)                                                                     \
     hipError_t launch_mt<MTV>(int, const FitDesc *, int, const FitDesc *, const int2 *, int,   \
                               const long long *, const int *, const FitDesc *,                 \
-                              const ServeWork *, int, int, hipStream_t)
+                              const ServeWork *, int, int, bool, hipStream_t)
 #define ISNMF_T32_EXTERN(MTV) extern template ISNMF_T32_SIG(MTV);
 #define ISNMF_T32_INSTANTIATE(MTV) template ISNMF_T32_SIG(MTV);
 

@@ -28,16 +28,17 @@ void split_k(int K, int &MT, int &KR) {
 // The class's kmax is K itself, so streams that share a launch share the split.
 hipError_t launch(const FitClass &c, const FitDesc *a, int b, const FitDesc *d, const int2 *items,
                   int n, const long long *cur, const int *beff, const FitDesc *tab,
-                  const ServeWork *work, int tiles, hipStream_t s) {
+                  const ServeWork *work, int tiles, bool fold, hipStream_t s) {
     if (!c.ok || c.cpw != -3 || c.nw != t32::NWT || c.kmax < 1 || c.kmax > 16 * t32::MT_MAX)
         return hipErrorNotSupported;
     int MT, KR;
     split_k(c.kmax, MT, KR);
     switch (MT) {
-        case 1: return t32::launch_mt<1>(KR, a, b, d, items, n, cur, beff, tab, work, tiles, c.rf, s);
-        case 2: return t32::launch_mt<2>(KR, a, b, d, items, n, cur, beff, tab, work, tiles, c.rf, s);
-        case 3: return t32::launch_mt<3>(KR, a, b, d, items, n, cur, beff, tab, work, tiles, c.rf, s);
-        case 4: return t32::launch_mt<4>(KR, a, b, d, items, n, cur, beff, tab, work, tiles, c.rf, s);
+#define ISNMF_T32_MT(M)                                                                          \
+    case M:                                                                                      \
+        return t32::launch_mt<M>(KR, a, b, d, items, n, cur, beff, tab, work, tiles, c.rf, fold, s);
+        ISNMF_T32_MT(1) ISNMF_T32_MT(2) ISNMF_T32_MT(3) ISNMF_T32_MT(4)
+#undef ISNMF_T32_MT
         default: return hipErrorNotSupported;
     }
 }
@@ -67,17 +68,25 @@ FitClass t32_class(int F, int K) {
 hipError_t launch_fit_t32(const FitDesc &a, const FitClass &c, int b, hipStream_t s) {
     const FitClass e = t32_class(a.F, a.K);
     if (!e.ok || e.rf != c.rf || e.kmax != c.kmax || !a.W) return hipErrorInvalidValue;
-    return launch(c, &a, b, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, s);
+    return launch(c, &a, b, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, false, s);
 }
 
 hipError_t launch_fit_t32_multi(const FitClass &c, const FitDesc *d, const int2 *items, int n,
-                                const long long *cur, const int *beff, hipStream_t s) {
-    return launch(c, nullptr, 0, d, items, n, cur, beff, nullptr, nullptr, 0, s);
+                                const long long *cur, const int *beff, bool fold, hipStream_t s) {
+    if (fold && !t32_fold_fits(c)) return hipErrorNotSupported;
+    return launch(c, nullptr, 0, d, items, n, cur, beff, nullptr, nullptr, 0, fold, s);
 }
 
 hipError_t launch_fit_t32_work(const FitClass &c, const FitDesc *tab, const ServeWork *work, int n,
                                int tiles, hipStream_t s) {
-    return launch(c, nullptr, 0, nullptr, nullptr, n, nullptr, nullptr, tab, work, tiles, s);
+    return launch(c, nullptr, 0, nullptr, nullptr, n, nullptr, nullptr, tab, work, tiles, false, s);
+}
+
+bool t32_fold_fits(const FitClass &c) {
+    if (!c.ok || c.cpw != -3 || c.kmax < 1 || c.kmax > 16 * t32::MT_MAX) return false;
+    int MT, KR;
+    split_k(c.kmax, MT, KR);
+    return t32::lds_fold_bytes(c.rf, MT) <= t32::LDS_MAX;
 }
 
 }  // namespace isnmf

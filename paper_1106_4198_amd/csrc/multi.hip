@@ -237,7 +237,8 @@ hipError_t enqueue_step(isnmf_multi *m, hipStream_t s) {
         else if (g.c.cpw == -2)
             e = launch_fit_stile_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else if (g.c.cpw == -3)
-            e = launch_fit_t32_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
+            e = launch_fit_t32_multi(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff,
+                                     g.fold, gs);
         else if (g.prec == 1)
             e = launch_fit_multi_p<1>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         else if (g.prec == 2)
@@ -354,17 +355,18 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
     std::vector<int2> items;
     items.reserve(nitems);
     // fit items grouped by (variant, precision, fold in the fit).  When every
-    // stream is on the 16-frame tile variant with a minibatch that fits one
-    // workgroup, each fit launch folds its streams itself (the same bits as the
-    // separate fold) and the step has no fold launch.  With any other stream
-    // the fold launch stays, and moving work from it into the fit lanes (the
-    // step's critical path) only lengthens them, so then no stream is folded
-    // in its fit.
+    // stream is on a 16-frame tile variant (BF16 or FP32) with a minibatch that
+    // fits one workgroup, each fit launch folds its streams itself (the same
+    // bits as the separate fold) and the step has no fold launch.  With any
+    // other stream the fold launch stays, and moving work from it into the fit
+    // lanes (the step's critical path) only lengthens them, so then no stream
+    // is folded in its fit.
     std::vector<std::pair<std::tuple<int, int, int, int, int, int, int>, std::vector<int2>>> groups;
     bool fold_in_fit = true;
     for (int s = 0; s < S && fold_in_fit; ++s) {
         const FitClass &c = *isnmf_handle_class(handles[s]);
-        fold_in_fit = c.cpw == -1 && b[s] <= frames_per_item(c) && tile_fold_fits(c);
+        fold_in_fit = b[s] <= frames_per_item(c) &&
+                      ((c.cpw == -1 && tile_fold_fits(c)) || (c.cpw == -3 && t32_fold_fits(c)));
     }
     std::vector<char> folded(S, fold_in_fit ? 1 : 0);
     for (int s = 0; s < S; ++s) {

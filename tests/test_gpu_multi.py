@@ -229,28 +229,39 @@ def test_autotune_offers_the_valu_variant_for_fp32():
 TILE_FOLD_MIX = [(513, 50, 128, "bf16", 300), (257, 64, 40, "bf16", 100), (129, 8, 16, "bf16", 40),
                  (200, 33, 37, "bf16", 100), (608, 64, 128, "bf16", 260), (64, 1, 5, "bf16", 12),
                  (33, 20, 100, "bf16", 250)]
+# FP32 16-frame tile streams: K splits into 1..4 matrix-pipe m-tiles and 0..4
+# VALU remainder components (K = 50: 3 + 2, 33: 2 + 1, 20: 1 + 4), F up to the
+# LDS bound of the folding pass at K = 64 (400 rows), ragged minibatches
+T32_FOLD_MIX = [(513, 50, 128, "fp32", 300), (257, 48, 40, "fp32", 100), (129, 8, 16, "fp32", 40),
+                (200, 33, 37, "fp32", 100), (400, 64, 128, "fp32", 260), (64, 1, 5, "fp32", 12),
+                (33, 20, 100, "fp32", 250)]
 
 
-@pytest.mark.parametrize("fold_in_fit", [False, True])
-def test_batched_tile_streams_equal_alone_bitwise(fold_in_fit):
-    """BF16 streams on the 16-frame tile variant (ragged minibatches included)
+@pytest.mark.parametrize("mixname", ["shared_fold", "bf16_fold_in_fit", "fp32_fold_in_fit"])
+def test_batched_tile_streams_equal_alone_bitwise(mixname):
+    """Streams on the 16-frame tile variants (ragged minibatches included)
     match their runs alone.  Mixed with other variants, they share the step's
     fold launch; alone in the step with at most 128 frames each, every fit
     launch folds its streams itself (no fold launch), while alone they run the
     separate fold: W, A, B and the running loss must agree bit for bit either
-    way.  The fold-in-fit set has K = 33 (an idle fold wave), K = 1, F = 200
-    and 33 (row tiles past F), F = 608 (19 contraction steps) and b = 5."""
-    if fold_in_fit:
+    way.  The fold-in-fit sets have an idle fold wave (K = 33), K = 1, row
+    tiles past F (F = 200, 33), the largest F the LDS allows and b = 5."""
+    fold_in_fit = mixname != "shared_fold"
+    if mixname == "bf16_fold_in_fit":
         mix = TILE_FOLD_MIX
+    elif mixname == "fp32_fold_in_fit":
+        mix = T32_FOLD_MIX
     else:
         mix = [(513, 50, 128, "bf16", 300), (257, 64, 40, "bf16", 100), (129, 8, 16, "bf16", 40),
                (513, 50, 64, "fp32", 200), (1025, 40, 32, "bf16", 90), (200, 33, 37, "bf16", 100),
                (513, 50, 256, "bf16", 600)]
-    say(f"batched tile vs alone, fold in fit {fold_in_fit}")
+    say(f"batched tile vs alone, {mixname}")
     bd.tune_clear()
     for F, K, _, prec, _ in mix:
         if prec == "bf16" and F <= 640 and K <= 64:
             bd.tune_set(F, K, "bf16", 8, -1, 0)
+        if prec == "fp32" and fold_in_fit:
+            bd.tune_set(F, K, "fp32", 8, -3, 0)
     try:
         data = []
         for i, (F, K, b, prec, N) in enumerate(mix):
@@ -284,7 +295,7 @@ def test_batched_tile_streams_equal_alone_bitwise(fold_in_fit):
         st = oracle.OnlineState(W0)
         for s in range(steps):
             st.step(V[:, s * 128:(s + 1) * 128], iters=20)
-        assert rel_fro(from_gpu_kf(state(mixed[0])[0]), st.W) <= 2e-2
+        assert rel_fro(from_gpu_kf(state(mixed[0])[0]), st.W) <= (1e-5 if mix[0][3] == "fp32" else 2e-2)
         m.close()
     finally:
         bd.tune_clear()
