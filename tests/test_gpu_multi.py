@@ -391,3 +391,51 @@ def test_fp32_tile_and_valu_batched_equal_alone_bitwise(precision, cpw):
         m.close()
     finally:
         bd.tune_clear()
+
+
+@pytest.mark.parametrize("precision,cpw", [("bf16", -1), ("fp32", -3)])
+def test_fold_in_fit_with_step_options_equal_alone_bitwise(precision, cpw):
+    """A plan whose fit launches fold (every stream on a 16-frame tile variant,
+    b <= 128) with the step's options varied per stream: forgetting rho < 1,
+    W frozen (update_w off: A and B still fold, no W update), no column
+    rescale, eps = 0.  Each stream matches the same stream stepped alone (the
+    separate fold), W, A, B, t and the running loss bit for bit."""
+    opts = [dict(rho=0.7), dict(update_w=False), dict(normalize=False), dict(eps=0.0),
+            dict(rho=0.5, normalize=False)]
+    shapes = [(257, 40, 128, 300), (129, 8, 64, 200), (200, 33, 100, 250), (513, 50, 37, 100),
+              (65, 16, 128, 260)]
+    say(f"fold in fit with options, {precision}")
+    bd.tune_clear()
+    for F, K, _, _ in shapes:
+        bd.tune_set(F, K, precision, 8, cpw, 0)
+    try:
+        data = []
+        for i, (F, K, b, N) in enumerate(shapes):
+            V, W0 = synth.problem(F, K, N, seed=900 + i)
+            data.append((torch.from_numpy(np.ascontiguousarray(W0.T)).to(DEV),
+                         torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV), b))
+
+        def make():
+            return [bd.OnlineISNMF(W0, b, precision=precision, **o) for (W0, _, b), o in zip(data, opts)]
+
+        steps = 3
+        alone, loss_alone = make(), []
+        for g, (W0, V, b) in zip(alone, data):
+            ls = torch.zeros((), dtype=torch.float64, device=DEV)
+            for s in range(steps):
+                g.step(V[s * b:(s + 1) * b], None, ls)
+            loss_alone.append(ls)
+        mixed = make()
+        m = bd.MultiISNMF(mixed, [d[1] for d in data], [d[2] for d in data])
+        assert m.launches()[1] == 0
+        m.run(steps, graph=True)
+        torch.cuda.synchronize()
+        for i, (ga, gm) in enumerate(zip(alone, mixed)):
+            sa, sm = state(ga), state(gm)
+            assert sa[3] == sm[3], i
+            for x, y in zip(sa[:3], sm[:3]):
+                assert torch.equal(x, y), f"stream {i} {shapes[i]} {opts[i]} differs"
+            assert torch.equal(loss_alone[i], m.loss[i]), i
+        m.close()
+    finally:
+        bd.tune_clear()
