@@ -308,9 +308,11 @@ int isnmf_multi_frames_left(const isnmf_multi *m, long long *host_max_left);
 
 /* Not part of the method: the launches of one step of the plan.
  * *fit_launches: one per group of streams on one kernel variant;
- * *fold_launches: 1, or 0 when every stream is on the 16-frame tile variant
- * with b[s] <= 128, so that each fit launch folds its streams' minibatches
- * itself (the same bits as the fold launch). */
+ * *fold_launches: 1, or 0 when every stream is on a 16-frame tile variant
+ * (BF16 or FP32; tune_set cpw -1 or -3) with b[s] <= 128 and its LDS holds
+ * the fold's staging (F <= 608 for BF16 at K <= 64; F = 513 at K <= 52, F <=
+ * 400 at K = 64 for FP32), so that each fit launch folds its streams'
+ * minibatches itself (the same bits as the fold launch). */
 int isnmf_multi_launches(const isnmf_multi *m, int *fit_launches, int *fold_launches);
 
 /* Not part of the method: wait for the plan's streams and free it (not the
