@@ -1,8 +1,7 @@
 // Batched form: many independent online streams (each its own W, A, B, F, K,
 // minibatch size) advanced by one minibatch per step with one fit launch per
-// kernel variant in use, one fold launch and one rescale launch for all
-// streams (the fit launches of different variants side by side on up to four
-// streams).  A step reads its per-stream frame cursors on the device, so it can
+// kernel variant in use, side by side on up to four streams (lanes), each lane
+// followed by one fold launch and one rescale launch for its streams.  A step reads its per-stream frame cursors on the device, so it can
 // be captured once into a hipGraph and replayed.  Also the autotuner that picks
 // the fit variant for a shape.
 //
@@ -123,8 +122,12 @@ struct isnmf_multi {
     int nlanes = 1;
     hipStream_t side[LANES - 1] = {};
     hipEvent_t ev_fork = nullptr, ev_join[LANES - 1] = {};
-    int fold_off = 0, fold_n = 0, rs_off = 0, rs_n = 0;
-    int fold_ktm = 1;   // fold instance: covers the widest stream's component tiles
+    // Per lane: the fold and rescale items of the streams whose fit groups run
+    // on it, launched on the lane right after its fits (a lane's streams do
+    // not wait for the other lanes' fits), and the fold instance that covers
+    // the lane's widest stream.
+    int fold_off[LANES] = {}, fold_n[LANES] = {}, rs_off[LANES] = {}, rs_n[LANES] = {};
+    int fold_ktm[LANES] = {1, 1, 1, 1};
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -247,6 +250,23 @@ hipError_t enqueue_step(isnmf_multi *m, hipStream_t s) {
             e = launch_fit_multi_p<0>(g.c, m->d_fit, m->d_items + g.off, g.n, m->d_cursor, m->d_beff, gs);
         if (e != hipSuccess) return e;
     }
+    for (int l = 0; l < m->nlanes; ++l) {
+        const hipStream_t ls = l ? m->side[l - 1] : s;
+        const int nf = m->fold_n[l];
+        if (nf) {
+            const int2 *fi = m->d_items + m->fold_off[l];
+            switch (m->fold_ktm[l]) {
+                case 1: fold_multi_kernel<1><<<nf, 256, 0, ls>>>(m->d_fold, fi, m->d_beff); break;
+                case 2: fold_multi_kernel<2><<<nf, 256, 0, ls>>>(m->d_fold, fi, m->d_beff); break;
+                case 4: fold_multi_kernel<4><<<nf, 256, 0, ls>>>(m->d_fold, fi, m->d_beff); break;
+                case 8: fold_multi_kernel<8><<<nf, 256, 0, ls>>>(m->d_fold, fi, m->d_beff); break;
+                default: return hipErrorNotSupported;
+            }
+        }
+        if (m->rs_n[l])
+            rescale_multi_kernel<<<m->rs_n[l], 64, 0, ls>>>(m->d_rs, m->d_upd,
+                                                            m->d_items + m->rs_off[l], m->d_beff);
+    }
     if (m->nlanes > 1) {
         hipError_t e = hipSuccess;
         for (int i = 0; e == hipSuccess && i < m->nlanes - 1; ++i) {
@@ -255,18 +275,6 @@ hipError_t enqueue_step(isnmf_multi *m, hipStream_t s) {
         }
         if (e != hipSuccess) return e;
     }
-    if (m->fold_n) {
-        const int2 *fi = m->d_items + m->fold_off;
-        switch (m->fold_ktm) {
-            case 1: fold_multi_kernel<1><<<m->fold_n, 256, 0, s>>>(m->d_fold, fi, m->d_beff); break;
-            case 2: fold_multi_kernel<2><<<m->fold_n, 256, 0, s>>>(m->d_fold, fi, m->d_beff); break;
-            case 4: fold_multi_kernel<4><<<m->fold_n, 256, 0, s>>>(m->d_fold, fi, m->d_beff); break;
-            case 8: fold_multi_kernel<8><<<m->fold_n, 256, 0, s>>>(m->d_fold, fi, m->d_beff); break;
-            default: return hipErrorNotSupported;
-        }
-    }
-    if (m->rs_n)
-        rescale_multi_kernel<<<m->rs_n, 64, 0, s>>>(m->d_rs, m->d_upd, m->d_items + m->rs_off, m->d_beff);
     advance_kernel<<<blocks, 256, 0, s>>>(m->S, m->d_beff, m->d_cursor);
     return hipGetLastError();
 }
@@ -418,31 +426,39 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
             load[best] += m->groups[gi].cost;
         }
     }
-    // streams to XCDs by their fold tiles x components (the state they move)
-    std::vector<size_t> state(S);
-    for (int s = 0; s < S; ++s) {
-        const OnlineDev &d = *isnmf_handle_dev(handles[s]);
-        state[s] = (size_t)d.F * d.K;
+    // fold and rescale items per lane (each stream's fit group sits on one
+    // lane), and within a lane streams to XCDs by their fold tiles x
+    // components (the state they move)
+    std::vector<int> lane_of(S, 0);
+    for (const auto &G : m->groups)
+        for (int i = 0; i < G.n; ++i) lane_of[items[G.off + i].x] = G.lane;
+    for (int l = 0; l < m->nlanes; ++l) {
+        std::vector<size_t> state(S, 0);
+        for (int s = 0; s < S; ++s) {
+            const OnlineDev &d = *isnmf_handle_dev(handles[s]);
+            if (lane_of[s] == l) state[s] = (size_t)d.F * d.K;
+        }
+        const std::vector<int> xcd = xcd_assign(state);
+        std::vector<int2> list;
+        m->fold_off[l] = (int)items.size();
+        for (int s = 0; s < S; ++s) {
+            if (lane_of[s] != l || folded[s]) continue;
+            const int nt = fold_tiles(*isnmf_handle_dev(handles[s]));
+            m->fold_ktm[l] = std::max(m->fold_ktm[l], fold_ktm(isnmf_handle_dev(handles[s])->K));
+            for (int t = 0; t < nt; ++t) list.push_back(int2{s, t});
+        }
+        push_xcd_ordered(items, list, xcd);
+        m->fold_n[l] = (int)items.size() - m->fold_off[l];
+        m->rs_off[l] = (int)items.size();
+        list.clear();
+        for (int s = 0; s < S; ++s) {
+            if (lane_of[s] != l) continue;
+            const int K = isnmf_handle_dev(handles[s])->K;
+            for (int k = 0; k < K; ++k) list.push_back(int2{s, k});
+        }
+        push_xcd_ordered(items, list, xcd);
+        m->rs_n[l] = (int)items.size() - m->rs_off[l];
     }
-    const std::vector<int> xcd = xcd_assign(state);
-    std::vector<int2> list;
-    m->fold_off = (int)items.size();
-    for (int s = 0; s < S; ++s) {
-        if (folded[s]) continue;
-        const int nt = fold_tiles(*isnmf_handle_dev(handles[s]));
-        m->fold_ktm = std::max(m->fold_ktm, fold_ktm(isnmf_handle_dev(handles[s])->K));
-        for (int t = 0; t < nt; ++t) list.push_back(int2{s, t});
-    }
-    push_xcd_ordered(items, list, xcd);
-    m->fold_n = (int)items.size() - m->fold_off;
-    m->rs_off = (int)items.size();
-    list.clear();
-    for (int s = 0; s < S; ++s) {
-        const int K = isnmf_handle_dev(handles[s])->K;
-        for (int k = 0; k < K; ++k) list.push_back(int2{s, k});
-    }
-    push_xcd_ordered(items, list, xcd);
-    m->rs_n = (int)items.size() - m->rs_off;
 
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
@@ -528,7 +544,8 @@ int isnmf_multi_frames_left(const isnmf_multi *m, long long *host_max_left) {
 int isnmf_multi_launches(const isnmf_multi *m, int *fit_launches, int *fold_launches) {
     if (!m || !fit_launches || !fold_launches) return ISNMF_EINVAL;
     *fit_launches = (int)m->groups.size();
-    *fold_launches = m->fold_n > 0 ? 1 : 0;
+    *fold_launches = 0;
+    for (int l = 0; l < m->nlanes; ++l) *fold_launches += m->fold_n[l] > 0 ? 1 : 0;
     return ISNMF_OK;
 }
 

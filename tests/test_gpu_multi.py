@@ -280,7 +280,8 @@ def test_batched_tile_streams_equal_alone_bitwise(mixname):
             loss_alone.append(ls)
         mixed = handles(data)
         m = bd.MultiISNMF(mixed, [d[1] for d in data], [d[2] for d in data])
-        assert m.launches()[1] == (0 if fold_in_fit else 1)
+        fits, folds = m.launches()
+        assert folds == 0 if fold_in_fit else 1 <= folds <= min(fits, 4)
         m.run(1, graph=False)
         m.run(steps - 1, graph=True)
         torch.cuda.synchronize()
