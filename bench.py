@@ -412,6 +412,83 @@ def bench_heldout(bd, synth, torch, np, g, Wt, dev, seed, start, n_test=8192):
     return out
 
 
+def study_forgetting(bd, synth, torch, np, dev, seed, n_train=10_000, n_test=2_000,
+                     Fs=257, Ks=10, betas=(1, 10, 100, 1000), rs=(0.5, 0.7, 0.9, 1.0),
+                     checkpoints=(1, 2, 5, 10, 20), long_checkpoints=(1, 2, 5, 10, 20, 50, 100),
+                     long_beta=100, batch_cycles=(1, 2, 5, 10, 20, 50, 100, 200)):
+    """The paper's small/medium-set protocol (section 3) on the synthetic
+    stand-in: online IS-NMF with warm restarts and one update of h per sample,
+    passes over a finite train set in a new order each pass, for a grid of
+    minibatch sizes beta and forgetting factors r (rho = r^(beta/N), section
+    2.3), against batch MU from the same W(0) (K random train frames, as the
+    paper initialises W).  The criterion is the paper's: eq. (1) per matrix
+    entry on held-out frames of the same stream, their h fitted (100 updates)
+    at the learned W, against the GPU time spent learning.  A run whose W or h
+    leaves the positive numbers (a guard flag) is marked unstable.  Minibatches
+    of at least long_beta frames take the longer pass schedule (their passes
+    are short on the GPU)."""
+    V = synth.frames(Fs, Ks, n_train + n_test, seed)
+    rng = np.random.default_rng(seed)
+    cols = rng.choice(n_train, size=Ks, replace=False)
+    W0 = np.ascontiguousarray(V[:, cols].T)                       # (K, F): K train frames
+    Vtr = torch.from_numpy(np.ascontiguousarray(V[:, :n_train].T)).to(dev)
+    Vte = torch.from_numpy(np.ascontiguousarray(V[:, n_train:].T)).to(dev)
+    W0t = torch.from_numpy(W0).to(dev)
+    P = max(max(checkpoints), max(long_checkpoints))
+    perm = torch.from_numpy(np.stack([rng.permutation(n_train) for _ in range(P)])
+                            .astype(np.int32)).to(dev)
+
+    def heldout(W):
+        g = bd.OnlineISNMF(W.contiguous(), n_test, inner_iters=100)
+        H = torch.empty((n_test, Ks), dtype=torch.float32, device=dev)
+        g.fit(Vte, H)
+        val = bd.objective(Vte, g.get()[0], H).item() / Fs
+        g.close()
+        return val
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    out = {"study": "forgetting factor and minibatch size (section 3 protocol, synthetic)",
+           "F": Fs, "K": Ks, "train_frames": n_train, "test_frames": n_test,
+           "inner_iters": 1, "restarts": "warm", "init": "K random train frames",
+           "heldout_W0_per_entry": heldout(W0t), "floor_per_entry": 0.5772156649015329,
+           "online": {}, "batch": []}
+    for beta in betas:
+        for r in rs:
+            rho = bd.forgetting_rho(r, beta, n_train)
+            g = bd.OnlineISNMF(W0t, beta, inner_iters=1, warm=True, rho=rho)
+            H = torch.ones((n_train, Ks), dtype=torch.float32, device=dev)
+            pts, done, ms = [], 0, 0.0
+            for c in (long_checkpoints if beta >= long_beta else checkpoints):
+                torch.cuda.synchronize()
+                e0.record()
+                g.run_passes(Vtr, perm[done:c].contiguous(), beta, H)
+                e1.record()
+                torch.cuda.synchronize()
+                ms += e0.elapsed_time(e1)
+                done = c
+                if g.status() != 0:
+                    pts.append([c, round(ms, 2), None])
+                    break
+                pts.append([c, round(ms, 2), heldout(g.get()[0])])
+            out["online"][f"beta={beta},r={r}"] = {"rho": rho, "stable": g.status() == 0,
+                                                   "passes_ms_heldout": pts}
+            g.close()
+    W = W0t.clone()
+    H = torch.ones((n_train, Ks), dtype=torch.float32, device=dev)
+    done, ms = 0, 0.0
+    for c in batch_cycles:
+        torch.cuda.synchronize()
+        e0.record()
+        bd.batch_mu(Vtr, W, H, c - done, trace=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1)
+        done = c
+        out["batch"].append([c, round(ms, 2), heldout(W)])
+    return out
+
+
 def bench_served(bd, synth, torch, np, dev, S, n_chunks, duration_s, threads, seed0,
                  tune="latency"):
     """Continuous batching: S sessions (F in {257,513}, K in {32,64}, BF16
@@ -516,6 +593,9 @@ def main() -> int:
                     help="comma-separated forms to run besides the timed pass (bf16, fp16, plain, "
                          "batch_mu, multipass, batched_uniform, batched_uniform_fp32, "
                          "batched_mixed, served, served_throughput); default all")
+    ap.add_argument("--study", default="", choices=["", "forgetting"],
+                    help="run a study instead of the benchmark: 'forgetting' is the paper's "
+                         "(beta, r) protocol of section 3 on synthetic frames (one JSON line)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic, to scale rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
@@ -537,6 +617,9 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
+    if args.study == "forgetting":
+        print(json.dumps(study_forgetting(bd, synth, torch, np, dev, args.seed)), flush=True)
+        return 0
     if args.copy_calib_mib > 0:
         src = torch.ones(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
