@@ -291,7 +291,7 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0, pr
     frames = int(sum(int(b) * steps for b in bs))
     flops = float(sum(flops_per_frame(int(Fi), int(Ki), ITERS) * int(b) * steps
                       for Fi, Ki, b in zip(Fs, Ks, bs)))
-    fit_launches, fold_launches = m.launches()
+    fit_launches, fold_launches, rescale_launches = m.launches()
     m.close()
     for h in hs:
         h.close()
@@ -301,7 +301,8 @@ def bench_batched(bd, synth, torch, np, dev, S, steps, threads, mixed, seed0, pr
            "achieved_tflops": flops / (ms / 1e3) / 1e12,
            f"frac_{precision}_peak": flops / (ms / 1e3) / peak,
            "gen_s": round(gen_s, 1),
-           "launches_per_step": {"fit": fit_launches, "fold": fold_launches}}
+           "launches_per_step": {"fit": fit_launches, "fold": fold_launches,
+                                 "rescale": rescale_launches}}
     n_tile = sum(1 for v in variants.values() if v[1] == -1)
     n_stile = sum(1 for v in variants.values() if v[1] == -2)
     n_t32 = sum(1 for v in variants.values() if v[1] == -3)

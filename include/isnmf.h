@@ -266,8 +266,9 @@ int isnmf_online_destroy(isnmf_online *h);
  * minibatch of every stream that has frames left (fresh restarts), folds it
  * into that stream's A and B and updates its W -- exactly
  * isnmf_online_step on each handle, with one fit launch per kernel variant
- * in use, on up to four lanes, each followed by one fold (see
- * isnmf_multi_launches) and one rescale launch for its streams.  The frame
+ * in use, on up to four lanes, each followed by one fold and one rescale
+ * launch for its streams (none where the fits fold and rescale themselves,
+ * see isnmf_multi_launches).  The frame
  * cursors live on the device, so a step can be captured into a hipGraph and
  * replayed (isnmf_multi_run with use_graph).
  *
@@ -308,13 +309,15 @@ int isnmf_multi_frames_left(const isnmf_multi *m, long long *host_max_left);
 
 /* Not part of the method: the launches of one step of the plan.
  * *fit_launches: one per group of streams on one kernel variant;
- * *fold_launches: one per lane of fit launches (up to four), or 0 when
- * every stream is on a 16-frame tile variant
+ * *fold_launches and *rescale_launches: one each per lane of fit launches
+ * (up to four), or 0 when every stream is on a 16-frame tile variant
  * (BF16 or FP32; tune_set cpw -1 or -3) with b[s] <= 128 and its LDS holds
  * the fold's staging (F <= 608 for BF16 at K <= 64; F = 513 at K <= 52, F <=
- * 400 at K = 64 for FP32), so that each fit launch folds its streams'
- * minibatches itself (the same bits as the fold launch). */
-int isnmf_multi_launches(const isnmf_multi *m, int *fit_launches, int *fold_launches);
+ * 400 at K = 64 for FP32), so that each fit workgroup folds its stream's
+ * minibatch and rescales W itself (the same bits as the fold and rescale
+ * launches).  ISNMF_EINVAL for a null argument. */
+int isnmf_multi_launches(const isnmf_multi *m, int *fit_launches, int *fold_launches,
+                         int *rescale_launches);
 
 /* Not part of the method: wait for the plan's streams and free it (not the
  * handles, not the workspace). */

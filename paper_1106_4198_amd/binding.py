@@ -74,7 +74,7 @@ def _load():
         "isnmf_multi_step": (i, [vp, vp]),
         "isnmf_multi_run": (i, [vp, i, i, vp]),
         "isnmf_multi_frames_left": (i, [vp, ctypes.POINTER(ctypes.c_longlong)]),
-        "isnmf_multi_launches": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
+        "isnmf_multi_launches": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
         "isnmf_multi_destroy": (i, [vp]),
         "isnmf_autotune_workspace_size": (sz, [i, i, i, P]),
         "isnmf_autotune": (i, [i, i, i, P, i, ctypes.POINTER(i), ctypes.POINTER(d), vp, sz, vp]),
@@ -392,11 +392,12 @@ class MultiISNMF:
         return n.value
 
     def launches(self) -> tuple:
-        """(fit launches, fold launches) of one step; 0 fold launches when every
-        fit launch folds its streams itself."""
-        f, g = ctypes.c_int(), ctypes.c_int()
-        _check(_lib.isnmf_multi_launches(self._m, ctypes.byref(f), ctypes.byref(g)), "launches")
-        return f.value, g.value
+        """(fit, fold, rescale) launches of one step; no fold or rescale launch
+        when every fit launch folds and rescales its streams itself."""
+        f, g, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.isnmf_multi_launches(self._m, ctypes.byref(f), ctypes.byref(g), ctypes.byref(r)),
+               "launches")
+        return f.value, g.value, r.value
 
     def close(self):
         if getattr(self, "_m", None):

@@ -90,7 +90,8 @@ struct LaunchTiming {
 };
 extern thread_local LaunchTiming g_launch_timing;
 
-struct FoldArgs;   // fold_body.h
+struct FoldArgs;      // fold_body.h
+struct RescaleArgs;   // state_body.h
 
 // One stream's fit problem for the fused kernels (by value for a single
 // stream, an array in device memory for the batched form).
@@ -116,6 +117,9 @@ struct FitDesc {
     // itself (the batched form's 16-frame tile streams of at most 128 frames),
     // else null: the fit then writes R1, R2 for a separate fold.
     const FoldArgs *fold;
+    // With fold: the stream's column rescale (device memory) when the fit
+    // launch also rescales W after its fold, else null.
+    const RescaleArgs *rs;
 };
 
 // One chunk of a served step: session (index in the server's device tables),

@@ -29,6 +29,7 @@
 #include "common.h"
 #include "devmath.h"
 #include "fold_body.h"
+#include "state_body.h"
 
 namespace isnmf {
 namespace tile {
@@ -561,7 +562,8 @@ __global__ __launch_bounds__(NWT * 64) void fit_tile_kernel(FitDesc a) {
 
 // Batched form: item = (stream, tile of 128 frames); tiles past the stream's
 // minibatch of this step exit.  FOLD: every stream of the launch has one tile
-// (b <= 128) and a fold descriptor.
+// (b <= 128) and a fold descriptor, and the workgroup also rescales W when the
+// descriptor carries the rescale.
 template <int S, int KS, bool FOLD>
 __global__ __launch_bounds__(NWT * 64) void fit_tile_multi_kernel(const FitDesc *__restrict__ descs,
                                                                   const int2 *__restrict__ items,
@@ -576,6 +578,7 @@ __global__ __launch_bounds__(NWT * 64) void fit_tile_multi_kernel(const FitDesc 
     a.V += c * a.ldv;
     if (a.Hb) a.Hb += c * a.ldh;
     body<S, KS, FOLD>(a, it.y * FPW);
+    if constexpr (FOLD) rescale_in_workgroup<NWT>(a, b, a.fold->update_w);
 }
 
 // Served form: grid (chunk i, 128-frame tile j) over a step's work list.

@@ -151,6 +151,7 @@ FitDesc make_fit_desc(const OnlineDev &d, const float *V, int ldv, int b, int it
     a.lossf = d.lossf;
     a.flags = d.flags;
     a.fold = nullptr;
+    a.rs = nullptr;
     return a;
 }
 

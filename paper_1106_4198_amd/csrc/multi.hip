@@ -383,7 +383,10 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         const FitClass &c = *isnmf_handle_class(handles[s]);
         fit[s] = make_fit_desc(d, V[s], ldv[s], b[s], p.inner_iters, p.eps, 0, nullptr, d.K);
         fold[s] = fold_args(d, b[s], p.rho, p.update_w, nullptr, d_loss ? d_loss + s : nullptr);
-        if (folded[s]) fit[s].fold = m->d_fold + s;
+        if (folded[s]) {
+            fit[s].fold = m->d_fold + s;
+            fit[s].rs = m->d_rs + s;
+        }
         rs[s] = rescale_args(d, p.normalize, 0, nullptr, d.K);
         rs[s].dwpart = nullptr;   // the batched step reports no dW
         upd[s] = p.update_w;
@@ -452,7 +455,7 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         m->rs_off[l] = (int)items.size();
         list.clear();
         for (int s = 0; s < S; ++s) {
-            if (lane_of[s] != l) continue;
+            if (lane_of[s] != l || folded[s]) continue;
             const int K = isnmf_handle_dev(handles[s])->K;
             for (int k = 0; k < K; ++k) list.push_back(int2{s, k});
         }
@@ -541,11 +544,16 @@ int isnmf_multi_frames_left(const isnmf_multi *m, long long *host_max_left) {
     return ISNMF_OK;
 }
 
-int isnmf_multi_launches(const isnmf_multi *m, int *fit_launches, int *fold_launches) {
-    if (!m || !fit_launches || !fold_launches) return ISNMF_EINVAL;
+int isnmf_multi_launches(const isnmf_multi *m, int *fit_launches, int *fold_launches,
+                         int *rescale_launches) {
+    if (!m || !fit_launches || !fold_launches || !rescale_launches) return ISNMF_EINVAL;
     *fit_launches = (int)m->groups.size();
     *fold_launches = 0;
-    for (int l = 0; l < m->nlanes; ++l) *fold_launches += m->fold_n[l] > 0 ? 1 : 0;
+    *rescale_launches = 0;
+    for (int l = 0; l < m->nlanes; ++l) {
+        *fold_launches += m->fold_n[l] > 0 ? 1 : 0;
+        *rescale_launches += m->rs_n[l] > 0 ? 1 : 0;
+    }
     return ISNMF_OK;
 }
 

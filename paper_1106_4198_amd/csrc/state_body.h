@@ -114,6 +114,25 @@ __device__ __forceinline__ void rescale_body(const RescaleArgs &a, int k, int b)
     }
 }
 
+// The column rescale of a stream whose fold ran in this workgroup (the
+// batched form's folding fits: one workgroup holds the stream's whole
+// minibatch, statistics and W).  A barrier first makes the workgroup's stores
+// of the unscaled W, of A and of B visible to all its waves; then wave w
+// rescales columns w, w + NW, ... with rescale_body, so the bits are those of
+// the separate rescale launch.  Without a W update the fold stored A and B
+// with no pending scale: sc = 1.
+template <int NW>
+__device__ inline void rescale_in_workgroup(const FitDesc &a, int b, bool update_w) {
+    if (!a.rs) return;   // uniform per workgroup
+    __syncthreads();
+    const RescaleArgs &ra = *a.rs;
+    if (!update_w) {
+        for (int k = threadIdx.x; k < ra.K; k += NW * 64) ra.sc[k] = 1.0;
+        return;
+    }
+    for (int k = threadIdx.x >> 6; k < ra.K; k += NW) rescale_body(ra, k, b);
+}
+
 inline W16Out w16_out(const OnlineDev &d) {
     W16Out o;
     o.r = d.w16_kind && d.w16_rows ? d.W16r : nullptr;

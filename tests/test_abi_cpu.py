@@ -119,11 +119,12 @@ def test_einval_before_any_device_work():
     assert L.isnmf_objective(fake, 9, fake, 10, fake, 2, 10, 2, 5, 0.0, fake, fake, 1 << 20, None) == bd.EINVAL
     # a served session's running loss needs a server (checked before any device work)
     assert L.isnmf_server_set_loss(None, 0, fake) == bd.EINVAL
-    # a batched plan's launch count needs a plan and both outputs
-    n1, n2 = ctypes.c_int(), ctypes.c_int()
-    assert L.isnmf_multi_launches(None, ctypes.byref(n1), ctypes.byref(n2)) == bd.EINVAL
-    assert L.isnmf_multi_launches(fake, None, ctypes.byref(n2)) == bd.EINVAL
-    assert L.isnmf_multi_launches(fake, ctypes.byref(n1), None) == bd.EINVAL
+    # a batched plan's launch count needs a plan and all three outputs
+    n1, n2, n3 = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert L.isnmf_multi_launches(None, ctypes.byref(n1), ctypes.byref(n2), ctypes.byref(n3)) == bd.EINVAL
+    assert L.isnmf_multi_launches(fake, None, ctypes.byref(n2), ctypes.byref(n3)) == bd.EINVAL
+    assert L.isnmf_multi_launches(fake, ctypes.byref(n1), None, ctypes.byref(n3)) == bd.EINVAL
+    assert L.isnmf_multi_launches(fake, ctypes.byref(n1), ctypes.byref(n2), None) == bd.EINVAL
 
 
 def test_product_path_does_not_touch_the_oracle():

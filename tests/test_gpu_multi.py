@@ -280,8 +280,9 @@ def test_batched_tile_streams_equal_alone_bitwise(mixname):
             loss_alone.append(ls)
         mixed = handles(data)
         m = bd.MultiISNMF(mixed, [d[1] for d in data], [d[2] for d in data])
-        fits, folds = m.launches()
+        fits, folds, rescales = m.launches()
         assert folds == 0 if fold_in_fit else 1 <= folds <= min(fits, 4)
+        assert rescales == folds
         m.run(1, graph=False)
         m.run(steps - 1, graph=True)
         torch.cuda.synchronize()
@@ -428,7 +429,7 @@ def test_fold_in_fit_with_step_options_equal_alone_bitwise(precision, cpw):
             loss_alone.append(ls)
         mixed = make()
         m = bd.MultiISNMF(mixed, [d[1] for d in data], [d[2] for d in data])
-        assert m.launches()[1] == 0
+        assert m.launches()[1:] == (0, 0)
         m.run(steps, graph=True)
         torch.cuda.synchronize()
         for i, (ga, gm) in enumerate(zip(alone, mixed)):
