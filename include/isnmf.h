@@ -310,12 +310,13 @@ int isnmf_multi_frames_left(const isnmf_multi *m, long long *host_max_left);
 /* Not part of the method: the launches of one step of the plan.
  * *fit_launches: one per group of streams on one kernel variant;
  * *fold_launches and *rescale_launches: one each per lane of fit launches
- * (up to four), or 0 when every stream is on a 16-frame tile variant
- * (BF16 or FP32; tune_set cpw -1 or -3) with b[s] <= 128 and its LDS holds
- * the fold's staging (F <= 608 for BF16 at K <= 64; F = 513 at K <= 52, F <=
- * 400 at K = 64 for FP32), so that each fit workgroup folds its stream's
- * minibatch and rescales W itself (the same bits as the fold and rescale
- * launches).  ISNMF_EINVAL for a null argument. */
+ * (up to four).  There is no fold launch when every stream is on a 16-frame
+ * tile variant (BF16 or FP32; tune_set cpw -1 or -3) with b[s] <= 128 and
+ * its LDS holds the fold's staging (F <= 608 for BF16 at K <= 64; F = 513 at
+ * K <= 52, F <= 400 at K = 64 for FP32): each fit workgroup then folds its
+ * stream's minibatch itself, and in the BF16 variant also rescales W (the
+ * same bits as the fold and rescale launches), so such a plan of BF16
+ * streams has no rescale launch either.  ISNMF_EINVAL for a null argument. */
 int isnmf_multi_launches(const isnmf_multi *m, int *fit_launches, int *fold_launches,
                          int *rescale_launches);
 

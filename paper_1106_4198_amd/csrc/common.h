@@ -118,7 +118,8 @@ struct FitDesc {
     // else null: the fit then writes R1, R2 for a separate fold.
     const FoldArgs *fold;
     // With fold: the stream's column rescale (device memory) when the fit
-    // launch also rescales W after its fold, else null.
+    // launch also rescales W after its fold (the BF16 16-frame tile variant),
+    // else null.
     const RescaleArgs *rs;
 };
 

@@ -41,7 +41,6 @@
 #include "common.h"
 #include "devmath.h"
 #include "fold_body.h"
-#include "state_body.h"
 
 namespace isnmf {
 namespace t32 {
@@ -591,8 +590,7 @@ __global__ __launch_bounds__(NWT * 64) void fit_t32_kernel(FitDesc a) {
 
 // Batched form: item = (stream, tile of 128 frames); tiles past the stream's
 // minibatch of this step exit.  FOLD: every stream of the launch has one tile
-// (b <= 128) and a fold descriptor, and the workgroup also rescales W when the
-// descriptor carries the rescale.
+// (b <= 128) and a fold descriptor.
 template <int MT, int KR, bool FOLD>
 __global__ __launch_bounds__(NWT * 64) void fit_t32_multi_kernel(const FitDesc *__restrict__ descs,
                                                                  const int2 *__restrict__ items,
@@ -607,7 +605,6 @@ __global__ __launch_bounds__(NWT * 64) void fit_t32_multi_kernel(const FitDesc *
     a.V += c * a.ldv;
     if (a.Hb) a.Hb += c * a.ldh;
     body<MT, KR, FOLD>(a, it.y * FPW);
-    if constexpr (FOLD) rescale_in_workgroup<NWT>(a, b, a.fold->update_w);
 }
 
 // Served form: grid (chunk i, 128-frame tile j) over a step's work list.

@@ -377,6 +377,10 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
                       ((c.cpw == -1 && tile_fold_fits(c)) || (c.cpw == -3 && t32_fold_fits(c)));
     }
     std::vector<char> folded(S, fold_in_fit ? 1 : 0);
+    // Folding BF16 tile fits also rescale their streams in the same workgroup.
+    // The FP32 tile fit keeps the rescale launch: at its register budget the
+    // rescale body spills inside its fold rounds and costs more than the launch.
+    std::vector<char> rescaled(S, 0);
     for (int s = 0; s < S; ++s) {
         const OnlineDev &d = *isnmf_handle_dev(handles[s]);
         const isnmf_params &p = *isnmf_handle_params(handles[s]);
@@ -385,7 +389,10 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         fold[s] = fold_args(d, b[s], p.rho, p.update_w, nullptr, d_loss ? d_loss + s : nullptr);
         if (folded[s]) {
             fit[s].fold = m->d_fold + s;
-            fit[s].rs = m->d_rs + s;
+            if (c.cpw == -1) {
+                fit[s].rs = m->d_rs + s;
+                rescaled[s] = 1;
+            }
         }
         rs[s] = rescale_args(d, p.normalize, 0, nullptr, d.K);
         rs[s].dwpart = nullptr;   // the batched step reports no dW
@@ -455,7 +462,7 @@ int isnmf_multi_create(isnmf_multi **out, isnmf_online *const *handles, int S,
         m->rs_off[l] = (int)items.size();
         list.clear();
         for (int s = 0; s < S; ++s) {
-            if (lane_of[s] != l || folded[s]) continue;
+            if (lane_of[s] != l || rescaled[s]) continue;
             const int K = isnmf_handle_dev(handles[s])->K;
             for (int k = 0; k < K; ++k) list.push_back(int2{s, k});
         }
