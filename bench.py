@@ -325,11 +325,22 @@ def bench_batch_mu(bd, torch, np, Vt, Wt, N, cycles):
     objective of eq. (1) after every cycle.  Algorithmic work per cycle: the
     H update (W H and the pair W^T r2, W^T r1), the statistics of eq. (3) at
     the new H (W H again and the rank-N products) and the objective's W H:
-    7 F K N multiply-adds."""
+    7 F K N multiply-adds.  The fit runs the variant the autotuner picks for
+    one update of N frames; the shape's tuning entry is restored afterwards."""
     V = Vt[:N]
+    saved = bd.tune_get(F, K, "fp32")
+    bd.autotune(F, K, N, precision="fp32", inner_iters=1, trials=3)
+    variant = bd.tune_get(F, K, "fp32")
+    try:
+        return _time_batch_mu(bd, torch, np, V, Wt, N, cycles, variant)
+    finally:
+        bd.tune_set(F, K, "fp32", *saved)
+
+
+def _time_batch_mu(bd, torch, np, V, Wt, N, cycles, variant):
 
     def fresh():
-        return Wt.clone(), torch.ones((N, K), dtype=torch.float32, device=Vt.device)
+        return Wt.clone(), torch.ones((N, K), dtype=torch.float32, device=V.device)
 
     W, H = fresh()
     bd.batch_mu(V, W, H, 1)                         # warm-up (and workspace allocation)
@@ -349,7 +360,7 @@ def bench_batch_mu(bd, torch, np, Vt, Wt, N, cycles):
             "achieved_tflops": flops / (ms / 1e3) / 1e12,
             "frac_fp32_peak": flops / (ms / 1e3) / PEAK_FP32_MFMA,
             "objective_per_entry": [float(tr[0]) / F, float(tr[-1]) / F],
-            "monotone": bool(np.all(np.diff(tr) <= 1e-6 * tr[:-1]))}
+            "monotone": bool(np.all(np.diff(tr) <= 1e-6 * tr[:-1])), "fit_variant": list(variant)}
 
 
 def bench_multipass(bd, torch, np, Vt, Wt, N, passes, seed):

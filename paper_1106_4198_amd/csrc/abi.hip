@@ -534,7 +534,7 @@ int isnmf_batch_mu(const float *V, int ldv, int F, int N, float *W, int ldw, flo
     h.p.update_w = 1;
     h.t = 0;
     h.kernel_used = use_fused(p, F, K) ? ISNMF_KERNEL_FUSED : ISNMF_KERNEL_PLAIN;
-    h.cls = fit_class(F, K, prec_code(p));
+    h.cls = tuned_class(F, K, prec_code(p), N);   // as an online handle of N frames
     hipStream_t s = (hipStream_t)stream;
     if (hipMemsetAsync(h.d.flags, 0, sizeof(int), s) != hipSuccess) return ISNMF_EDEVICE;
     if (hipMemsetAsync(h.d.counter, 0, sizeof(unsigned), s) != hipSuccess) return ISNMF_EDEVICE;

@@ -41,6 +41,55 @@ __global__ void objective_frames(const float *__restrict__ V, int ldv,
     if (threadIdx.x == 0) frame_buf[n] = red[0];
 }
 
+// The same sums as objective_frames, with W read once per block instead of
+// once per frame: thread t keeps its rows t, t + 256, ... of W (RF =
+// ceil(F / 256) rows, K <= KM components) in registers and the block loops
+// over frames n = blockIdx.x, blockIdx.x + gridDim.x, ...  Each model value
+// is the same FMA chain over k in increasing order, the thread adds its
+// terms in row order and the block sums the 256 thread sums in the same
+// tree, so every frame sum has objective_frames' bits.
+template <int RF, int KM>
+__global__ __launch_bounds__(256) void objective_frames_reg(const float *__restrict__ V, int ldv,
+                                                            const float *__restrict__ W, int ldw,
+                                                            const float *__restrict__ H, int ldh,
+                                                            int F, int K, int N, double eps,
+                                                            double *__restrict__ frame_buf) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    const float epsf = float(eps);
+    float w[RF][KM];
+#pragma unroll
+    for (int r = 0; r < RF; ++r) {
+        const int f = t + 256 * r;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) w[r][k] = (f < F && k < K) ? W[f + (size_t)k * ldw] : 0.f;
+    }
+    for (int n = blockIdx.x; n < N; n += gridDim.x) {
+        const float *h = H + (size_t)n * ldh;
+        const float *v = V + (size_t)n * ldv;
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
+            const int f = t + 256 * r;
+            if (f < F) {
+                float x = epsf;
+#pragma unroll
+                for (int k = 0; k < KM; ++k)
+                    if (k < K) x = __builtin_fmaf(w[r][k], h[k], x);
+                s += dis_term(eps + double(v[f]), double(x));
+            }
+        }
+        red[t] = s;
+        __syncthreads();
+        for (int m = 128; m > 0; m >>= 1) {
+            if (t < m) red[t] += red[t + m];
+            __syncthreads();
+        }
+        if (t == 0) frame_buf[n] = red[0];
+        __syncthreads();   // red is written again for the next frame
+    }
+}
+
 // One block: fixed-order total of the frame sums, scaled by 1/N.
 __global__ void objective_total(int N, const double *__restrict__ frame_buf,
                                 double *__restrict__ out) {
@@ -84,11 +133,51 @@ hipError_t scratch_ptr(double **out) {
     return hipSuccess;
 }
 
+namespace {
+
+// Register-resident form for RF = ceil(F / 256) <= 4 rows per thread and K
+// components rounded up to KM (a multiple of 8) with RF * KM <= 168 floats of
+// W per thread; false where it has no instance.
+constexpr int OBJ_BLOCKS = 512;   // two 4-wave blocks per CU
+
+template <int RF>
+bool launch_reg(int KM, const float *V, int ldv, const float *W, int ldw, const float *H, int ldh,
+                int F, int K, int N, double eps, double *frame_buf, hipStream_t s) {
+    const int grid = N < OBJ_BLOCKS ? N : OBJ_BLOCKS;
+    switch (KM) {
+#define ISNMF_OBJ_KM(M)                                                                          \
+    case M:                                                                                      \
+        if constexpr (RF * M <= 168) {                                                           \
+            objective_frames_reg<RF, M><<<grid, 256, 0, s>>>(V, ldv, W, ldw, H, ldh, F, K, N, eps, \
+                                                             frame_buf);                         \
+            return true;                                                                         \
+        }                                                                                        \
+        return false;
+        ISNMF_OBJ_KM(8) ISNMF_OBJ_KM(16) ISNMF_OBJ_KM(24) ISNMF_OBJ_KM(32)
+        ISNMF_OBJ_KM(40) ISNMF_OBJ_KM(48) ISNMF_OBJ_KM(56) ISNMF_OBJ_KM(64)
+#undef ISNMF_OBJ_KM
+        default: return false;
+    }
+}
+
+}  // namespace
+
 hipError_t launch_objective(const float *V, int ldv, const float *W, int ldw, const float *H,
                             int ldh, int F, int K, int N, double eps, double *frame_buf,
                             double *d_out, hipStream_t s) {
-    if (N > 0)
-        objective_frames<<<N, 256, 0, s>>>(V, ldv, W, ldw, H, ldh, F, K, eps, frame_buf);
+    if (N > 0) {
+        const int RF = (F + 255) / 256, KM = (K + 7) / 8 * 8;
+        bool done = false;
+        switch (RF) {
+            case 1: done = launch_reg<1>(KM, V, ldv, W, ldw, H, ldh, F, K, N, eps, frame_buf, s); break;
+            case 2: done = launch_reg<2>(KM, V, ldv, W, ldw, H, ldh, F, K, N, eps, frame_buf, s); break;
+            case 3: done = launch_reg<3>(KM, V, ldv, W, ldw, H, ldh, F, K, N, eps, frame_buf, s); break;
+            case 4: done = launch_reg<4>(KM, V, ldv, W, ldw, H, ldh, F, K, N, eps, frame_buf, s); break;
+            default: break;
+        }
+        if (!done)
+            objective_frames<<<N, 256, 0, s>>>(V, ldv, W, ldw, H, ldh, F, K, eps, frame_buf);
+    }
     objective_total<<<1, 256, 0, s>>>(N, frame_buf, d_out);
     return hipGetLastError();
 }

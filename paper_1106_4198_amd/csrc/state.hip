@@ -53,6 +53,17 @@ __global__ __launch_bounds__(64) void rescale_kernel(RescaleArgs a, int b) {
     rescale_body(a, blockIdx.x, b);
 }
 
+// Warm-start activations times their column's scale, H[n][k] *= s_k, one
+// thread per entry (the multiplication rescale_body applies per column, here
+// over rows of H in memory order).
+__global__ void scale_h_kernel(float *__restrict__ Hb, int ldh, int b, int K,
+                               const double *__restrict__ sc) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)b * K) return;
+    const int n = (int)(i / K), k = (int)(i % K);
+    Hb[(size_t)n * ldh + k] *= float(sc[k]);
+}
+
 __global__ void unit_scale_kernel(double *__restrict__ sc, int K) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < K) sc[k] = 1.0;
@@ -155,12 +166,23 @@ hipError_t launch_fold(const OnlineDev &d, int b, double rho, int update_w, int 
     return hipGetLastError();
 }
 
+// Warm frames per step above which H is scaled by its own launch.
+constexpr int SCALE_H_APART = 2048;
+
 hipError_t launch_rescale(const OnlineDev &d, int b, int update_w, int normalize, int warm,
                           float *Hb, int ldh, double *d_dw, hipStream_t s) {
     if (update_w) {
         RescaleArgs a = rescale_args(d, normalize, warm, Hb, ldh);
         if (!d_dw) a.dwpart = nullptr;
+        // Many warm frames (batch MU's whole set): the per-column loop over H
+        // strides by ldh, so a separate launch scales H row by row instead.
+        const bool h_apart = warm && Hb && normalize && b > SCALE_H_APART;
+        if (h_apart) a.Hb = nullptr;
         rescale_kernel<<<d.K, 64, 0, s>>>(a, b);
+        if (h_apart) {
+            const long n = (long)b * d.K;
+            scale_h_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(Hb, ldh, b, d.K, d.sc);
+        }
     } else {
         // the fold stored A and B with no pending scale
         unit_scale_kernel<<<(d.K + 63) / 64, 64, 0, s>>>(d.sc, d.K);
