@@ -45,17 +45,20 @@ __global__ void objective_frames(const float *__restrict__ V, int ldv,
 // once per frame: thread t keeps its rows t, t + 256, ... of W (RF =
 // ceil(F / 256) rows, K <= KM components) in registers and the block loops
 // over frames n = blockIdx.x, blockIdx.x + gridDim.x, ...  Each model value
-// is the same FMA chain over k in increasing order, the thread adds its
-// terms in row order and the block sums the 256 thread sums in the same
-// tree, so every frame sum has objective_frames' bits.
+// is the same FMA chain over k in increasing order (the KM - K padded steps
+// add 0 * 0, which leaves a chain that starts at eps >= 0 with non-negative
+// W and H unchanged), the thread adds its terms in row order, and the 256
+// thread sums meet in the same tree: the two levels across waves through LDS,
+// the last six within wave 0 by shuffles that pair the same lanes.  So every
+// frame sum has objective_frames' bits for W, H >= 0.
 template <int RF, int KM>
 __global__ __launch_bounds__(256) void objective_frames_reg(const float *__restrict__ V, int ldv,
                                                             const float *__restrict__ W, int ldw,
                                                             const float *__restrict__ H, int ldh,
                                                             int F, int K, int N, double eps,
                                                             double *__restrict__ frame_buf) {
-    __shared__ double red[256];
-    const int t = threadIdx.x;
+    __shared__ double red[2][256];   // alternate frames, so one barrier less per frame
+    const int t = threadIdx.x, lane = t & 63;
     const float epsf = float(eps);
     float w[RF][KM];
 #pragma unroll
@@ -64,29 +67,49 @@ __global__ __launch_bounds__(256) void objective_frames_reg(const float *__restr
 #pragma unroll
         for (int k = 0; k < KM; ++k) w[r][k] = (f < F && k < K) ? W[f + (size_t)k * ldw] : 0.f;
     }
-    for (int n = blockIdx.x; n < N; n += gridDim.x) {
-        const float *h = H + (size_t)n * ldh;
-        const float *v = V + (size_t)n * ldv;
-        double s = 0.0;
+    // a frame's h (lane k of every wave holds h_k, zero past K) and the
+    // thread's v values, loaded one frame ahead
+    auto load = [&](int n, float &hv, float (&vv)[RF]) {
+        hv = (n < N && lane < K) ? H[(size_t)n * ldh + lane] : 0.f;
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
             const int f = t + 256 * r;
-            if (f < F) {
-                float x = epsf;
+            vv[r] = (n < N && f < F) ? V[(size_t)n * ldv + f] : 0.f;
+        }
+    };
+    float hv, vv[RF];
+    load(blockIdx.x, hv, vv);
+    int p = 0;
+    for (int n = blockIdx.x; n < N; n += gridDim.x, p ^= 1) {
+        float hn, vn[RF];
+        load(n + gridDim.x, hn, vn);
+        float x[RF];
 #pragma unroll
-                for (int k = 0; k < KM; ++k)
-                    if (k < K) x = __builtin_fmaf(w[r][k], h[k], x);
-                s += dis_term(eps + double(v[f]), double(x));
-            }
+        for (int r = 0; r < RF; ++r) x[r] = epsf;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const float hk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hv), k));
+#pragma unroll
+            for (int r = 0; r < RF; ++r) x[r] = __builtin_fmaf(w[r][k], hk, x[r]);
         }
-        red[t] = s;
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < RF; ++r)
+            if (t + 256 * r < F) s += dis_term(eps + double(vv[r]), double(x[r]));
+        double *rd = red[p];
+        rd[t] = s;
         __syncthreads();
-        for (int m = 128; m > 0; m >>= 1) {
-            if (t < m) red[t] += red[t + m];
-            __syncthreads();
+        if (t < 128) rd[t] += rd[t + 128];
+        __syncthreads();
+        if (t < 64) {
+            double v = rd[t] + rd[t + 64];
+#pragma unroll
+            for (int m = 32; m > 0; m >>= 1) v += __shfl_down(v, m, 64);
+            if (t == 0) frame_buf[n] = v;
         }
-        if (t == 0) frame_buf[n] = red[0];
-        __syncthreads();   // red is written again for the next frame
+        hv = hn;
+#pragma unroll
+        for (int r = 0; r < RF; ++r) vv[r] = vn[r];
     }
 }
 
@@ -98,7 +121,16 @@ __global__ void objective_total(int N, const double *__restrict__ frame_buf,
     const int per = (N + 255) / 256;
     const int lo = threadIdx.x * per;
     const int hi = min(N, lo + per);
-    for (int n = lo; n < hi; ++n) s += frame_buf[n];
+    // the thread's frames in index order; eight loads are issued before
+    // their adds, so the adds do not wait on one load at a time
+    for (int n = lo; n < hi; n += 8) {
+        double b[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b[j] = n + j < hi ? frame_buf[n + j] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (n + j < hi) s += b[j];
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -136,8 +168,8 @@ hipError_t scratch_ptr(double **out) {
 namespace {
 
 // Register-resident form for RF = ceil(F / 256) <= 4 rows per thread and K
-// components rounded up to KM (a multiple of 8) with RF * KM <= 168 floats of
-// W per thread; false where it has no instance.
+// components rounded up to KM (a multiple of 4) with RF * KM <= 160 floats of
+// W per thread (two blocks per CU); false where it has no instance.
 constexpr int OBJ_BLOCKS = 512;   // two 4-wave blocks per CU
 
 template <int RF>
@@ -147,14 +179,16 @@ bool launch_reg(int KM, const float *V, int ldv, const float *W, int ldw, const 
     switch (KM) {
 #define ISNMF_OBJ_KM(M)                                                                          \
     case M:                                                                                      \
-        if constexpr (RF * M <= 168) {                                                           \
+        if constexpr (RF * M <= 160) {                                                           \
             objective_frames_reg<RF, M><<<grid, 256, 0, s>>>(V, ldv, W, ldw, H, ldh, F, K, N, eps, \
                                                              frame_buf);                         \
             return true;                                                                         \
         }                                                                                        \
         return false;
-        ISNMF_OBJ_KM(8) ISNMF_OBJ_KM(16) ISNMF_OBJ_KM(24) ISNMF_OBJ_KM(32)
-        ISNMF_OBJ_KM(40) ISNMF_OBJ_KM(48) ISNMF_OBJ_KM(56) ISNMF_OBJ_KM(64)
+        ISNMF_OBJ_KM(4) ISNMF_OBJ_KM(8) ISNMF_OBJ_KM(12) ISNMF_OBJ_KM(16)
+        ISNMF_OBJ_KM(20) ISNMF_OBJ_KM(24) ISNMF_OBJ_KM(28) ISNMF_OBJ_KM(32)
+        ISNMF_OBJ_KM(36) ISNMF_OBJ_KM(40) ISNMF_OBJ_KM(44) ISNMF_OBJ_KM(48)
+        ISNMF_OBJ_KM(52) ISNMF_OBJ_KM(56) ISNMF_OBJ_KM(60) ISNMF_OBJ_KM(64)
 #undef ISNMF_OBJ_KM
         default: return false;
     }
@@ -166,7 +200,7 @@ hipError_t launch_objective(const float *V, int ldv, const float *W, int ldw, co
                             int ldh, int F, int K, int N, double eps, double *frame_buf,
                             double *d_out, hipStream_t s) {
     if (N > 0) {
-        const int RF = (F + 255) / 256, KM = (K + 7) / 8 * 8;
+        const int RF = (F + 255) / 256, KM = (K + 3) / 4 * 4;
         bool done = false;
         switch (RF) {
             case 1: done = launch_reg<1>(KM, V, ldv, W, ldw, H, ldh, F, K, N, eps, frame_buf, s); break;
