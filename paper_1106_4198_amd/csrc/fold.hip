@@ -30,7 +30,22 @@ __global__ void fold_reduce_kernel(FoldArgs a, int slices) {
     const size_t fk = (size_t)a.F * a.K;
     if (e >= (long)fk) return;
     double sa = 0.0, sb = 0.0;
-    for (int s = 0; s < slices; ++s) {
+    int s = 0;
+    // eight slices' loads issued before their adds, which stay in slice order
+    for (; s + 8 <= slices; s += 8) {
+        float pa[8], pb[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            pa[j] = a.part[(size_t)(s + j) * 2 * fk + e];
+            pb[j] = a.part[(size_t)(s + j) * 2 * fk + fk + e];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            sa += double(pa[j]);
+            sb += double(pb[j]);
+        }
+    }
+    for (; s < slices; ++s) {
         sa += double(a.part[(size_t)s * 2 * fk + e]);
         sb += double(a.part[(size_t)s * 2 * fk + fk + e]);
     }
