@@ -19,8 +19,17 @@
 namespace isnmf {
 namespace {
 
+// Blocks reach the 8 XCDs round-robin by launch index.  Work item g = (tile,
+// slice) in slice-major order is given to blocks so that each XCD takes one
+// contiguous range of items: the tiles of a slice, which read the same H and
+// r1, r2 rows, meet in one L2.  Every item is the same computation whichever
+// block runs it.
 __global__ __launch_bounds__(256) void fold_mfma_kernel(FoldArgs a) {
-    fold_tile16_body(a, blockIdx.x, blockIdx.y, gridDim.y);
+    const unsigned T = gridDim.x * gridDim.y;
+    const unsigned L = blockIdx.y * gridDim.x + blockIdx.x;
+    const unsigned x = L % 8, pos = L / 8;
+    const unsigned g = x * (T / 8) + (x < T % 8 ? x : T % 8) + pos;
+    fold_tile16_body(a, (int)(g % gridDim.x), (int)(g / gridDim.x), gridDim.y);
 }
 
 
