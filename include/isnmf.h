@@ -523,7 +523,9 @@ size_t isnmf_batch_workspace_size(int F, int K, int N, const isnmf_params *p);
  * V: device F x N FP32.  W (F x K, ldw) and H (K x N, ldh): device FP32,
  * in/out (H is the starting point; use ones for a fresh start).
  * d_obj_trace: NULL or device double[cycles], objective of eq. (1) after
- * each cycle.  p->inner_iters, rho, h_init and update_w are ignored.
+ * each cycle.  p->inner_iters, rho, h_init and update_w are ignored.  The
+ * fused fit runs the tuning table's variant for (F, K, precision), as an
+ * online handle does (isnmf_autotune with b = N tunes it for this use).
  */
 int isnmf_batch_mu(const float *V, int ldv, int F, int N, float *W, int ldw,
                    float *H, int ldh, int K, int cycles, const isnmf_params *p,
